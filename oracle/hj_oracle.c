@@ -1,0 +1,420 @@
+/*
+ * hj_oracle.c -- plain, slow, FP64 CPU reference for one explicit time step
+ * of the grid Hamilton-Jacobi reachability PDE (Backward Reachable Tube of a
+ * 4D car), written from the paper "Real-Time Formal Verification of
+ * Autonomous Systems With An FPGA" (arXiv 2012.04011).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker that the HIP library is
+ * compared against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code, header, table or constant
+ * with the HIP library: every quantity below is recomputed here from its
+ * definition.
+ *
+ * What is computed (paper section "Basic Numerical Solution", Algorithm 2,
+ * with the readings listed at each function):
+ *   - nodes of a 4D grid (axes x, y, v, theta; theta periodic);
+ *   - the cone/cylinder target V0 of eq (7), generalised to a union (min);
+ *   - the dissipation coefficients alpha_d(z) and the CFL step
+ *     dt = cfl / sum_d(alpha_d^max / dx_d)  (Algorithm 1, step-bound lines);
+ *   - one-sided derivatives D-, D+ of eq (5) (first order) and the textbook
+ *     second-order ENO variant (Osher & Shu 1991; Osher & Fedkiw 2003, s3.3);
+ *   - the Hamiltonian H = grad(V) . f(z, u*, d*) with the control maximising
+ *     and the disturbance minimising (eq 4), evaluated at the central
+ *     derivative, plus Lax-Friedrichs dissipation with a '+' sign (the paper
+ *     prints '-', which is anti-dissipative for this time direction);
+ *   - forward Euler (Algorithm 2) or the two-stage TVD Runge-Kutta scheme
+ *     (Shu & Osher 1988), followed by the clamp V = min(V0, V) (Algorithm 2,
+ *     last line of the loop body; eq 4);
+ *   - a fixed-horizon schedule: n = ceil(T / dt) steps, the last one shortened
+ *     to T - (n - 1) dt.
+ *
+ * Layout: C order [x][y][v][theta], theta fastest (the paper's 4D array).
+ * All arithmetic is IEEE binary64; build with -ffp-contract=off so that no
+ * multiply-add is fused behind the reader's back.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { HJO_CAR4D = 0, HJO_DRIFT_INPUT = 1 };
+enum { HJO_UPWIND1 = 0, HJO_ENO2 = 1 };
+enum { HJO_EULER = 0, HJO_TVD_RK2 = 1 };
+enum { HJO_BOX = 0, HJO_BALL = 1 };
+enum { HJO_INPUT_MAXIMIZES = 0, HJO_INPUT_MINIMIZES = 1 };
+
+typedef struct {
+  int32_t n[4];        /* nodes per axis: x, y, v, theta */
+  double lo[4], hi[4]; /* axis ranges; for a periodic axis hi - lo is the period */
+  uint32_t periodic_mask;
+} hjo_grid;
+
+/*
+ * Dynamics.
+ *   HJO_CAR4D:  x' = v cos(theta) + d_x, y' = v sin(theta) + d_y,
+ *               v' = a, theta' = w; control (a, w) in a box, maximises;
+ *               disturbance (d_x, d_y) in a box, minimises.
+ *   HJO_DRIFT_INPUT (closed-form test cases):
+ *               z' = drift + u, u nonzero only on the axes in in_axes_mask,
+ *               bounded by in_speed in the box (per-axis) or Euclidean-ball
+ *               norm; the input either maximises or minimises.
+ */
+typedef struct {
+  int32_t kind;
+  double a_max, w_max, d_max[2];
+  double drift[4], in_speed;
+  uint32_t in_axes_mask;
+  int32_t in_norm, in_role;
+} hjo_dyn;
+
+typedef struct {
+  int32_t deriv, integrator, clamp;
+  double cfl;
+} hjo_scheme;
+
+/* ---------------------------------------------------------------- grid --- */
+
+static int is_periodic(const hjo_grid *g, int d) { return (int)((g->periodic_mask >> d) & 1u); }
+
+/* Node spacing: N nodes including both ends on an ordinary axis; N nodes over
+ * one period on a periodic axis (theta_l = -pi + l * 2 pi / N). */
+double hjo_spacing(const hjo_grid *g, int d) {
+  if (is_periodic(g, d)) return (g->hi[d] - g->lo[d]) / g->n[d];
+  return (g->hi[d] - g->lo[d]) / (g->n[d] - 1);
+}
+
+double hjo_node(const hjo_grid *g, int d, int i) { return g->lo[d] + i * hjo_spacing(g, d); }
+
+int64_t hjo_num_points(const hjo_grid *g) {
+  return (int64_t)g->n[0] * g->n[1] * g->n[2] * g->n[3];
+}
+
+static void strides_of(const hjo_grid *g, int64_t st[4]) {
+  st[3] = 1;
+  st[2] = g->n[3];
+  st[1] = (int64_t)g->n[2] * g->n[3];
+  st[0] = (int64_t)g->n[1] * g->n[2] * g->n[3];
+}
+
+static void unravel(const hjo_grid *g, int64_t p, int idx[4]) {
+  for (int d = 3; d >= 0; --d) {
+    idx[d] = (int)(p % g->n[d]);
+    p /= g->n[d];
+  }
+}
+
+/* ------------------------------------------------------------- target --- */
+
+/* Eq (7) for a union of cylinders: distance in the (x, y) plane to each
+ * obstacle centre minus its radius, minimum over obstacles; the same value
+ * for every (v, theta). */
+void hjo_target_cylinders(const hjo_grid *g, const double *cx, const double *cy, const double *r,
+                          int32_t m, double *V0) {
+  int64_t np = hjo_num_points(g);
+  for (int64_t p = 0; p < np; ++p) {
+    int idx[4];
+    unravel(g, p, idx);
+    double x = hjo_node(g, 0, idx[0]);
+    double y = hjo_node(g, 1, idx[1]);
+    double best = INFINITY;
+    for (int o = 0; o < m; ++o) {
+      double dist = sqrt((x - cx[o]) * (x - cx[o]) + (y - cy[o]) * (y - cy[o])) - r[o];
+      if (dist < best) best = dist;
+    }
+    V0[p] = best;
+  }
+}
+
+/* ------------------------------------------------------------ dynamics --- */
+
+/* f(z, u, d) for the car; u = (a, w), dist = (d_x, d_y). */
+static void car_f(double v, double theta, const double u[2], const double dist[2], double f[4]) {
+  f[0] = v * cos(theta) + dist[0];
+  f[1] = v * sin(theta) + dist[1];
+  f[2] = u[0];
+  f[3] = u[1];
+}
+
+/*
+ * alpha_d(z) = max over all admissible controls and disturbances of
+ * |f_d(z, u, d)| (state-local, independent of p).  The paper's Algorithm 2
+ * uses |x'_d| at the optimal control; with a disturbance present that can be
+ * smaller than the true bound and lose monotonicity, so the bound over the
+ * whole input set is used.  For box sets the maximum of |affine| sits at a
+ * vertex: |v cos(theta)| + d_x^max, |v sin(theta)| + d_y^max, a_max, w_max.
+ * For the drift+input test dynamics: |drift_d| + speed on input axes (true
+ * for both the box and the ball).
+ */
+static void alpha_at(const hjo_dyn *dy, const double z[4], double alpha[4]) {
+  if (dy->kind == HJO_CAR4D) {
+    alpha[0] = fabs(z[2] * cos(z[3])) + dy->d_max[0];
+    alpha[1] = fabs(z[2] * sin(z[3])) + dy->d_max[1];
+    alpha[2] = dy->a_max;
+    alpha[3] = dy->w_max;
+  } else {
+    for (int d = 0; d < 4; ++d) {
+      alpha[d] = fabs(dy->drift[d]);
+      if ((dy->in_axes_mask >> d) & 1u) alpha[d] += dy->in_speed;
+    }
+  }
+}
+
+/*
+ * H(z, p) = p . f(z, u*, d*) with u* = argmax_u p.f (control) and
+ * d* = argmin_d p.f (disturbance), eq (4) and eq (9).  Bang-bang on boxes;
+ * ties (p_d = 0) take the '+' vertex for the control and the '-' vertex for
+ * the disturbance -- the term they multiply is zero, so H does not depend on
+ * the choice.
+ */
+static double hamiltonian(const hjo_dyn *dy, const double z[4], const double p[4]) {
+  double f[4];
+  if (dy->kind == HJO_CAR4D) {
+    double u[2], dist[2];
+    u[0] = p[2] >= 0.0 ? dy->a_max : -dy->a_max;
+    u[1] = p[3] >= 0.0 ? dy->w_max : -dy->w_max;
+    dist[0] = p[0] >= 0.0 ? -dy->d_max[0] : dy->d_max[0];
+    dist[1] = p[1] >= 0.0 ? -dy->d_max[1] : dy->d_max[1];
+    car_f(z[2], z[3], u, dist, f);
+  } else {
+    double sgn = dy->in_role == HJO_INPUT_MAXIMIZES ? 1.0 : -1.0;
+    double u[4] = {0.0, 0.0, 0.0, 0.0};
+    if (dy->in_norm == HJO_BOX) {
+      for (int d = 0; d < 4; ++d)
+        if ((dy->in_axes_mask >> d) & 1u) u[d] = sgn * (p[d] >= 0.0 ? dy->in_speed : -dy->in_speed);
+    } else {
+      double norm2 = 0.0;
+      for (int d = 0; d < 4; ++d)
+        if ((dy->in_axes_mask >> d) & 1u) norm2 += p[d] * p[d];
+      double norm = sqrt(norm2);
+      if (norm > 0.0)
+        for (int d = 0; d < 4; ++d)
+          if ((dy->in_axes_mask >> d) & 1u) u[d] = sgn * dy->in_speed * p[d] / norm;
+    }
+    for (int d = 0; d < 4; ++d) f[d] = dy->drift[d] + u[d];
+  }
+  return p[0] * f[0] + p[1] * f[1] + p[2] * f[2] + p[3] * f[3];
+}
+
+/* Exported for tests: H and alpha at an arbitrary state and gradient. */
+double hjo_hamiltonian(const hjo_dyn *dy, const double z[4], const double p[4]) {
+  return hamiltonian(dy, z, p);
+}
+void hjo_alpha(const hjo_dyn *dy, const double z[4], double alpha[4]) { alpha_at(dy, z, alpha); }
+
+/* ------------------------------------------------------------ CFL step --- */
+
+/* alpha_d^max = max over every grid node of alpha_d(z) (Algorithm 1). */
+void hjo_alpha_max(const hjo_grid *g, const hjo_dyn *dy, double amax[4]) {
+  for (int d = 0; d < 4; ++d) amax[d] = 0.0;
+  int64_t np = hjo_num_points(g);
+  for (int64_t p = 0; p < np; ++p) {
+    int idx[4];
+    double z[4], a[4];
+    unravel(g, p, idx);
+    for (int d = 0; d < 4; ++d) z[d] = hjo_node(g, d, idx[d]);
+    alpha_at(dy, z, a);
+    for (int d = 0; d < 4; ++d)
+      if (a[d] > amax[d]) amax[d] = a[d];
+  }
+}
+
+/* dt = cfl / sum_d(alpha_d^max / dx_d); a zero sum (no motion at all) makes
+ * one step of the whole horizon. */
+double hjo_cfl_dt(const hjo_grid *g, const hjo_dyn *dy, double cfl, double horizon) {
+  double amax[4];
+  hjo_alpha_max(g, dy, amax);
+  double s = 0.0;
+  for (int d = 0; d < 4; ++d) s += amax[d] / hjo_spacing(g, d);
+  if (s == 0.0) return horizon;
+  return cfl / s;
+}
+
+/* Fixed horizon: n = ceil(T / dt); steps 1..n-1 take dt, the last takes
+ * T - (n - 1) dt.  T = 0 means no step. */
+void hjo_schedule(double dt, double horizon, int64_t *n_steps, double *dt_last) {
+  if (horizon <= 0.0) {
+    *n_steps = 0;
+    *dt_last = 0.0;
+    return;
+  }
+  int64_t n = (int64_t)ceil(horizon / dt);
+  if (n < 1) n = 1;
+  *n_steps = n;
+  *dt_last = horizon - (double)(n - 1) * dt;
+}
+
+/* ------------------------------------------------------- derivatives --- */
+
+/* Value at node idx shifted by `off` nodes along axis d.  Off the grid, a
+ * periodic axis wraps; any other axis uses linear extrapolation from its two
+ * end nodes ("extrapolated points" of eq (5)): the ghost k layers beyond an
+ * end equals V_end + k (V_end - V_next). */
+static double value_at(const hjo_grid *g, const double *V, const int64_t st[4], int64_t p,
+                       const int idx[4], int d, int off) {
+  int n = g->n[d];
+  int i = idx[d] + off;
+  int64_t base = p - (int64_t)idx[d] * st[d];
+  if (i >= 0 && i < n) return V[base + (int64_t)i * st[d]];
+  if (is_periodic(g, d)) {
+    i = ((i % n) + n) % n;
+    return V[base + (int64_t)i * st[d]];
+  }
+  if (i < 0) {
+    double e = V[base], nx = V[base + st[d]];
+    return e + (double)(-i) * (e - nx);
+  }
+  double e = V[base + (int64_t)(n - 1) * st[d]], nx = V[base + (int64_t)(n - 2) * st[d]];
+  return e + (double)(i - (n - 1)) * (e - nx);
+}
+
+/*
+ * One-sided derivatives along axis d at one node.
+ *   UPWIND1 (eq 5):  p- = (V_i - V_{i-1}) / h,  p+ = (V_{i+1} - V_i) / h.
+ *   ENO2 (textbook): with Q_j = V_{j+1} - 2 V_j + V_{j-1},
+ *     p- = (V_i - V_{i-1}) / h + c- / (2h),  c- = the smaller-magnitude of
+ *          Q_{i-1}, Q_i (ties pick Q_{i-1});
+ *     p+ = (V_{i+1} - V_i) / h - c+ / (2h),  c+ = the smaller-magnitude of
+ *          Q_i, Q_{i+1} (ties pick Q_i).
+ */
+static void one_sided(const hjo_grid *g, int deriv, const double *V, const int64_t st[4], int64_t p,
+                      const int idx[4], int d, double *pm, double *pp) {
+  double h = hjo_spacing(g, d);
+  if (deriv == HJO_UPWIND1) {
+    double vm = value_at(g, V, st, p, idx, d, -1);
+    double v0 = V[p];
+    double vp = value_at(g, V, st, p, idx, d, +1);
+    *pm = (v0 - vm) / h;
+    *pp = (vp - v0) / h;
+    return;
+  }
+  double w[5];
+  for (int k = -2; k <= 2; ++k) w[k + 2] = value_at(g, V, st, p, idx, d, k);
+  double q_left = w[2] - 2.0 * w[1] + w[0];  /* Q_{i-1} */
+  double q_mid = w[3] - 2.0 * w[2] + w[1];   /* Q_i     */
+  double q_right = w[4] - 2.0 * w[3] + w[2]; /* Q_{i+1} */
+  double c_minus = fabs(q_left) <= fabs(q_mid) ? q_left : q_mid;
+  double c_plus = fabs(q_mid) <= fabs(q_right) ? q_mid : q_right;
+  *pm = (w[2] - w[1]) / h + c_minus / (2.0 * h);
+  *pp = (w[3] - w[2]) / h - c_plus / (2.0 * h);
+}
+
+/* Exported for tests: p- and p+ along axis d at every node. */
+void hjo_derivs(const hjo_grid *g, const hjo_scheme *sc, const double *V, int32_t d, double *pm,
+                double *pp) {
+  int64_t st[4];
+  strides_of(g, st);
+  int64_t np = hjo_num_points(g);
+  for (int64_t p = 0; p < np; ++p) {
+    int idx[4];
+    unravel(g, p, idx);
+    one_sided(g, sc->deriv, V, st, p, idx, d, &pm[p], &pp[p]);
+  }
+}
+
+/* ------------------------------------------------------------ L(V) --- */
+
+/* L(V)(z) = H(z, (p+ + p-)/2) + sum_d alpha_d(z) (p+_d - p-_d) / 2. */
+static double rhs_at(const hjo_grid *g, const hjo_dyn *dy, int deriv, const double *V,
+                     const int64_t st[4], int64_t p) {
+  int idx[4];
+  double z[4], pm[4], pp[4], pbar[4], alpha[4];
+  unravel(g, p, idx);
+  for (int d = 0; d < 4; ++d) {
+    z[d] = hjo_node(g, d, idx[d]);
+    one_sided(g, deriv, V, st, p, idx, d, &pm[d], &pp[d]);
+    pbar[d] = (pp[d] + pm[d]) / 2.0;
+  }
+  alpha_at(dy, z, alpha);
+  double diss = 0.0;
+  for (int d = 0; d < 4; ++d) diss += alpha[d] * (pp[d] - pm[d]) / 2.0;
+  return hamiltonian(dy, z, pbar) + diss;
+}
+
+/* L(V) at every node (outermost axis split across OpenMP threads; every
+ * node is independent, so the result does not depend on the thread count). */
+void hjo_rhs(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V,
+             double *L) {
+  int64_t st[4];
+  strides_of(g, st);
+  int n0 = g->n[0];
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n0; ++i)
+    for (int64_t q = 0; q < st[0]; ++q) {
+      int64_t p = (int64_t)i * st[0] + q;
+      L[p] = rhs_at(g, dy, sc->deriv, V, st, p);
+    }
+}
+
+/* ------------------------------------------------------------- steps --- */
+
+/*
+ * One full time step of length dt, in place on V.  work must hold 2 N
+ * doubles.
+ *   Euler (Algorithm 2):  V <- V + dt L(V).
+ *   TVD-RK2 (textbook):    V1 = V + dt L(V);  V2 = V1 + dt L(V1);
+ *                          V <- (V + V2) / 2.
+ * Then, if the clamp is on, V <- min(V0, V) (once per full step).
+ */
+void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0, double *V,
+              double dt, double *work) {
+  int64_t np = hjo_num_points(g);
+  double *L = work, *V1 = work + np;
+  hjo_rhs(g, dy, sc, V, L);
+  if (sc->integrator == HJO_EULER) {
+    for (int64_t p = 0; p < np; ++p) V[p] = V[p] + dt * L[p];
+  } else {
+    for (int64_t p = 0; p < np; ++p) V1[p] = V[p] + dt * L[p];
+    hjo_rhs(g, dy, sc, V1, L);
+    for (int64_t p = 0; p < np; ++p) {
+      double v2 = V1[p] + dt * L[p];
+      V[p] = (V[p] + v2) / 2.0;
+    }
+  }
+  if (sc->clamp)
+    for (int64_t p = 0; p < np; ++p)
+      if (V0[p] < V[p]) V[p] = V0[p];
+}
+
+/*
+ * Whole fixed-horizon solve: V := V0, then n = ceil(T / dt) steps with the
+ * CFL step dt and a shortened last step.  Returns 0 on success, -1 if memory
+ * runs out.
+ */
+int hjo_solve(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0,
+              double horizon, double *V, int64_t *n_steps, double *dt_out, double *dt_last_out) {
+  int64_t np = hjo_num_points(g);
+  double dt = hjo_cfl_dt(g, dy, sc->cfl, horizon);
+  int64_t n;
+  double dt_last;
+  hjo_schedule(dt, horizon, &n, &dt_last);
+  double *work = (double *)malloc((size_t)np * 2 * sizeof(double));
+  if (!work) return -1;
+  memcpy(V, V0, (size_t)np * sizeof(double));
+  for (int64_t k = 0; k < n; ++k) hjo_step(g, dy, sc, V0, V, k + 1 < n ? dt : dt_last, work);
+  free(work);
+  if (n_steps) *n_steps = n;
+  if (dt_out) *dt_out = dt;
+  if (dt_last_out) *dt_last_out = dt_last;
+  return 0;
+}
+
+/* Thread count the OpenMP loops use (1 without OpenMP). */
+int32_t hjo_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void hjo_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -1,0 +1,122 @@
+"""Seeded synthetic workloads for the BRT solver.
+
+This module holds problem descriptions (grids, dynamics, schemes) and the
+seeded obstacle draws.  It contains none of the method's arithmetic, so both
+the HIP library's callers and the FP64 oracle can take their inputs from it.
+
+Obstacles are cylinders in (x, y) extruded over (v, theta), standing in for
+the paper's motion-captured cone layouts (section "Experiment setup", eq (7):
+cone radius 0.08 m inflated to 0.75 m), which were never published.  Centres
+are uniform in [-3, 3]^2 and radii uniform in [0.4, 1.0]; the draw order is
+cx[0..m), cy[0..m), r[0..m) from ``numpy.random.default_rng(seed)``.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+THETA_PERIODIC = 1 << 3  # bit d set = axis d periodic; theta is axis 3
+
+
+def car_grid(nx: int, ny: int, nv: int, nth: int, xy=(-5.0, 5.0), v=(0.0, 2.0)) -> dict:
+    """4D car grid: x, y in [-5, 5], v in [0, 2] (ends included), theta in
+    [-pi, pi) periodic."""
+    return {
+        "n": (int(nx), int(ny), int(nv), int(nth)),
+        "lo": (xy[0], xy[0], v[0], -math.pi),
+        "hi": (xy[1], xy[1], v[1], math.pi),
+        "periodic_mask": THETA_PERIODIC,
+    }
+
+
+def car_dynamics(a_max: float = 1.5, w_max: float = 1.0, d_max: float = 0.0) -> dict:
+    """x' = v cos(theta) + d_x, y' = v sin(theta) + d_y, v' = a, theta' = w;
+    |a| <= a_max, |w| <= w_max (control, maximises); |d_x|, |d_y| <= d_max
+    (disturbance, minimises)."""
+    return {"kind": "car4d", "a_max": a_max, "w_max": w_max, "d_max": (d_max, d_max)}
+
+
+def scheme(deriv: str, integrator: str, cfl: float = 0.8, clamp: bool = True) -> dict:
+    return {"deriv": deriv, "integrator": integrator, "clamp": clamp, "cfl": cfl}
+
+
+def cylinders(seed: int, m: int):
+    """Seeded obstacle set: (cx, cy, r) float64 arrays of length m."""
+    rng = np.random.default_rng(seed)
+    cx = rng.uniform(-3.0, 3.0, size=m)
+    cy = rng.uniform(-3.0, 3.0, size=m)
+    r = rng.uniform(0.4, 1.0, size=m)
+    return cx, cy, r
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: dict
+    dyn: dict
+    scheme: dict
+    horizon: float
+    obstacles: int
+    seeds: tuple
+    precision: str = "f32"
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def points(self) -> int:
+        n = self.grid["n"]
+        return int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+
+
+# Plain method, FP64, first order upwind + Euler, 3 cylinders, T = 1 s.
+PLAIN_40 = Workload(
+    name="car4d 40x40x20x24 upwind1+euler f64 T=1",
+    grid=car_grid(40, 40, 20, 24),
+    dyn=car_dynamics(),
+    scheme=scheme("upwind1", "euler"),
+    horizon=1.0,
+    obstacles=3,
+    seeds=(0, 1, 2),
+    precision="f64",
+)
+
+# The paper's grid size, ENO2 + TVD-RK2, disturbance |d| <= 0.1, 5 cylinders, T = 2 s.
+ENO_60_DIST = Workload(
+    name="car4d 60x60x20x36 eno2+rk2 d=0.1 f32 T=2",
+    grid=car_grid(60, 60, 20, 36),
+    dyn=car_dynamics(d_max=0.1),
+    scheme=scheme("eno2", "rk2"),
+    horizon=2.0,
+    obstacles=5,
+    seeds=(0, 1, 2),
+    precision="f32",
+)
+
+# Large single grid, 41.5M points, ENO2 + TVD-RK2, 8 cylinders, T = 2 s.
+LARGE_120 = Workload(
+    name="car4d 120x120x40x72 eno2+rk2 f32 T=2",
+    grid=car_grid(120, 120, 40, 72),
+    dyn=car_dynamics(),
+    scheme=scheme("eno2", "rk2"),
+    horizon=2.0,
+    obstacles=8,
+    seeds=(0,),
+    precision="f32",
+)
+
+# The large grid coarsened 2x (the oracle's companion of LARGE_120).
+LARGE_120_COARSE = Workload(
+    name="car4d 60x60x20x36 eno2+rk2 f64 T=2 (2x-coarsened large grid)",
+    grid=car_grid(60, 60, 20, 36),
+    dyn=car_dynamics(),
+    scheme=scheme("eno2", "rk2"),
+    horizon=2.0,
+    obstacles=8,
+    seeds=(0,),
+    precision="f64",
+)
+
+WORKLOADS = {w.name: w for w in (PLAIN_40, ENO_60_DIST, LARGE_120, LARGE_120_COARSE)}

@@ -1,0 +1,462 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names what fixes the expected value: a number the paper prints, a
+closed-form solution of the PDE, a polynomial-exactness property of the
+difference formulas, a brute-force max/min over the input sets, or a symmetry
+of the car dynamics.  All run on the CPU.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2012_04011_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+UP_EU = W.scheme("upwind1", "euler")
+ENO_RK = W.scheme("eno2", "rk2")
+ALL_SCHEMES = [W.scheme(d, i) for d in ("upwind1", "eno2") for i in ("euler", "rk2")]
+
+
+def small_grid(nx=12, ny=11, nv=6, nth=8, periodic_mask=W.THETA_PERIODIC):
+    g = W.car_grid(nx, ny, nv, nth)
+    g["periodic_mask"] = periodic_mask
+    return g
+
+
+def drift_dyn(drift=(0, 0, 0, 0), axes=(), speed=0.0, norm="box", role="max"):
+    return {"kind": "drift_input", "drift": tuple(float(x) for x in drift), "in_axes": tuple(axes),
+            "in_speed": float(speed), "in_norm": norm, "in_role": role}
+
+
+# --------------------------------------------------------------- schedule ---
+
+
+def test_schedule_matches_paper_table2(oracle_lib):
+    """Table II: horizon 0.5 s at dt = 0.007497 s takes 67 iterations."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_schedule.txt")) if l.strip() and l[0] != "#"]
+    for dt, T, iters in rows:
+        n, last = oracle_lib.schedule(float(dt), float(T))
+        assert n == int(iters)
+        assert 0.0 < last <= float(dt)
+        # n - 1 full steps fall short of the horizon, n full steps do not
+        assert (n - 1) * float(dt) < float(T) <= n * float(dt)
+
+
+def test_schedule_edge_cases(oracle_lib):
+    assert oracle_lib.schedule(0.1, 0.0) == (0, 0.0)
+    n, last = oracle_lib.schedule(0.25, 1.0)  # exact multiple: 4 full steps
+    assert n == 4 and last == 0.25
+    n, last = oracle_lib.schedule(2.0, 1.0)  # horizon shorter than one step
+    assert n == 1 and last == 1.0
+
+
+@pytest.mark.parametrize("wl", [W.PLAIN_40, W.ENO_60_DIST, W.LARGE_120])
+def test_cfl_step_closed_form(oracle_lib, wl):
+    """alpha^max over the nodes of the car grids in closed form: theta = -pi
+    and theta = -pi/2 are nodes (N_theta divisible by 4), and the top speed
+    node is v = 2, so alpha_x^max = alpha_y^max = 2 + d_max, alpha_v = 1.5,
+    alpha_theta = 1; spacings are 10/(N-1), 2/(N-1), 2 pi / N."""
+    n = wl.grid["n"]
+    d = wl.dyn["d_max"][0]
+    s = (2 + d) / (10 / (n[0] - 1)) + (2 + d) / (10 / (n[1] - 1)) + 1.5 / (2 / (n[2] - 1)) + 1.0 / (2 * math.pi / n[3])
+    dt = oracle_lib.cfl_dt(wl.grid, wl.dyn, 0.8, wl.horizon)
+    assert dt == pytest.approx(0.8 / s, rel=1e-14)
+    steps, _ = oracle_lib.schedule(dt, wl.horizon)
+    assert steps == math.ceil(wl.horizon * s / 0.8)
+
+
+def test_cfl_uses_nodes_not_supremum(oracle_lib):
+    """With 18 theta nodes (20 degree spacing) no node sits at +-90 degrees:
+    alpha_y^max = 2 sin(80 deg), not 2."""
+    g = W.car_grid(30, 30, 12, 18)
+    amax = oracle_lib.alpha_max(g, W.car_dynamics())
+    assert amax[1] == pytest.approx(2 * math.sin(math.radians(80)), rel=1e-14)
+    assert amax[0] == pytest.approx(2.0, rel=1e-15)
+
+
+def test_zero_motion_takes_one_step(oracle_lib):
+    g = small_grid()
+    assert oracle_lib.cfl_dt(g, drift_dyn(), 0.8, 1.7) == 1.7
+
+
+# ------------------------------------------------------------ derivatives ---
+
+
+def _line(grid, axis):
+    """Node coordinates broadcast along `axis` (independent of the oracle's
+    own node helper: lo + i * spacing from the grid description)."""
+    n, lo, hi = grid["n"][axis], grid["lo"][axis], grid["hi"][axis]
+    per = (grid["periodic_mask"] >> axis) & 1
+    h = (hi - lo) / (n if per else n - 1)
+    x = lo + np.arange(n) * h
+    shape = [1, 1, 1, 1]
+    shape[axis] = n
+    return x.reshape(shape), h
+
+
+@pytest.mark.parametrize("deriv", ["upwind1", "eno2"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_derivative_exact_on_linear(oracle_lib, deriv, axis):
+    """A linear function has exact one-sided differences, and linear
+    extrapolation reproduces it beyond the ends: p- = p+ = slope everywhere."""
+    g = small_grid()
+    x, _ = _line(g, axis)
+    V = np.broadcast_to(0.7 - 1.3 * x, g["n"]).copy()
+    pm, pp = oracle_lib.derivs(g, W.scheme(deriv, "euler"), V, axis)
+    np.testing.assert_allclose(pm, -1.3, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(pp, -1.3, rtol=0, atol=1e-12)
+
+
+def test_eno2_exact_on_quadratic_interior(oracle_lib):
+    """Second-order one-sided differences are exact for quadratics; first
+    order ones are off by exactly -h and +h."""
+    g = small_grid(nx=14)
+    x, h = _line(g, 0)
+    V = np.broadcast_to((x - 0.3) ** 2, g["n"]).copy()
+    exact = np.broadcast_to(2 * (x - 0.3), g["n"])
+    pm, pp = oracle_lib.derivs(g, W.scheme("eno2", "euler"), V, 0)
+    inner = slice(2, -2)
+    np.testing.assert_allclose(pm[inner], exact[inner], atol=1e-12)
+    np.testing.assert_allclose(pp[inner], exact[inner], atol=1e-12)
+    pm1, pp1 = oracle_lib.derivs(g, W.scheme("upwind1", "euler"), V, 0)
+    np.testing.assert_allclose(pm1[inner], exact[inner] - h, atol=1e-12)
+    np.testing.assert_allclose(pp1[inner], exact[inner] + h, atol=1e-12)
+
+
+def test_eno2_avoids_kink(oracle_lib):
+    """V = |x - k| with the kink between two nodes: every one-sided
+    derivative whose own two-point difference stays on one side of the kink
+    is the exact slope (+-1): the ENO choice takes the second difference that
+    does not straddle the kink."""
+    g = small_grid(nx=20)
+    x, h = _line(g, 0)
+    k = x.ravel()[9] + 0.37 * h
+    V = np.broadcast_to(np.abs(x - k), g["n"]).copy()
+    pm, pp = oracle_lib.derivs(g, W.scheme("eno2", "euler"), V, 0)
+    xs = x.ravel()
+    for i in range(2, 18):
+        if xs[i - 1] > k or xs[i] < k:  # left difference does not straddle
+            assert pm[i, 0, 0, 0] == pytest.approx(np.sign(xs[i] - k), abs=1e-12)
+        if xs[i] > k or xs[i + 1] < k:
+            assert pp[i, 0, 0, 0] == pytest.approx(np.sign(xs[i] - k), abs=1e-12)
+
+
+@pytest.mark.parametrize("deriv,order", [("upwind1", 1), ("eno2", 2)])
+def test_periodic_axis_convergence(oracle_lib, deriv, order):
+    """On the periodic theta axis, d/dtheta sin(theta) = cos(theta): the
+    error over all nodes (including the wrapped ends) falls as h^order."""
+    errs = []
+    for nth in (32, 64):
+        g = small_grid(nx=4, ny=4, nv=4, nth=nth)
+        th, _ = _line(g, 3)
+        V = np.broadcast_to(np.sin(th), g["n"]).copy()
+        pm, pp = oracle_lib.derivs(g, W.scheme(deriv, "euler"), V, 3)
+        ex = np.broadcast_to(np.cos(th), g["n"])
+        errs.append(max(np.abs(pm - ex).max(), np.abs(pp - ex).max()))
+    ratio = errs[0] / errs[1]
+    assert ratio > 2 ** order * 0.8, (errs, ratio)
+
+
+# ----------------------------------------------------- Hamiltonian / alpha ---
+
+
+def _car_f(z, a, w, dx, dy):
+    return np.stack(np.broadcast_arrays(z[2] * np.cos(z[3]) + dx, z[2] * np.sin(z[3]) + dy, a, w), axis=-1)
+
+
+def test_car_hamiltonian_brute_force(oracle_lib):
+    """H = max over controls of min over disturbances of p.f, by exhaustive
+    search over a grid of each input box (box vertices included, so the
+    search is exact for this input-affine f)."""
+    rng = np.random.default_rng(11)
+    dyn = W.car_dynamics(a_max=1.5, w_max=1.0, d_max=0.1)
+    s = np.linspace(-1, 1, 9)
+    A, Wc, DX, DY = np.meshgrid(1.5 * s, 1.0 * s, 0.1 * s, 0.1 * s, indexing="ij")
+    for _ in range(40):
+        z = np.array([rng.uniform(-5, 5), rng.uniform(-5, 5), rng.uniform(0, 2), rng.uniform(-math.pi, math.pi)])
+        p = rng.normal(size=4)
+        if rng.random() < 0.2:
+            p[rng.integers(4)] = 0.0
+        val = (_car_f(z, A, Wc, DX, DY) @ p)  # shape (a, w, dx, dy)
+        bf = val.min(axis=(2, 3)).max()
+        assert oracle_lib.hamiltonian(dyn, z, p) == pytest.approx(bf, abs=1e-12)
+
+
+def test_car_alpha_brute_force(oracle_lib):
+    """alpha_d(z) = max over all inputs of |f_d(z, u, d)|."""
+    rng = np.random.default_rng(12)
+    dyn = W.car_dynamics(a_max=1.5, w_max=1.0, d_max=0.1)
+    s = np.linspace(-1, 1, 9)
+    A, Wc, DX, DY = np.meshgrid(1.5 * s, 1.0 * s, 0.1 * s, 0.1 * s, indexing="ij")
+    for _ in range(20):
+        z = np.array([0.0, 0.0, rng.uniform(0, 2), rng.uniform(-math.pi, math.pi)])
+        f = _car_f(z, A, Wc, DX, DY)
+        bf = np.abs(f).reshape(-1, 4).max(axis=0)
+        np.testing.assert_allclose(oracle_lib.alpha(dyn, z), bf, atol=1e-13)
+
+
+@pytest.mark.parametrize("role", ["max", "min"])
+@pytest.mark.parametrize("norm", ["box", "ball"])
+def test_drift_input_hamiltonian_brute_force(oracle_lib, role, norm):
+    """z' = drift + u on axes (0, 2), |u| <= 0.7 in the box or ball norm; the
+    input maximises (role max) or minimises (role min) p.f."""
+    rng = np.random.default_rng(13)
+    dyn = drift_dyn(drift=(0.3, -0.2, 0.1, 0.5), axes=(0, 2), speed=0.7, norm=norm, role=role)
+    if norm == "box":
+        s = np.linspace(-0.7, 0.7, 15)
+        U0, U2 = np.meshgrid(s, s, indexing="ij")
+    else:
+        ang = np.linspace(0, 2 * math.pi, 20001)
+        U0, U2 = 0.7 * np.cos(ang), 0.7 * np.sin(ang)
+    for _ in range(30):
+        p = rng.normal(size=4)
+        vals = p[0] * (0.3 + U0) + p[1] * -0.2 + p[2] * (0.1 + U2) + p[3] * 0.5
+        bf = vals.max() if role == "max" else vals.min()
+        got = oracle_lib.hamiltonian(dyn, np.zeros(4), p)
+        assert got == pytest.approx(bf, abs=1e-7 if norm == "ball" else 1e-12)
+    a = oracle_lib.alpha(dyn, np.zeros(4))
+    np.testing.assert_allclose(a, [1.0, 0.2, 0.8, 0.5], atol=1e-15)
+
+
+def test_rhs_on_linear_is_hamiltonian(oracle_lib):
+    """For linear V, p+ = p- = grad V at every node, the dissipation vanishes
+    and L(V) = H(z, grad V): the car's H written out at the theta nodes with
+    exactly known cos/sin (theta = -pi, -pi/2, 0, pi/2)."""
+    g = small_grid(nx=7, ny=7, nv=5, nth=4)
+    dyn = W.car_dynamics(a_max=1.5, w_max=1.0, d_max=0.1)
+    x, _ = _line(g, 0)
+    y, _ = _line(g, 1)
+    v, _ = _line(g, 2)
+    px, py, pv = 0.4, -0.9, 0.25
+    V = np.broadcast_to(px * x + py * y + pv * v, g["n"]).copy()
+    for deriv in ("upwind1", "eno2"):
+        L = oracle_lib.rhs(g, dyn, W.scheme(deriv, "euler"), V)
+        vs = v.ravel()
+        cos_t = np.array([-1.0, 0.0, 1.0, 0.0])
+        sin_t = np.array([0.0, -1.0, 0.0, 1.0])
+        # control maximises: a = +1.5 since pv > 0, w term zero (p_theta = 0);
+        # disturbance minimises: d_x = -0.1 (px > 0), d_y = +0.1 (py < 0)
+        exp = (px * (vs[:, None] * cos_t[None, :] - 0.1) + py * (vs[:, None] * sin_t[None, :] + 0.1) + pv * 1.5)
+        np.testing.assert_allclose(L, np.broadcast_to(exp, g["n"]), atol=1e-12)
+
+
+# ------------------------------------------------------------ closed forms ---
+
+
+@pytest.mark.parametrize("sch", ALL_SCHEMES)
+@pytest.mark.parametrize("clamp", [True, False])
+def test_p1_zero_dynamics_is_identity(oracle_lib, sch, clamp):
+    """No motion: one step of the whole horizon with H = 0 and zero
+    dissipation leaves V0 unchanged bit for bit."""
+    g = small_grid()
+    rng = np.random.default_rng(1)
+    V0 = rng.normal(size=g["n"])
+    sch = dict(sch, clamp=clamp)
+    V, info = oracle_lib.solve(g, drift_dyn(), sch, V0, 0.9)
+    assert info["steps"] == 1 and info["dt"] == 0.9
+    assert np.array_equal(V, V0)
+
+
+@pytest.mark.parametrize("sch", ALL_SCHEMES)
+def test_p2_affine_translation(oracle_lib, sch):
+    """Car with a = w = d = 0 and V0 = ax + by + c (clamp off): the level sets
+    translate rigidly, V_T = V0 + T v (a cos(theta) + b sin(theta)) at every
+    node including the ends (linear ghosts are exact, RK2 is exact because
+    L(V) stays constant in time)."""
+    g = small_grid(nx=10, ny=9, nv=5, nth=12)
+    dyn = W.car_dynamics(a_max=0.0, w_max=0.0, d_max=0.0)
+    x, _ = _line(g, 0)
+    y, _ = _line(g, 1)
+    v, _ = _line(g, 2)
+    th, _ = _line(g, 3)
+    a, b, c = 0.35, -0.6, 1.2
+    V0 = np.broadcast_to(a * x + b * y + c, g["n"]).copy()
+    T = 0.77
+    V, info = oracle_lib.solve(g, dyn, dict(sch, clamp=False), V0, T)
+    exact = V0 + T * v * (a * np.cos(th) + b * np.sin(th))
+    assert info["steps"] > 3
+    ulp = np.spacing(np.abs(exact).max())
+    assert np.abs(V - exact).max() <= 8 * info["steps"] * ulp
+
+
+@pytest.mark.parametrize("c", [0.8, -1.3])
+def test_p3_courant_one_shift_periodic(oracle_lib, c):
+    """Pure drift c along periodic theta, first order upwind, Euler, CFL 1:
+    each step copies the upwind neighbour, V^n = roll(V0, -n sign(c)).  The
+    paper's printed dissipation sign would instead give 2 V_i - V_(i-1) and
+    blow up."""
+    g = small_grid(nx=3, ny=3, nv=3, nth=16)
+    dyn = drift_dyn(drift=(0, 0, 0, c))
+    sch = W.scheme("upwind1", "euler", cfl=1.0, clamp=False)
+    rng = np.random.default_rng(2)
+    V0 = rng.uniform(-1, 1, size=g["n"])
+    dt = oracle_lib.cfl_dt(g, dyn, 1.0, 10.0)
+    assert dt == pytest.approx(abs((2 * math.pi / 16) / c), rel=1e-15)
+    V = V0.copy()
+    n = 21
+    for _ in range(n):
+        V = oracle_lib.step(g, dyn, sch, V0, V, dt)
+    exp = np.roll(V0, -n if c > 0 else n, axis=3)
+    assert np.abs(V - exp).max() <= 2 * n * np.spacing(1.0)
+
+
+def test_p3_courant_one_shift_open_axis(oracle_lib):
+    """The same shift along the open x axis: information enters from the
+    right end only, so nodes more than n from it are exact shifts."""
+    g = small_grid(nx=30, ny=3, nv=3, nth=4)
+    c = 1.7
+    dyn = drift_dyn(drift=(c, 0, 0, 0))
+    sch = W.scheme("upwind1", "euler", cfl=1.0, clamp=False)
+    V0 = np.random.default_rng(3).uniform(-1, 1, size=g["n"])
+    dt = oracle_lib.cfl_dt(g, dyn, 1.0, 10.0)
+    V = V0.copy()
+    n = 9
+    for _ in range(n):
+        V = oracle_lib.step(g, dyn, sch, V0, V, dt)
+    m = 30 - 1 - n
+    assert np.abs(V[:m] - V0[n:n + m]).max() <= 2 * n * np.spacing(1.0)
+
+
+def _disk_problem(N, role, r=1.0):
+    g = W.car_grid(N, N, 3, 4, xy=(-4.0, 4.0))
+    dyn = drift_dyn(axes=(0, 1), speed=1.0, norm="ball", role=role)
+    return g, dyn
+
+
+@pytest.mark.parametrize("sch", [UP_EU, ENO_RK])
+def test_p4_disk_grows_at_unit_speed(oracle_lib, sch):
+    """z' = u on (x, y), |u| <= 1, the input minimising (adversarial): the
+    exact value is max(|z| - t, 0) - r, a disk whose radius grows to r + t.
+    First-order scheme: the error in a band around the zero level set halves
+    with h; ENO2 + RK2 is at least as accurate."""
+    errs = []
+    for N in (41, 81):
+        g, dyn = _disk_problem(N, "min")
+        V0 = oracle_lib.target_cylinders(g, [0.0], [0.0], [1.0])
+        V, _ = oracle_lib.solve(g, dyn, sch, V0, 1.0)
+        x, _ = _line(g, 0)
+        y, _ = _line(g, 1)
+        rad = np.broadcast_to(np.sqrt(x ** 2 + y ** 2), g["n"])
+        exact = np.maximum(rad - 1.0, 0.0) - 1.0
+        band = (rad > 1.5) & (rad < 3.0)
+        errs.append(np.abs(V - exact)[band].max())
+    h = 8.0 / 40
+    assert errs[0] < 1.5 * h
+    assert errs[0] / errs[1] > 1.6, errs
+    if sch is ENO_RK:
+        assert errs[1] < 0.05
+
+
+def test_p4_disk_eno_beats_upwind(oracle_lib):
+    g, dyn = _disk_problem(61, "min")
+    V0 = oracle_lib.target_cylinders(g, [0.0], [0.0], [1.0])
+    x, _ = _line(g, 0)
+    y, _ = _line(g, 1)
+    rad = np.broadcast_to(np.sqrt(x ** 2 + y ** 2), g["n"])
+    exact = np.maximum(rad - 1.0, 0.0) - 1.0
+    band = (rad > 1.5) & (rad < 3.0)
+    e1 = np.abs(oracle_lib.solve(g, dyn, UP_EU, V0, 1.0)[0] - exact)[band].max()
+    e2 = np.abs(oracle_lib.solve(g, dyn, ENO_RK, V0, 1.0)[0] - exact)[band].max()
+    assert e2 < e1
+
+
+@pytest.mark.parametrize("sch", ALL_SCHEMES)
+def test_p4_disk_stays_when_input_maximises(oracle_lib, sch):
+    """With the input maximising (escaping), the tube is the disk itself:
+    V0 is convex, L(V) >= 0 everywhere and the clamp keeps V = V0."""
+    g, dyn = _disk_problem(31, "max")
+    V0 = oracle_lib.target_cylinders(g, [0.13], [-0.21], [1.0])
+    V, _ = oracle_lib.solve(g, dyn, sch, V0, 1.0)
+    assert np.array_equal(V, V0)
+
+
+def _car_small(nth=12):
+    g = W.car_grid(24, 24, 8, nth)
+    return g
+
+
+@pytest.mark.parametrize("sch", [UP_EU, W.scheme("upwind1", "rk2"), ENO_RK])
+def test_p5_tube_is_monotone(oracle_lib, sch):
+    """The BRT only grows.  V^n <= V0 bit for bit at every step (the clamp).
+    First-order upwind with CFL <= 1 is a monotone scheme (every update is a
+    convex combination of neighbours, and TVD-RK2 is a convex combination of
+    Euler steps), so {V^n <= 0} stays inside {V^(n+1) <= 0}.  ENO2 is not
+    monotone: it may drop a node, but only one lying within a small band
+    (0.1 h) of the zero level set."""
+    g = _car_small()
+    dyn = W.car_dynamics()
+    cx, cy, r = W.cylinders(5, 3)
+    V0 = oracle_lib.target_cylinders(g, cx, cy, r)
+    dt = oracle_lib.cfl_dt(g, dyn, 0.8, 1.0)
+    h = min(oracle_lib.spacing(g, 0), oracle_lib.spacing(g, 1))
+    V = V0.copy()
+    sizes = []
+    for _ in range(20):
+        Vn = oracle_lib.step(g, dyn, sch, V0, V, dt)
+        assert np.all(Vn <= V0)
+        lost = (V <= 0) & (Vn > 0)
+        if sch["deriv"] == "upwind1":
+            assert not lost.any()
+        else:
+            assert np.all(V[lost] > -0.1 * h)
+            assert np.all(Vn[lost] < 0.1 * h)
+        sizes.append(int((Vn <= 0).sum()))
+        V = Vn
+    assert sizes[-1] > sizes[0] > int((V0 <= 0).sum())
+
+
+def test_p6_mirror_and_rotation_symmetry(oracle_lib):
+    """The car is invariant under the mirror (x, y, theta) -> (x, -y, -theta)
+    and the quarter turn (x, y, theta) -> (y, -x, theta - pi/2).  Solving
+    for the mirrored/rotated obstacles gives the mirrored/rotated value
+    function (first order scheme: to rounding)."""
+    g = W.car_grid(20, 20, 6, 12)
+    dyn = W.car_dynamics()
+    cx, cy, r = W.cylinders(7, 3)
+    T = 0.5
+    V0 = oracle_lib.target_cylinders(g, cx, cy, r)
+    V, _ = oracle_lib.solve(g, dyn, UP_EU, V0, T)
+    # mirror: y -> -y, theta node l -> (N - l) mod N
+    Vm0 = oracle_lib.target_cylinders(g, cx, -cy, r)
+    Vm, _ = oracle_lib.solve(g, dyn, UP_EU, Vm0, T)
+    lidx = (-np.arange(12)) % 12
+    mapped = V[:, ::-1, :, :][:, :, :, lidx]
+    assert np.abs(Vm - mapped).max() < 1e-11
+    # rotation: obstacle (cx, cy) -> (cy, -cx); node (i, j, l) of the rotated
+    # problem holds the original value at (N-1-j, i, l + N/4)
+    Vr0 = oracle_lib.target_cylinders(g, cy, -cx, r)
+    Vr, _ = oracle_lib.solve(g, dyn, UP_EU, Vr0, T)
+    rot = np.transpose(V, (1, 0, 2, 3))[:, ::-1, :, :]
+    rot = np.roll(rot, -3, axis=3)
+    assert np.abs(Vr - rot).max() < 1e-11
+
+
+def test_thread_count_invariance(oracle_lib):
+    g = _car_small(nth=8)
+    cx, cy, r = W.cylinders(3, 2)
+    V0 = oracle_lib.target_cylinders(g, cx, cy, r)
+    before = oracle_lib.threads()
+    try:
+        oracle_lib.set_threads(1)
+        V1, _ = oracle_lib.solve(g, W.car_dynamics(d_max=0.1), ENO_RK, V0, 0.3)
+        oracle_lib.set_threads(4)
+        V4, _ = oracle_lib.solve(g, W.car_dynamics(d_max=0.1), ENO_RK, V0, 0.3)
+    finally:
+        oracle_lib.set_threads(before)
+    assert np.array_equal(V1, V4)
+
+
+def test_target_is_signed_distance(oracle_lib):
+    """Eq (7): distance to the cone centre minus its radius; for a union the
+    minimum over cones; the same value for every (v, theta)."""
+    g = small_grid(nx=9, ny=7, nv=3, nth=4)
+    V0 = oracle_lib.target_cylinders(g, [0.5, -2.0], [1.0, 0.0], [0.75, 0.4])
+    x, _ = _line(g, 0)
+    y, _ = _line(g, 1)
+    d1 = np.hypot(x - 0.5, y - 1.0) - 0.75
+    d2 = np.hypot(x + 2.0, y - 0.0) - 0.4
+    np.testing.assert_allclose(V0, np.broadcast_to(np.minimum(d1, d2), g["n"]), atol=1e-14)
