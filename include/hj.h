@@ -1,0 +1,213 @@
+/*
+ * hj.h -- C ABI of the MI355X (gfx950) Hamilton-Jacobi reachability library.
+ *
+ * The library computes the Backward Reachable Tube (BRT) of a 4D car
+ * (x, y, v, theta) on a grid by time-stepping the HJ variational inequality
+ * of arXiv 2012.04011 (eq (4)): one-sided derivatives (eq (5), or second-order
+ * ENO), a Lax-Friedrichs Hamiltonian with the optimal bang-bang control and
+ * disturbance plus dissipation, forward Euler (Algorithm 2) or two-stage TVD
+ * Runge-Kutta, a CFL step from a max-reduction of the dissipation
+ * coefficients (Algorithm 1, step-bound lines), and the clamp V = min(V0, V)
+ * (Algorithm 2, end of the loop body).  The BRT is {z : V(z) <= 0}
+ * (section "Hamilton-Jacobi Reachability Analysis").
+ *
+ * Conventions for every function:
+ *   - Every function returns hj_status; nothing throws across the ABI.  On
+ *     failure a message is available from hj_last_error() (thread-local), and
+ *     the handle is unchanged: all arguments are validated before any device
+ *     work is enqueued.
+ *   - External array layout: C order [Nx][Ny][Nv][Ntheta], theta fastest --
+ *     the paper's 4D array V[N1][N2][N3][N4].  Element type per `dtype`
+ *     (HJ_F32 or HJ_F64); location per `where` (HJ_HOST or HJ_DEVICE; device
+ *     pointers must be on the handle's device).
+ *   - Ownership: inputs are copied during the call and stay the caller's.
+ *     Device buffers allocated by hj_grid_create belong to the handle until
+ *     hj_grid_destroy.
+ *   - Streams: all device work is enqueued in order on the stream given to
+ *     hj_grid_create (borrowed; NULL = the device's null stream).  Calls that
+ *     return data to host memory synchronise that stream; the rest return
+ *     before the GPU finishes.  Device outputs are ready in stream order.
+ *   - Threads: one host thread per handle at a time; different handles may
+ *     be used concurrently.
+ */
+#ifndef HJ_H
+#define HJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HJ_OK = 0,
+  HJ_ERR_INVALID_ARG = 1,   /* a null pointer, bad size, range or enum value */
+  HJ_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+  HJ_ERR_DEVICE = 3,        /* a HIP call failed (message names it) */
+  HJ_ERR_NOT_READY = 4,     /* no target set yet */
+  HJ_ERR_NONFINITE = 5,     /* NaN or infinity in an input array */
+  HJ_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+} hj_status;
+
+/* enum values used in the descriptors */
+enum { HJ_F32 = 0, HJ_F64 = 1 };                      /* dtype / precision */
+enum { HJ_HOST = 0, HJ_DEVICE = 1 };                  /* where an array lives */
+enum { HJ_DYN_CAR4D = 0, HJ_DYN_DRIFT_INPUT = 1 };    /* dynamics kind */
+enum { HJ_UPWIND1 = 0, HJ_ENO2 = 1 };                 /* derivative scheme */
+enum { HJ_EULER = 0, HJ_TVD_RK2 = 1 };                /* integrator */
+enum { HJ_CLAMP_NONE = 0, HJ_CLAMP_MIN_V0 = 1 };      /* target clamp */
+enum { HJ_NORM_BOX = 0, HJ_NORM_BALL = 1 };           /* test input set norm */
+enum { HJ_INPUT_MAXIMIZES = 0, HJ_INPUT_MINIMIZES = 1 };
+
+typedef struct hj_grid hj_grid; /* opaque, library-owned */
+
+/*
+ * Grid (section "Basic Numerical Solution": N_d nodes on axis d).  Axes are
+ * x, y, v, theta.  An ordinary axis has n[d] >= 3 nodes including both ends,
+ * x_i = lo + i (hi - lo) / (n - 1).  A periodic axis (bit d of
+ * periodic_mask) has n[d] >= 3 nodes over one period hi - lo,
+ * x_i = lo + i (hi - lo) / n.  hi > lo.  The total node count may not exceed
+ * 2^31 - 1.
+ */
+typedef struct {
+  int32_t n[4];
+  double lo[4], hi[4];
+  uint32_t periodic_mask;
+} hj_grid_desc;
+
+/*
+ * Dynamics.
+ * HJ_DYN_CAR4D: x' = v cos(theta) + d_x, y' = v sin(theta) + d_y, v' = a,
+ *   theta' = w.  Control |a| <= a_max, |w| <= w_max maximises grad(V).f;
+ *   disturbance |d_x| <= d_max[0], |d_y| <= d_max[1] minimises it (eq (3),
+ *   eq (4); the paper's car, eq (6), with the steering term replaced by a
+ *   bounded turn rate).  Axis 2 must be v and axis 3 theta.
+ * HJ_DYN_DRIFT_INPUT (closed-form checks): z' = drift + u, u nonzero only on
+ *   the axes in in_axes_mask, |u| <= in_speed in the box (per axis) or
+ *   Euclidean-ball norm (in_norm); the input maximises or minimises
+ *   (in_role).
+ * All bounds must be finite and >= 0.
+ */
+typedef struct {
+  int32_t kind;
+  double a_max, w_max, d_max[2];
+  double drift[4], in_speed;
+  uint32_t in_axes_mask;
+  int32_t in_norm, in_role;
+} hj_dynamics_desc;
+
+/*
+ * Scheme.  deriv: HJ_UPWIND1 (eq (5)) or HJ_ENO2; integrator: HJ_EULER
+ * (Algorithm 2) or HJ_TVD_RK2; precision: HJ_F32 or HJ_F64 storage and
+ * arithmetic of the time step (the CFL reduction is always FP64); clamp:
+ * HJ_CLAMP_MIN_V0 applies V = min(V0, V) once per full step; cfl in (0, 1].
+ */
+typedef struct {
+  int32_t deriv, integrator, precision, clamp;
+  double cfl;
+} hj_scheme_desc;
+
+/* What a solve did: steps taken, the CFL step, the shortened last step and
+ * the time reached (= the horizon). */
+typedef struct {
+  int64_t steps;
+  double dt, dt_last, t_final;
+} hj_solve_info;
+
+/* Device-side timing of the time loop (HIP events recorded on the handle's
+ * stream around the step kernels of each solve while profiling is on). */
+typedef struct {
+  int64_t solves;         /* solves timed */
+  int64_t step_launches;  /* step-kernel launches inside the timed loops */
+  double loop_ms;         /* summed event time of the timed loops */
+} hj_profile;
+
+/*
+ * Create a grid handle: validates the descriptors, allocates the device
+ * buffers (target V0, value V and the step's stage buffers, N values each in
+ * the scheme's precision) and builds the per-(v, theta) coefficient table on
+ * the host in FP64 (section "Indexed Processing Element": state vectors and
+ * cos/sin kept in a lookup table).  hip_stream is a hipStream_t (borrowed,
+ * must outlive the handle) or NULL.  *out receives the handle.
+ * Errors: HJ_ERR_INVALID_ARG, HJ_ERR_OUT_OF_MEMORY, HJ_ERR_DEVICE.
+ */
+hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn,
+                         const hj_scheme_desc *scheme, void *hip_stream, hj_grid **out);
+
+/* Free every buffer of the handle (after synchronising its stream).  NULL is
+ * accepted and ignored. */
+hj_status hj_grid_destroy(hj_grid *g);
+
+/*
+ * Set the target V0 = l(z) from a caller array (eq (4): V(z, 0) = l(z); the
+ * target set is {V0 <= 0}).  Also sets V := V0 and the time to 0.  v0 holds N
+ * values of `dtype` at `where` in the external layout.  Non-finite values are
+ * rejected (HJ_ERR_NONFINITE) and leave the handle unchanged.
+ */
+hj_status hj_set_target(hj_grid *g, const void *v0, int32_t dtype, int32_t where);
+
+/*
+ * Set the target to a union of m >= 1 cylinders in (x, y) (eq (7), minimum
+ * over obstacles): V0 = min_o(sqrt((x - cx_o)^2 + (y - cy_o)^2) - r_o), the
+ * same for every (v, theta); computed on the GPU in the scheme's precision.
+ * cx, cy, r are host arrays of m finite doubles, r >= 0.  Also sets V := V0
+ * and the time to 0.  Requires axes 0 and 1 to be x and y.
+ */
+hj_status hj_set_target_cylinders(hj_grid *g, const double *cx, const double *cy, const double *r,
+                                  int32_t m);
+
+/*
+ * Fixed-horizon BRT solve: V := V0, then n = ceil(T / dt) full steps with the
+ * CFL step dt (the last one shortened to T - (n - 1) dt), each step followed
+ * by the clamp if enabled.  T >= 0 (T = 0: no step).  The first call on a
+ * handle runs the CFL reduction and caches dt (the dissipation coefficients
+ * depend on the grid only).  Returns before the GPU finishes; *info (may be
+ * NULL) is filled on return.  Errors: HJ_ERR_NOT_READY without a target.
+ */
+hj_status hj_solve_brt(hj_grid *g, double horizon, hj_solve_info *info);
+
+/*
+ * One full time step (Euler, or both TVD-RK2 stages) from the current V,
+ * followed by the clamp if enabled.  dt > 0 is used as given; dt <= 0 takes
+ * the cached CFL step.  *dt_taken (may be NULL) receives the step used.
+ */
+hj_status hj_step(hj_grid *g, double dt, double *dt_taken);
+
+/* The CFL step dt = cfl / sum_d(alpha_d^max / dx_d) in FP64 (a max-reduction
+ * on the GPU over the dissipation coefficients of every node); a zero sum
+ * returns +infinity.  Synchronises. */
+hj_status hj_get_cfl_dt(hj_grid *g, double *dt);
+
+/* The per-axis maxima alpha_d^max behind hj_get_cfl_dt (4 doubles). */
+hj_status hj_get_alpha_max(hj_grid *g, double alpha_max[4]);
+
+/* Copy the current V (or, for hj_get_target, V0) out in the external layout
+ * as `dtype` at `where`.  HJ_HOST synchronises the stream. */
+hj_status hj_get_value(hj_grid *g, void *out, int32_t dtype, int32_t where);
+hj_status hj_get_target(hj_grid *g, void *out, int32_t dtype, int32_t where);
+
+/* Replace the current V (checkpoint resume at a step boundary); V0 is kept.
+ * Non-finite values are rejected. */
+hj_status hj_set_value(hj_grid *g, const void *v, int32_t dtype, int32_t where);
+
+/* Number of grid points N of the handle. */
+hj_status hj_get_num_points(hj_grid *g, int64_t *n);
+
+/* Turn the step-loop event timing on (1) or off (0); turning it on resets the
+ * counters. */
+hj_status hj_set_profiling(hj_grid *g, int32_t enable);
+
+/* Read the step-loop timing (synchronises the stream). */
+hj_status hj_get_profile(hj_grid *g, hj_profile *out);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *hj_last_error(void);
+
+/* Library version string. */
+const char *hj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJ_H */

@@ -1,0 +1,720 @@
+// hj_abi.hip -- the C ABI (include/hj.h): validation, device buffers, the
+// per-(v, theta) coefficient table, the CFL step and the step schedule.
+// Every numerical step of the solve runs in the kernels of hj_kernels.hip.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hj.h"
+#include "hj_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hj_status fail(hj_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HJ_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? HJ_ERR_OUT_OF_MEMORY : HJ_ERR_DEVICE,        \
+                  "%s failed: %s", #call, hipGetErrorString(e_));                          \
+  } while (0)
+
+bool bit(uint32_t mask, int d) { return ((mask >> d) & 1u) != 0; }
+
+}  // namespace
+
+struct hj_grid {
+  hj_grid_desc g;
+  hj_dynamics_desc dyn;
+  hj_scheme_desc sch;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t npts = 0;
+  size_t elem = 4;
+
+  // device buffers (precision of the scheme)
+  void *v0 = nullptr;   // target
+  void *v = nullptr;    // current value V^n
+  void *w1 = nullptr;   // RK stage value V^1
+  void *w2 = nullptr;   // next value (swapped with v after a step)
+  void *lut = nullptr;  // bx | by | ax | ay in the scheme's precision
+  double *lut64 = nullptr;  // ax | ay in FP64 for the CFL reduction
+  double *amax_dev = nullptr;
+  int32_t *flag_dev = nullptr;
+  double *amax_host = nullptr;  // pinned
+  int32_t *flag_host = nullptr;  // pinned
+
+  // host-side constants of the Hamiltonian (see hj_internal.h)
+  double bv = 0, bth = 0, av = 0, ath = 0, sig[4] = {0, 0, 0, 0}, sig_ball = 0;
+  uint32_t ball_mask = 0;
+  double h[4];
+
+  bool has_target = false;
+  bool dt_cached = false;
+  double amax[4] = {0, 0, 0, 0};
+  double dt_cfl = 0;  // +inf when nothing moves
+
+  // step-loop timing: one (begin, end) event pair per timed solve, folded
+  // into prof when read (no host synchronisation between solves)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;  // pairs recorded since the last fold
+  hj_profile prof = {0, 0, 0.0};
+};
+
+namespace {
+
+double spacing(const hj_grid_desc &g, int d) {
+  if (bit(g.periodic_mask, d)) return (g.hi[d] - g.lo[d]) / g.n[d];
+  return (g.hi[d] - g.lo[d]) / (g.n[d] - 1);
+}
+
+// Node coordinate x_i = lo + i h (the same expression everywhere; no fused
+// multiply-add so that the table is reproducible on any host).
+double node(const hj_grid_desc &g, int d, int i) {
+#pragma clang fp contract(off)
+  return g.lo[d] + i * spacing(g, d);
+}
+
+hj_status validate(const hj_grid_desc *g, const hj_dynamics_desc *dy, const hj_scheme_desc *s) {
+  if (!g || !dy || !s) return fail(HJ_ERR_INVALID_ARG, "null descriptor");
+  int64_t np = 1;
+  for (int d = 0; d < 4; ++d) {
+    if (g->n[d] < 3) return fail(HJ_ERR_INVALID_ARG, "grid axis %d has %d nodes (need >= 3)", d, g->n[d]);
+    if (!isfinite(g->lo[d]) || !isfinite(g->hi[d]) || !(g->hi[d] > g->lo[d]))
+      return fail(HJ_ERR_INVALID_ARG, "grid axis %d: need finite lo < hi", d);
+    np *= g->n[d];
+    if (np > INT32_MAX) return fail(HJ_ERR_INVALID_ARG, "grid has more than 2^31-1 nodes");
+  }
+  if (g->periodic_mask & ~0xFu) return fail(HJ_ERR_INVALID_ARG, "periodic_mask has bits above axis 3");
+  if (dy->kind != HJ_DYN_CAR4D && dy->kind != HJ_DYN_DRIFT_INPUT)
+    return fail(HJ_ERR_INVALID_ARG, "unknown dynamics kind %d", dy->kind);
+  double vals[] = {dy->a_max, dy->w_max, dy->d_max[0], dy->d_max[1], dy->in_speed};
+  for (double x : vals)
+    if (!isfinite(x) || x < 0) return fail(HJ_ERR_INVALID_ARG, "input bounds must be finite and >= 0");
+  for (int d = 0; d < 4; ++d)
+    if (!isfinite(dy->drift[d])) return fail(HJ_ERR_INVALID_ARG, "drift must be finite");
+  if (dy->kind == HJ_DYN_DRIFT_INPUT) {
+    if (dy->in_axes_mask & ~0xFu) return fail(HJ_ERR_INVALID_ARG, "in_axes_mask has bits above axis 3");
+    if (dy->in_norm != HJ_NORM_BOX && dy->in_norm != HJ_NORM_BALL)
+      return fail(HJ_ERR_INVALID_ARG, "unknown in_norm %d", dy->in_norm);
+    if (dy->in_role != HJ_INPUT_MAXIMIZES && dy->in_role != HJ_INPUT_MINIMIZES)
+      return fail(HJ_ERR_INVALID_ARG, "unknown in_role %d", dy->in_role);
+  }
+  if (s->deriv != HJ_UPWIND1 && s->deriv != HJ_ENO2) return fail(HJ_ERR_INVALID_ARG, "unknown deriv %d", s->deriv);
+  if (s->integrator != HJ_EULER && s->integrator != HJ_TVD_RK2)
+    return fail(HJ_ERR_INVALID_ARG, "unknown integrator %d", s->integrator);
+  if (s->precision != HJ_F32 && s->precision != HJ_F64)
+    return fail(HJ_ERR_INVALID_ARG, "unknown precision %d", s->precision);
+  if (s->clamp != HJ_CLAMP_NONE && s->clamp != HJ_CLAMP_MIN_V0)
+    return fail(HJ_ERR_INVALID_ARG, "unknown clamp %d", s->clamp);
+  if (!(s->cfl > 0.0 && s->cfl <= 1.0)) return fail(HJ_ERR_INVALID_ARG, "cfl must lie in (0, 1]");
+  return HJ_OK;
+}
+
+// Per-(v, theta) coefficient table in FP64 (bx, by, ax, ay) and the uniform
+// constants.  Car: bx = v cos(theta), by = v sin(theta), alpha_x =
+// |v cos(theta)| + d_x^max (the bound on |x'| over all inputs), alpha_y
+// likewise; v' = a and theta' = w are pure inputs: sig = +a_max, +w_max
+// (maximising control), -d_max on x, y (minimising disturbance).
+void build_table(hj_grid *G, std::vector<double> &tab) {
+#pragma clang fp contract(off)
+  const hj_grid_desc &g = G->g;
+  const hj_dynamics_desc &dy = G->dyn;
+  int n2 = g.n[2], n3 = g.n[3];
+  int64_t m = (int64_t)n2 * n3;
+  tab.assign(4 * m, 0.0);
+  for (int d = 0; d < 4; ++d) G->h[d] = spacing(g, d);
+  if (dy.kind == HJ_DYN_CAR4D) {
+    for (int k = 0; k < n2; ++k) {
+      double v = node(g, 2, k);
+      for (int l = 0; l < n3; ++l) {
+        double th = node(g, 3, l);
+        int64_t c = (int64_t)k * n3 + l;
+        double bx = v * cos(th), by = v * sin(th);
+        tab[c] = bx;
+        tab[m + c] = by;
+        tab[2 * m + c] = fabs(bx) + dy.d_max[0];
+        tab[3 * m + c] = fabs(by) + dy.d_max[1];
+      }
+    }
+    G->bv = 0;
+    G->bth = 0;
+    G->av = dy.a_max;
+    G->ath = dy.w_max;
+    G->sig[0] = -dy.d_max[0];
+    G->sig[1] = -dy.d_max[1];
+    G->sig[2] = dy.a_max;
+    G->sig[3] = dy.w_max;
+    G->sig_ball = 0;
+    G->ball_mask = 0;
+  } else {
+    double s = dy.in_speed;
+    double sgn = dy.in_role == HJ_INPUT_MAXIMIZES ? 1.0 : -1.0;
+    double alpha[4];
+    for (int d = 0; d < 4; ++d) alpha[d] = fabs(dy.drift[d]) + (bit(dy.in_axes_mask, d) ? s : 0.0);
+    for (int64_t c = 0; c < m; ++c) {
+      tab[c] = dy.drift[0];
+      tab[m + c] = dy.drift[1];
+      tab[2 * m + c] = alpha[0];
+      tab[3 * m + c] = alpha[1];
+    }
+    G->bv = dy.drift[2];
+    G->bth = dy.drift[3];
+    G->av = alpha[2];
+    G->ath = alpha[3];
+    for (int d = 0; d < 4; ++d)
+      G->sig[d] = (dy.in_norm == HJ_NORM_BOX && bit(dy.in_axes_mask, d)) ? sgn * s : 0.0;
+    G->sig_ball = dy.in_norm == HJ_NORM_BALL ? sgn * s : 0.0;
+    G->ball_mask = dy.in_norm == HJ_NORM_BALL ? dy.in_axes_mask : 0u;
+  }
+}
+
+hipStream_t S(hj_grid *g) { return g->stream; }
+
+template <typename T>
+T *buf(void *p) {
+  return static_cast<T *>(p);
+}
+
+void free_all(hj_grid *G) {
+  void *ptrs[] = {G->v0, G->v, G->w1, G->w2, G->lut, G->lut64, G->amax_dev, G->flag_dev};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (G->amax_host) (void)hipHostFree(G->amax_host);
+  if (G->flag_host) (void)hipHostFree(G->flag_host);
+  for (hipEvent_t e : G->ev_pool) (void)hipEventDestroy(e);
+  G->ev_pool.clear();
+}
+
+// Fold the recorded event pairs into the profile (synchronises on them).
+hj_status fold_events(hj_grid *G) {
+  for (size_t i = 0; i < G->ev_used; ++i) {
+    HJ_HIP(hipEventSynchronize(G->ev_pool[2 * i + 1]));
+    float ms = 0;
+    HJ_HIP(hipEventElapsedTime(&ms, G->ev_pool[2 * i], G->ev_pool[2 * i + 1]));
+    G->prof.loop_ms += ms;
+  }
+  G->ev_used = 0;
+  return HJ_OK;
+}
+
+// The next free (begin, end) pair, growing the pool as needed.
+hj_status next_events(hj_grid *G, hipEvent_t *b, hipEvent_t *e) {
+  while (G->ev_pool.size() < 2 * (G->ev_used + 1)) {
+    hipEvent_t ev;
+    HJ_HIP(hipEventCreate(&ev));
+    G->ev_pool.push_back(ev);
+  }
+  *b = G->ev_pool[2 * G->ev_used];
+  *e = G->ev_pool[2 * G->ev_used + 1];
+  G->ev_used += 1;
+  return HJ_OK;
+}
+
+hj_status check_handle(hj_grid *g) {
+  if (!g) return fail(HJ_ERR_INVALID_ARG, "null handle");
+  return HJ_OK;
+}
+
+hj_status check_array(const void *p, int32_t dtype, int32_t where) {
+  if (!p) return fail(HJ_ERR_INVALID_ARG, "null array");
+  if (dtype != HJ_F32 && dtype != HJ_F64) return fail(HJ_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+  if (where != HJ_HOST && where != HJ_DEVICE) return fail(HJ_ERR_INVALID_ARG, "unknown location %d", where);
+  return HJ_OK;
+}
+
+hj_status set_device(hj_grid *G) {
+  HJ_HIP(hipSetDevice(G->device));
+  return HJ_OK;
+}
+
+// Is every value of a caller array finite?  Host arrays are scanned on the
+// host; device arrays by a kernel (then one 4-byte read-back).
+hj_status all_finite(hj_grid *G, const void *p, int32_t dtype, int32_t where, bool *ok) {
+  int64_t n = G->npts;
+  if (where == HJ_HOST) {
+    *ok = true;
+    if (dtype == HJ_F32) {
+      const float *a = static_cast<const float *>(p);
+      for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(a[i])) return *ok = false, HJ_OK;
+    } else {
+      const double *a = static_cast<const double *>(p);
+      for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(a[i])) return *ok = false, HJ_OK;
+    }
+    return HJ_OK;
+  }
+  if (dtype == HJ_F32)
+    HJ_HIP(hj::launch_nonfinite(static_cast<const float *>(p), n, G->flag_dev, S(G)));
+  else
+    HJ_HIP(hj::launch_nonfinite(static_cast<const double *>(p), n, G->flag_dev, S(G)));
+  HJ_HIP(hipMemcpyAsync(G->flag_host, G->flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, S(G)));
+  HJ_HIP(hipStreamSynchronize(S(G)));
+  *ok = G->flag_host[0] == 0;
+  return HJ_OK;
+}
+
+// Copy a caller array (any dtype / location) into the device buffer dst of
+// the handle's precision.
+hj_status import_array(hj_grid *G, void *dst, const void *src, int32_t dtype, int32_t where) {
+  int64_t n = G->npts;
+  bool same = (dtype == HJ_F32) == (G->elem == 4);
+  if (where == HJ_DEVICE) {
+    if (same) {
+      HJ_HIP(hipMemcpyAsync(dst, src, n * G->elem, hipMemcpyDeviceToDevice, S(G)));
+    } else if (G->elem == 4) {
+      HJ_HIP(hj::launch_cast(buf<float>(dst), static_cast<const double *>(src), n, S(G)));
+    } else {
+      HJ_HIP(hj::launch_cast(buf<double>(dst), static_cast<const float *>(src), n, S(G)));
+    }
+    return HJ_OK;
+  }
+  if (same) {
+    HJ_HIP(hipMemcpyAsync(dst, src, n * G->elem, hipMemcpyHostToDevice, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+    return HJ_OK;
+  }
+  // host array of the other precision: convert on the host, then copy
+  if (G->elem == 4) {
+    std::vector<float> tmp(n);
+    const double *a = static_cast<const double *>(src);
+    for (int64_t i = 0; i < n; ++i) tmp[i] = (float)a[i];
+    HJ_HIP(hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+  } else {
+    std::vector<double> tmp(n);
+    const float *a = static_cast<const float *>(src);
+    for (int64_t i = 0; i < n; ++i) tmp[i] = (double)a[i];
+    HJ_HIP(hipMemcpyAsync(dst, tmp.data(), n * 8, hipMemcpyHostToDevice, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+  }
+  return HJ_OK;
+}
+
+hj_status export_array(hj_grid *G, const void *src, void *dst, int32_t dtype, int32_t where) {
+  int64_t n = G->npts;
+  bool same = (dtype == HJ_F32) == (G->elem == 4);
+  if (where == HJ_DEVICE) {
+    if (same) {
+      HJ_HIP(hipMemcpyAsync(dst, src, n * G->elem, hipMemcpyDeviceToDevice, S(G)));
+    } else if (G->elem == 4) {
+      HJ_HIP(hj::launch_cast(static_cast<double *>(dst), static_cast<const float *>(src), n, S(G)));
+    } else {
+      HJ_HIP(hj::launch_cast(static_cast<float *>(dst), static_cast<const double *>(src), n, S(G)));
+    }
+    return HJ_OK;
+  }
+  if (same) {
+    HJ_HIP(hipMemcpyAsync(dst, src, n * G->elem, hipMemcpyDeviceToHost, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+    return HJ_OK;
+  }
+  if (G->elem == 4) {
+    std::vector<float> tmp(n);
+    HJ_HIP(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+    double *o = static_cast<double *>(dst);
+    for (int64_t i = 0; i < n; ++i) o[i] = tmp[i];
+  } else {
+    std::vector<double> tmp(n);
+    HJ_HIP(hipMemcpyAsync(tmp.data(), src, n * 8, hipMemcpyDeviceToHost, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+    float *o = static_cast<float *>(dst);
+    for (int64_t i = 0; i < n; ++i) o[i] = (float)tmp[i];
+  }
+  return HJ_OK;
+}
+
+// CFL step (Algorithm 1): alpha_d^max by the FP64 reduction kernel, then
+// dt = cfl / sum_d(alpha_d^max / dx_d) on the host.  Cached per handle.
+hj_status ensure_dt(hj_grid *G) {
+  if (G->dt_cached) return HJ_OK;
+  int64_t m = (int64_t)G->g.n[2] * G->g.n[3];
+  HJ_HIP(hj::launch_alpha_max(G->lut64, G->lut64 + m, m, G->av, G->ath, G->amax_dev, S(G)));
+  HJ_HIP(hipMemcpyAsync(G->amax_host, G->amax_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, S(G)));
+  HJ_HIP(hipStreamSynchronize(S(G)));
+  double s = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    G->amax[d] = G->amax_host[d];
+    s += G->amax[d] / G->h[d];
+  }
+  G->dt_cfl = s == 0.0 ? INFINITY : G->sch.cfl / s;
+  G->dt_cached = true;
+  return HJ_OK;
+}
+
+template <typename T>
+hj::StageArgs<T> stage_args(hj_grid *G) {
+  hj::StageArgs<T> a;
+  memset(&a, 0, sizeof a);
+  const hj_grid_desc &g = G->g;
+  for (int d = 0; d < 4; ++d) a.n[d] = g.n[d];
+  a.st[3] = 1;
+  a.st[2] = g.n[3];
+  a.st[1] = (int64_t)g.n[2] * g.n[3];
+  a.st[0] = (int64_t)g.n[1] * g.n[2] * g.n[3];
+  a.periodic_mask = g.periodic_mask;
+  for (int d = 0; d < 4; ++d) {
+    a.inv_h[d] = (T)(1.0 / G->h[d]);
+    a.sig[d] = (T)G->sig[d];
+  }
+  a.lut = buf<const T>(G->lut);
+  a.bv = (T)G->bv;
+  a.bth = (T)G->bth;
+  a.av = (T)G->av;
+  a.ath = (T)G->ath;
+  a.sig_ball = (T)G->sig_ball;
+  a.ball_mask = G->ball_mask;
+  a.npts = G->npts;
+  return a;
+}
+
+// One full step of length dt: Euler (one stage) or TVD-RK2 (two stages),
+// clamp fused into the last stage.  Swaps v and w2.
+template <typename T>
+hj_status enqueue_step(hj_grid *G, double dt, int64_t *launches) {
+  hj::StageArgs<T> a = stage_args<T>(G);
+  a.dt = (T)dt;
+  a.v0 = buf<const T>(G->v0);
+  bool ball = G->ball_mask != 0;
+  int clamp = G->sch.clamp == HJ_CLAMP_MIN_V0;
+  if (G->sch.integrator == HJ_EULER) {
+    a.vs = buf<const T>(G->v);
+    a.out = buf<T>(G->w2);
+    a.mode = hj::kPlain;
+    a.clamp = clamp;
+    HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
+    *launches += 1;
+  } else {
+    a.vs = buf<const T>(G->v);
+    a.out = buf<T>(G->w1);
+    a.mode = hj::kPlain;
+    a.clamp = 0;
+    HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
+    a.vs = buf<const T>(G->w1);
+    a.vn = buf<const T>(G->v);
+    a.out = buf<T>(G->w2);
+    a.mode = hj::kAverage;
+    a.clamp = clamp;
+    HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
+    *launches += 2;
+  }
+  void *t = G->v;
+  G->v = G->w2;
+  G->w2 = t;
+  return HJ_OK;
+}
+
+hj_status step_once(hj_grid *G, double dt, int64_t *launches) {
+  if (G->elem == 4) return enqueue_step<float>(G, dt, launches);
+  return enqueue_step<double>(G, dt, launches);
+}
+
+hj_status reset_value(hj_grid *G) {
+  HJ_HIP(hipMemcpyAsync(G->v, G->v0, G->npts * G->elem, hipMemcpyDeviceToDevice, S(G)));
+  return HJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hj_last_error(void) { return g_last_error.c_str(); }
+
+const char *hj_version(void) { return "hjreach-gfx950 0.1"; }
+
+hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, const hj_scheme_desc *scheme,
+                         void *hip_stream, hj_grid **out) {
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output handle pointer");
+  *out = nullptr;
+  hj_status st = validate(grid, dyn, scheme);
+  if (st != HJ_OK) return st;
+  hj_grid *G = new (std::nothrow) hj_grid;
+  if (!G) return fail(HJ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  G->g = *grid;
+  G->dyn = *dyn;
+  G->sch = *scheme;
+  G->stream = static_cast<hipStream_t>(hip_stream);
+  G->npts = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * grid->n[3];
+  G->elem = scheme->precision == HJ_F32 ? 4 : 8;
+  std::vector<double> tab;
+  build_table(G, tab);
+  int64_t m = (int64_t)grid->n[2] * grid->n[3];
+
+  hipError_t e = hipGetDevice(&G->device);
+  size_t bytes = G->npts * G->elem;
+  bool rk2 = scheme->integrator == HJ_TVD_RK2;
+  if (e == hipSuccess) e = hipMalloc(&G->v0, bytes);
+  if (e == hipSuccess) e = hipMalloc(&G->v, bytes);
+  if (e == hipSuccess) e = hipMalloc(&G->w2, bytes);
+  if (e == hipSuccess && rk2) e = hipMalloc(&G->w1, bytes);
+  if (e == hipSuccess) e = hipMalloc(&G->lut, 4 * m * G->elem);
+  if (e == hipSuccess) e = hipMalloc(&G->lut64, 2 * m * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&G->amax_dev, 4 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&G->flag_dev, sizeof(int32_t));
+  if (e == hipSuccess) e = hipHostMalloc(&G->amax_host, 4 * sizeof(double), 0);
+  if (e == hipSuccess) e = hipHostMalloc(&G->flag_host, sizeof(int32_t), 0);
+  if (e == hipSuccess) {
+    // FP64 alphas for the reduction; the table in the step's precision.
+    e = hipMemcpyAsync(G->lut64, tab.data() + 2 * m, 2 * m * sizeof(double), hipMemcpyHostToDevice, G->stream);
+    if (e == hipSuccess) {
+      if (G->elem == 8) {
+        e = hipMemcpyAsync(G->lut, tab.data(), 4 * m * 8, hipMemcpyHostToDevice, G->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
+      } else {
+        std::vector<float> t32(4 * m);
+        for (int64_t i = 0; i < 4 * m; ++i) t32[i] = (float)tab[i];
+        e = hipMemcpyAsync(G->lut, t32.data(), 4 * m * 4, hipMemcpyHostToDevice, G->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
+      }
+    }
+  }
+  if (e != hipSuccess) {
+    free_all(G);
+    delete G;
+    return fail(e == hipErrorOutOfMemory ? HJ_ERR_OUT_OF_MEMORY : HJ_ERR_DEVICE, "hj_grid_create: %s",
+                hipGetErrorString(e));
+  }
+  *out = G;
+  return HJ_OK;
+}
+
+hj_status hj_grid_destroy(hj_grid *G) {
+  if (!G) return HJ_OK;
+  (void)hipSetDevice(G->device);
+  (void)hipStreamSynchronize(G->stream);
+  free_all(G);
+  delete G;
+  return HJ_OK;
+}
+
+hj_status hj_set_target(hj_grid *G, const void *v0, int32_t dtype, int32_t where) {
+  hj_status st = check_handle(G);
+  if (st == HJ_OK) st = check_array(v0, dtype, where);
+  if (st != HJ_OK) return st;
+  if ((st = set_device(G)) != HJ_OK) return st;
+  bool ok = false;
+  if ((st = all_finite(G, v0, dtype, where, &ok)) != HJ_OK) return st;
+  if (!ok) return fail(HJ_ERR_NONFINITE, "target contains NaN or infinity");
+  if ((st = import_array(G, G->v0, v0, dtype, where)) != HJ_OK) return st;
+  if ((st = reset_value(G)) != HJ_OK) return st;
+  G->has_target = true;
+  return HJ_OK;
+}
+
+hj_status hj_set_target_cylinders(hj_grid *G, const double *cx, const double *cy, const double *r, int32_t m) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!cx || !cy || !r) return fail(HJ_ERR_INVALID_ARG, "null obstacle array");
+  if (m < 1) return fail(HJ_ERR_INVALID_ARG, "need at least one obstacle (m = %d)", m);
+  if (bit(G->g.periodic_mask, 0) || bit(G->g.periodic_mask, 1))
+    return fail(HJ_ERR_INVALID_ARG, "cylinder targets need open x and y axes");
+  for (int o = 0; o < m; ++o)
+    if (!isfinite(cx[o]) || !isfinite(cy[o]) || !isfinite(r[o]) || r[o] < 0)
+      return fail(HJ_ERR_INVALID_ARG, "obstacle %d: need finite centre and radius >= 0", o);
+  if ((st = set_device(G)) != HJ_OK) return st;
+  const int K = hj::kMaxCylindersPerLaunch;
+  for (int o0 = 0; o0 < m; o0 += K) {
+    int cnt = m - o0 < K ? m - o0 : K;
+    bool last = o0 + cnt >= m;
+    if (G->elem == 4) {
+      hj::CylinderArgs<float> a;
+      memset(&a, 0, sizeof a);
+      a.v0 = buf<float>(G->v0);
+      a.v = last ? buf<float>(G->v) : nullptr;
+      a.n0 = G->g.n[0];
+      a.n1 = G->g.n[1];
+      a.plane = (int64_t)G->g.n[2] * G->g.n[3];
+      a.lo0 = (float)G->g.lo[0];
+      a.h0 = (float)G->h[0];
+      a.lo1 = (float)G->g.lo[1];
+      a.h1 = (float)G->h[1];
+      a.m = cnt;
+      a.combine = o0 > 0;
+      for (int i = 0; i < cnt; ++i) {
+        a.cx[i] = (float)cx[o0 + i];
+        a.cy[i] = (float)cy[o0 + i];
+        a.r[i] = (float)r[o0 + i];
+      }
+      HJ_HIP(hj::launch_cylinders(a, S(G)));
+    } else {
+      hj::CylinderArgs<double> a;
+      memset(&a, 0, sizeof a);
+      a.v0 = buf<double>(G->v0);
+      a.v = last ? buf<double>(G->v) : nullptr;
+      a.n0 = G->g.n[0];
+      a.n1 = G->g.n[1];
+      a.plane = (int64_t)G->g.n[2] * G->g.n[3];
+      a.lo0 = G->g.lo[0];
+      a.h0 = G->h[0];
+      a.lo1 = G->g.lo[1];
+      a.h1 = G->h[1];
+      a.m = cnt;
+      a.combine = o0 > 0;
+      for (int i = 0; i < cnt; ++i) {
+        a.cx[i] = cx[o0 + i];
+        a.cy[i] = cy[o0 + i];
+        a.r[i] = r[o0 + i];
+      }
+      HJ_HIP(hj::launch_cylinders(a, S(G)));
+    }
+  }
+  G->has_target = true;
+  return HJ_OK;
+}
+
+hj_status hj_get_cfl_dt(hj_grid *G, double *dt) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!dt) return fail(HJ_ERR_INVALID_ARG, "null output");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if ((st = ensure_dt(G)) != HJ_OK) return st;
+  *dt = G->dt_cfl;
+  return HJ_OK;
+}
+
+hj_status hj_get_alpha_max(hj_grid *G, double alpha_max[4]) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!alpha_max) return fail(HJ_ERR_INVALID_ARG, "null output");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if ((st = ensure_dt(G)) != HJ_OK) return st;
+  for (int d = 0; d < 4; ++d) alpha_max[d] = G->amax[d];
+  return HJ_OK;
+}
+
+hj_status hj_solve_brt(hj_grid *G, double horizon, hj_solve_info *info) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!isfinite(horizon) || horizon < 0) return fail(HJ_ERR_INVALID_ARG, "horizon must be finite and >= 0");
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if ((st = ensure_dt(G)) != HJ_OK) return st;
+  // fixed horizon: n = ceil(T / dt) steps, the last shortened (a zero CFL
+  // sum, i.e. nothing moves, makes one step of the whole horizon)
+  double dt = isinf(G->dt_cfl) ? horizon : G->dt_cfl;
+  int64_t n = 0;
+  double dt_last = 0.0;
+  if (horizon > 0.0) {
+    n = (int64_t)ceil(horizon / dt);
+    if (n < 1) n = 1;
+    dt_last = horizon - (double)(n - 1) * dt;
+  }
+  if ((st = reset_value(G)) != HJ_OK) return st;
+  bool timed = G->profiling && n > 0;
+  hipEvent_t ev_b = nullptr, ev_e = nullptr;
+  if (timed) {
+    if ((st = next_events(G, &ev_b, &ev_e)) != HJ_OK) return st;
+    HJ_HIP(hipEventRecord(ev_b, S(G)));
+  }
+  int64_t launches = 0;
+  for (int64_t k = 0; k < n; ++k)
+    if ((st = step_once(G, k + 1 < n ? dt : dt_last, &launches)) != HJ_OK) return st;
+  if (timed) {
+    HJ_HIP(hipEventRecord(ev_e, S(G)));
+    G->prof.solves += 1;
+    G->prof.step_launches += launches;
+  }
+  if (info) {
+    info->steps = n;
+    info->dt = dt;
+    info->dt_last = dt_last;
+    info->t_final = horizon;
+  }
+  return HJ_OK;
+}
+
+hj_status hj_step(hj_grid *G, double dt, double *dt_taken) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if (isnan(dt) || isinf(dt)) return fail(HJ_ERR_INVALID_ARG, "dt must be finite");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if (dt <= 0) {
+    if ((st = ensure_dt(G)) != HJ_OK) return st;
+    if (isinf(G->dt_cfl)) return fail(HJ_ERR_INVALID_ARG, "nothing moves: the CFL step is unbounded, pass dt > 0");
+    dt = G->dt_cfl;
+  }
+  int64_t launches = 0;
+  if ((st = step_once(G, dt, &launches)) != HJ_OK) return st;
+  if (dt_taken) *dt_taken = dt;
+  return HJ_OK;
+}
+
+hj_status hj_get_value(hj_grid *G, void *out, int32_t dtype, int32_t where) {
+  hj_status st = check_handle(G);
+  if (st == HJ_OK) st = check_array(out, dtype, where);
+  if (st != HJ_OK) return st;
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  return export_array(G, G->v, out, dtype, where);
+}
+
+hj_status hj_get_target(hj_grid *G, void *out, int32_t dtype, int32_t where) {
+  hj_status st = check_handle(G);
+  if (st == HJ_OK) st = check_array(out, dtype, where);
+  if (st != HJ_OK) return st;
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  return export_array(G, G->v0, out, dtype, where);
+}
+
+hj_status hj_set_value(hj_grid *G, const void *v, int32_t dtype, int32_t where) {
+  hj_status st = check_handle(G);
+  if (st == HJ_OK) st = check_array(v, dtype, where);
+  if (st != HJ_OK) return st;
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  bool ok = false;
+  if ((st = all_finite(G, v, dtype, where, &ok)) != HJ_OK) return st;
+  if (!ok) return fail(HJ_ERR_NONFINITE, "value contains NaN or infinity");
+  return import_array(G, G->v, v, dtype, where);
+}
+
+hj_status hj_get_num_points(hj_grid *G, int64_t *n) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!n) return fail(HJ_ERR_INVALID_ARG, "null output");
+  *n = G->npts;
+  return HJ_OK;
+}
+
+hj_status hj_set_profiling(hj_grid *G, int32_t enable) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if ((st = fold_events(G)) != HJ_OK) return st;
+  G->profiling = enable != 0;
+  G->prof = {0, 0, 0.0};
+  return HJ_OK;
+}
+
+hj_status hj_get_profile(hj_grid *G, hj_profile *out) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if ((st = fold_events(G)) != HJ_OK) return st;
+  *out = G->prof;
+  return HJ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// hj_internal.h -- kernel argument blocks and launcher declarations shared by
+// the ABI layer (hj_abi.hip) and the kernels (hj_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hj {
+
+enum Deriv { kUpwind1 = 0, kEno2 = 1 };
+
+// How a stage combines its Lax-Friedrichs right-hand side L(Vs):
+//   kPlain: out = Vs + dt L(Vs)                 (Euler; TVD-RK2 stage 1)
+//   kAverage: out = (Vn + Vs + dt L(Vs)) / 2     (TVD-RK2 stage 2)
+enum StageMode { kPlain = 0, kAverage = 1 };
+
+// The Hamiltonian of every supported dynamics, written in separable form
+// (see the kernels for the derivation):
+//   H(z, p) = bx(v,th) px + by(v,th) py + bv pv + bth pth
+//           + sum_d sig_d |p_d| + sig_ball |p_S|_2
+// and the dissipation coefficients alpha = (ax(v,th), ay(v,th), av, ath).
+// Per-(v, theta) values live in a table of four arrays (bx, by, ax, ay), each
+// Nv * Ntheta long, index k * Ntheta + l.
+template <typename T>
+struct StageArgs {
+  const T *vs;   // stencil input: V^n (Euler, stage 1) or V^1 (stage 2)
+  const T *vn;   // V^n for the stage-2 average (unused in kPlain)
+  const T *v0;   // target, for the clamp (unused without clamp)
+  T *out;
+  const T *lut;  // bx | by | ax | ay, each n[2] * n[3] values
+  int32_t n[4];
+  int64_t st[4];  // C-order strides of the external layout
+  uint32_t periodic_mask;
+  T inv_h[4];
+  T bv, bth, av, ath;
+  T sig[4];
+  T sig_ball;
+  uint32_t ball_mask;
+  T dt;
+  int32_t mode;
+  int32_t clamp;
+  int64_t npts;
+};
+
+constexpr int kMaxCylindersPerLaunch = 32;
+
+template <typename T>
+struct CylinderArgs {
+  T *v0;
+  T *v;  // also written (V := V0); may equal nullptr
+  int32_t n0, n1;
+  int64_t plane;  // nodes per (x, y) pair: n[2] * n[3]
+  T lo0, h0, lo1, h1;
+  int32_t m;
+  int32_t combine;  // 0: overwrite, 1: min with the existing V0
+  T cx[kMaxCylindersPerLaunch], cy[kMaxCylindersPerLaunch], r[kMaxCylindersPerLaunch];
+};
+
+template <typename T>
+hipError_t launch_stage(const StageArgs<T> &a, int deriv, bool ball, hipStream_t s);
+
+template <typename T>
+hipError_t launch_cylinders(const CylinderArgs<T> &a, hipStream_t s);
+
+// alpha_max[0..1] = max over the table of ax, ay (FP64); [2], [3] = av, ath.
+hipError_t launch_alpha_max(const double *ax, const double *ay, int64_t m, double av, double ath,
+                            double *alpha_max, hipStream_t s);
+
+// dst[i] = (To)src[i]
+template <typename To, typename Ti>
+hipError_t launch_cast(To *dst, const Ti *src, int64_t n, hipStream_t s);
+
+template <typename T>
+hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s);
+
+// flag[0] = 1 if any of the n values is NaN or infinite (flag cleared first).
+template <typename T>
+hipError_t launch_nonfinite(const T *src, int64_t n, int32_t *flag, hipStream_t s);
+
+}  // namespace hj

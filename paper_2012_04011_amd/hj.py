@@ -1,0 +1,361 @@
+"""Python binding of the C ABI in ``include/hj.h`` (ctypes; argument
+marshalling only -- every step of the solve runs in the gfx950 kernels of
+``libhj.so``).
+
+The functions keep the C names (``hj_grid_create`` ...).  Problem
+descriptions are the dicts of ``paper_2012_04011_amd.workloads``.  Arrays are
+numpy arrays (host) or torch tensors on the GPU (device; passed by
+``data_ptr()``); streams are torch streams or raw ``hipStream_t`` integers.
+
+There is no fallback: if ``libhj.so`` is missing, loading fails with an
+error that says how to build it.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhj.so")
+
+HJ_OK, HJ_ERR_INVALID_ARG, HJ_ERR_OUT_OF_MEMORY, HJ_ERR_DEVICE, HJ_ERR_NOT_READY, HJ_ERR_NONFINITE, \
+    HJ_ERR_UNSUPPORTED = range(7)
+HJ_F32, HJ_F64 = 0, 1
+HJ_HOST, HJ_DEVICE = 0, 1
+HJ_DYN_CAR4D, HJ_DYN_DRIFT_INPUT = 0, 1
+HJ_UPWIND1, HJ_ENO2 = 0, 1
+HJ_EULER, HJ_TVD_RK2 = 0, 1
+HJ_CLAMP_NONE, HJ_CLAMP_MIN_V0 = 0, 1
+HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
+HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
+
+STATUS_NAMES = {0: "HJ_OK", 1: "HJ_ERR_INVALID_ARG", 2: "HJ_ERR_OUT_OF_MEMORY", 3: "HJ_ERR_DEVICE",
+                4: "HJ_ERR_NOT_READY", 5: "HJ_ERR_NONFINITE", 6: "HJ_ERR_UNSUPPORTED"}
+
+EXPORTED = [
+    "hj_grid_create", "hj_grid_destroy", "hj_set_target", "hj_set_target_cylinders", "hj_solve_brt",
+    "hj_step", "hj_get_cfl_dt", "hj_get_alpha_max", "hj_get_value", "hj_get_target", "hj_set_value",
+    "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_last_error", "hj_version",
+]
+
+
+class HJError(RuntimeError):
+    def __init__(self, status: int, func: str, message: str):
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class hj_grid_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 4), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
+                ("periodic_mask", ctypes.c_uint32)]
+
+
+class hj_dynamics_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("a_max", ctypes.c_double), ("w_max", ctypes.c_double),
+                ("d_max", ctypes.c_double * 2), ("drift", ctypes.c_double * 4), ("in_speed", ctypes.c_double),
+                ("in_axes_mask", ctypes.c_uint32), ("in_norm", ctypes.c_int32), ("in_role", ctypes.c_int32)]
+
+
+class hj_scheme_desc(ctypes.Structure):
+    _fields_ = [("deriv", ctypes.c_int32), ("integrator", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("clamp", ctypes.c_int32), ("cfl", ctypes.c_double)]
+
+
+class hj_solve_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("dt", ctypes.c_double), ("dt_last", ctypes.c_double),
+                ("t_final", ctypes.c_double)]
+
+
+class hj_profile(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int64), ("step_launches", ctypes.c_int64), ("loop_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libhj.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is not built; run `python -m paper_2012_04011_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "hj_grid_create": [P(hj_grid_desc), P(hj_dynamics_desc), P(hj_scheme_desc), vp, P(vp)],
+        "hj_grid_destroy": [vp],
+        "hj_set_target": [vp, vp, i32, i32],
+        "hj_set_target_cylinders": [vp, P(dbl), P(dbl), P(dbl), i32],
+        "hj_solve_brt": [vp, dbl, P(hj_solve_info)],
+        "hj_step": [vp, dbl, P(dbl)],
+        "hj_get_cfl_dt": [vp, P(dbl)],
+        "hj_get_alpha_max": [vp, P(dbl)],
+        "hj_get_value": [vp, vp, i32, i32],
+        "hj_get_target": [vp, vp, i32, i32],
+        "hj_set_value": [vp, vp, i32, i32],
+        "hj_get_num_points": [vp, P(i64)],
+        "hj_set_profiling": [vp, i32],
+        "hj_get_profile": [vp, P(hj_profile)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.hj_last_error.restype = ctypes.c_char_p
+    lib.hj_last_error.argtypes = []
+    lib.hj_version.restype = ctypes.c_char_p
+    lib.hj_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status: int, func: str):
+    if status != HJ_OK:
+        raise HJError(status, func, _lib.hj_last_error().decode())
+
+
+# ----------------------------------------------------------- marshalling ---
+
+_KIND = {"car4d": HJ_DYN_CAR4D, "drift_input": HJ_DYN_DRIFT_INPUT}
+_DERIV = {"upwind1": HJ_UPWIND1, "eno2": HJ_ENO2}
+_INTEG = {"euler": HJ_EULER, "rk2": HJ_TVD_RK2}
+_NORM = {"box": HJ_NORM_BOX, "ball": HJ_NORM_BALL}
+_ROLE = {"max": HJ_INPUT_MAXIMIZES, "min": HJ_INPUT_MINIMIZES}
+_PREC = {"f32": HJ_F32, "f64": HJ_F64}
+
+
+def grid_desc(grid: dict) -> hj_grid_desc:
+    s = hj_grid_desc()
+    for d in range(4):
+        s.n[d], s.lo[d], s.hi[d] = int(grid["n"][d]), float(grid["lo"][d]), float(grid["hi"][d])
+    s.periodic_mask = int(grid.get("periodic_mask", 0))
+    return s
+
+
+def dynamics_desc(dyn: dict) -> hj_dynamics_desc:
+    s = hj_dynamics_desc()
+    s.kind = _KIND[dyn["kind"]]
+    s.a_max, s.w_max = float(dyn.get("a_max", 0.0)), float(dyn.get("w_max", 0.0))
+    dm = dyn.get("d_max", (0.0, 0.0))
+    s.d_max[0], s.d_max[1] = float(dm[0]), float(dm[1])
+    for d, x in enumerate(dyn.get("drift", (0.0,) * 4)):
+        s.drift[d] = float(x)
+    s.in_speed = float(dyn.get("in_speed", 0.0))
+    s.in_axes_mask = sum(1 << int(a) for a in dyn.get("in_axes", ()))
+    s.in_norm = _NORM[dyn.get("in_norm", "box")]
+    s.in_role = _ROLE[dyn.get("in_role", "max")]
+    return s
+
+
+def scheme_desc(scheme: dict, precision: str) -> hj_scheme_desc:
+    s = hj_scheme_desc()
+    s.deriv = _DERIV[scheme["deriv"]]
+    s.integrator = _INTEG[scheme["integrator"]]
+    s.precision = _PREC[precision]
+    s.clamp = HJ_CLAMP_MIN_V0 if scheme.get("clamp", True) else HJ_CLAMP_NONE
+    s.cfl = float(scheme.get("cfl", 0.8))
+    return s
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _array_arg(a):
+    """(pointer, dtype code, where code) of a numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        dt = {np.dtype(np.float32): HJ_F32, np.dtype(np.float64): HJ_F64}.get(a.dtype)
+        if dt is None:
+            raise TypeError(f"unsupported dtype {a.dtype}")
+        return a.ctypes.data, dt, HJ_HOST
+    import torch
+
+    if not isinstance(a, torch.Tensor):
+        raise TypeError("expected a numpy array or a torch tensor")
+    if not a.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    dt = {torch.float32: HJ_F32, torch.float64: HJ_F64}.get(a.dtype)
+    if dt is None:
+        raise TypeError(f"unsupported dtype {a.dtype}")
+    if a.device.type == "cuda":
+        return a.data_ptr(), dt, HJ_DEVICE
+    return a.data_ptr(), dt, HJ_HOST
+
+
+# --------------------------------------------------------- C-named calls ---
+
+
+def hj_grid_create(grid: dict, dyn: dict, scheme: dict, precision: str = "f32", stream=None) -> int:
+    lib = load_library()
+    g, d, s = grid_desc(grid), dynamics_desc(dyn), scheme_desc(scheme, precision)
+    out = ctypes.c_void_p()
+    _check(lib.hj_grid_create(ctypes.byref(g), ctypes.byref(d), ctypes.byref(s), _stream_handle(stream),
+                              ctypes.byref(out)), "hj_grid_create")
+    return out.value
+
+
+def hj_grid_destroy(h: int) -> None:
+    _check(load_library().hj_grid_destroy(h), "hj_grid_destroy")
+
+
+def hj_set_target(h: int, v0) -> None:
+    ptr, dt, where = _array_arg(v0)
+    _check(load_library().hj_set_target(h, ptr, dt, where), "hj_set_target")
+
+
+def hj_set_target_cylinders(h: int, cx, cy, r) -> None:
+    cx, cy, r = (np.ascontiguousarray(a, dtype=np.float64) for a in (cx, cy, r))
+    if not (len(cx) == len(cy) == len(r)):
+        raise ValueError("cx, cy, r must have the same length")
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().hj_set_target_cylinders(h, cx.ctypes.data_as(dp), cy.ctypes.data_as(dp),
+                                                  r.ctypes.data_as(dp), len(cx)), "hj_set_target_cylinders")
+
+
+def hj_solve_brt(h: int, horizon: float) -> dict:
+    info = hj_solve_info()
+    _check(load_library().hj_solve_brt(h, float(horizon), ctypes.byref(info)), "hj_solve_brt")
+    return {"steps": info.steps, "dt": info.dt, "dt_last": info.dt_last, "t_final": info.t_final}
+
+
+def hj_step(h: int, dt: float = 0.0) -> float:
+    taken = ctypes.c_double()
+    _check(load_library().hj_step(h, float(dt), ctypes.byref(taken)), "hj_step")
+    return taken.value
+
+
+def hj_get_cfl_dt(h: int) -> float:
+    dt = ctypes.c_double()
+    _check(load_library().hj_get_cfl_dt(h, ctypes.byref(dt)), "hj_get_cfl_dt")
+    return dt.value
+
+
+def hj_get_alpha_max(h: int) -> np.ndarray:
+    out = (ctypes.c_double * 4)()
+    _check(load_library().hj_get_alpha_max(h, out), "hj_get_alpha_max")
+    return np.array(out[:])
+
+
+def hj_get_value(h: int, out) -> None:
+    ptr, dt, where = _array_arg(out)
+    _check(load_library().hj_get_value(h, ptr, dt, where), "hj_get_value")
+
+
+def hj_get_target(h: int, out) -> None:
+    ptr, dt, where = _array_arg(out)
+    _check(load_library().hj_get_target(h, ptr, dt, where), "hj_get_target")
+
+
+def hj_set_value(h: int, v) -> None:
+    ptr, dt, where = _array_arg(v)
+    _check(load_library().hj_set_value(h, ptr, dt, where), "hj_set_value")
+
+
+def hj_get_num_points(h: int) -> int:
+    n = ctypes.c_int64()
+    _check(load_library().hj_get_num_points(h, ctypes.byref(n)), "hj_get_num_points")
+    return n.value
+
+
+def hj_set_profiling(h: int, enable: bool) -> None:
+    _check(load_library().hj_set_profiling(h, 1 if enable else 0), "hj_set_profiling")
+
+
+def hj_get_profile(h: int) -> dict:
+    p = hj_profile()
+    _check(load_library().hj_get_profile(h, ctypes.byref(p)), "hj_get_profile")
+    return {"solves": p.solves, "step_launches": p.step_launches, "loop_ms": p.loop_ms}
+
+
+def hj_last_error() -> str:
+    return load_library().hj_last_error().decode()
+
+
+def hj_version() -> str:
+    return load_library().hj_version().decode()
+
+
+# ------------------------------------------------------------ convenience ---
+
+
+class Grid:
+    """Owning wrapper of an ``hj_grid`` handle (same operations as the C
+    calls)."""
+
+    def __init__(self, grid: dict, dyn: dict, scheme: dict, precision: str = "f32", stream=None):
+        self.grid, self.dyn, self.scheme, self.precision = grid, dyn, scheme, precision
+        self.shape = tuple(int(x) for x in grid["n"])
+        self.handle = hj_grid_create(grid, dyn, scheme, precision, stream)
+
+    def close(self):
+        if self.handle:
+            hj_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_target(self, v0):
+        hj_set_target(self.handle, v0)
+
+    def set_target_cylinders(self, cx, cy, r):
+        hj_set_target_cylinders(self.handle, cx, cy, r)
+
+    def solve_brt(self, horizon: float) -> dict:
+        return hj_solve_brt(self.handle, horizon)
+
+    def step(self, dt: float = 0.0) -> float:
+        return hj_step(self.handle, dt)
+
+    def cfl_dt(self) -> float:
+        return hj_get_cfl_dt(self.handle)
+
+    def alpha_max(self) -> np.ndarray:
+        return hj_get_alpha_max(self.handle)
+
+    def value(self, dtype=np.float64) -> np.ndarray:
+        out = np.empty(self.shape, dtype=dtype)
+        hj_get_value(self.handle, out)
+        return out
+
+    def target(self, dtype=np.float64) -> np.ndarray:
+        out = np.empty(self.shape, dtype=dtype)
+        hj_get_target(self.handle, out)
+        return out
+
+    def get_value(self, out):
+        hj_get_value(self.handle, out)
+
+    def set_value(self, v):
+        hj_set_value(self.handle, v)
+
+    @property
+    def num_points(self) -> int:
+        return hj_get_num_points(self.handle)
+
+    def set_profiling(self, enable: bool):
+        hj_set_profiling(self.handle, enable)
+
+    def profile(self) -> dict:
+        return hj_get_profile(self.handle)
