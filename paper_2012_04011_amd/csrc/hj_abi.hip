@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -54,6 +55,9 @@ struct hj_grid {
   void *w1 = nullptr;   // RK stage value V^1
   void *w2 = nullptr;   // next value (swapped with v after a step)
   void *lut = nullptr;  // bx | by | ax | ay in the scheme's precision
+  void *coef = nullptr;  // kp_x | km_x | kp_y | km_y (streaming kernel)
+  bool stream_ok = false;  // shape suits the streaming kernel
+  int x_chunks = 1;
   double *lut64 = nullptr;  // ax | ay in FP64 for the CFL reduction
   double *amax_dev = nullptr;
   int32_t *flag_dev = nullptr;
@@ -186,6 +190,36 @@ void build_table(hj_grid *G, std::vector<double> &tab) {
   }
 }
 
+// Streaming-kernel coefficients from the FP64 table: per axis
+// kp = (b + alpha) / (2h), km = (b - alpha) / (2h).
+void build_coef(hj_grid *G, const std::vector<double> &tab, std::vector<double> &coef) {
+  int64_t m = (int64_t)G->g.n[2] * G->g.n[3];
+  coef.assign(4 * m, 0.0);
+  for (int64_t c = 0; c < m; ++c) {
+    double bx = tab[c], by = tab[m + c], ax = tab[2 * m + c], ay = tab[3 * m + c];
+    coef[c] = (bx + ax) / (2.0 * G->h[0]);
+    coef[m + c] = (bx - ax) / (2.0 * G->h[0]);
+    coef[2 * m + c] = (by + ay) / (2.0 * G->h[1]);
+    coef[3 * m + c] = (by - ay) / (2.0 * G->h[1]);
+  }
+}
+
+// Number of x chunks the streaming kernel splits the sweep into: enough
+// blocks to give every CU about five (256 CUs), but at least 8 planes per
+// chunk (each chunk re-reads up to 4 planes to start its ring).
+int choose_x_chunks(int nx, int64_t slab_runs) {
+  const char *env = getenv("HJ_X_CHUNKS");
+  if (env && atoi(env) > 0) {
+    int c = atoi(env);
+    return c > nx ? nx : c;
+  }
+  int64_t bpc = (slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  int64_t want = (1280 + bpc - 1) / bpc;
+  int64_t cap = nx / 8 > 1 ? nx / 8 : 1;
+  int64_t c = want < cap ? want : cap;
+  return c < 1 ? 1 : (int)c;
+}
+
 hipStream_t S(hj_grid *g) { return g->stream; }
 
 template <typename T>
@@ -194,7 +228,7 @@ T *buf(void *p) {
 }
 
 void free_all(hj_grid *G) {
-  void *ptrs[] = {G->v0, G->v, G->w1, G->w2, G->lut, G->lut64, G->amax_dev, G->flag_dev};
+  void *ptrs[] = {G->v0, G->v, G->w1, G->w2, G->lut, G->coef, G->lut64, G->amax_dev, G->flag_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (G->amax_host) (void)hipHostFree(G->amax_host);
@@ -387,34 +421,79 @@ hj::StageArgs<T> stage_args(hj_grid *G) {
   return a;
 }
 
+template <typename T>
+hj::StreamArgs<T> stream_args(hj_grid *G) {
+  hj::StreamArgs<T> a;
+  memset(&a, 0, sizeof a);
+  const hj_grid_desc &g = G->g;
+  const int run = hj::stream_run<T>();
+  for (int d = 0; d < 4; ++d) a.n[d] = g.n[d];
+  a.periodic_mask = g.periodic_mask;
+  a.plane = g.n[1] * g.n[2] * g.n[3];
+  a.row = g.n[2] * g.n[3];
+  a.runs_per_row = g.n[3] / run;
+  a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
+  a.blocks_per_chunk = (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  a.n_chunks = G->x_chunks;
+  a.chunk_len = (g.n[0] + a.n_chunks - 1) / a.n_chunks;
+  a.n_chunks = (g.n[0] + a.chunk_len - 1) / a.chunk_len;
+  a.coef = buf<const T>(G->coef);
+  // uniform v and theta coefficients: b = bv / bth, alpha = av / ath
+  a.kp_v = (T)((G->bv + G->av) / (2.0 * G->h[2]));
+  a.km_v = (T)((G->bv - G->av) / (2.0 * G->h[2]));
+  a.kp_th = (T)((G->bth + G->ath) / (2.0 * G->h[3]));
+  a.km_th = (T)((G->bth - G->ath) / (2.0 * G->h[3]));
+  for (int d = 0; d < 4; ++d) {
+    a.sg[d] = (T)(G->sig[d] / (2.0 * G->h[d]));
+    a.half_inv_h[d] = (T)(1.0 / (2.0 * G->h[d]));
+  }
+  a.sig_ball = (T)G->sig_ball;
+  a.ball_mask = G->ball_mask;
+  return a;
+}
+
+template <typename T>
+hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mode, int clamp, double dt) {
+  bool ball = G->ball_mask != 0;
+  if (G->stream_ok) {
+    hj::StreamArgs<T> a = stream_args<T>(G);
+    a.vs = vs;
+    a.vn = vn;
+    a.v0 = buf<const T>(G->v0);
+    a.out = out;
+    a.mode = mode;
+    a.clamp = clamp;
+    a.dt = (T)dt;
+    HJ_HIP(hj::launch_stream(a, G->sch.deriv, ball, S(G)));
+    return HJ_OK;
+  }
+  hj::StageArgs<T> a = stage_args<T>(G);
+  a.vs = vs;
+  a.vn = vn;
+  a.v0 = buf<const T>(G->v0);
+  a.out = out;
+  a.mode = mode;
+  a.clamp = clamp;
+  a.dt = (T)dt;
+  HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
+  return HJ_OK;
+}
+
 // One full step of length dt: Euler (one stage) or TVD-RK2 (two stages),
 // clamp fused into the last stage.  Swaps v and w2.
 template <typename T>
 hj_status enqueue_step(hj_grid *G, double dt, int64_t *launches) {
-  hj::StageArgs<T> a = stage_args<T>(G);
-  a.dt = (T)dt;
-  a.v0 = buf<const T>(G->v0);
-  bool ball = G->ball_mask != 0;
+  hj_status st;
   int clamp = G->sch.clamp == HJ_CLAMP_MIN_V0;
   if (G->sch.integrator == HJ_EULER) {
-    a.vs = buf<const T>(G->v);
-    a.out = buf<T>(G->w2);
-    a.mode = hj::kPlain;
-    a.clamp = clamp;
-    HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
+    st = launch_one_stage<T>(G, buf<const T>(G->v), nullptr, buf<T>(G->w2), hj::kPlain, clamp, dt);
+    if (st != HJ_OK) return st;
     *launches += 1;
   } else {
-    a.vs = buf<const T>(G->v);
-    a.out = buf<T>(G->w1);
-    a.mode = hj::kPlain;
-    a.clamp = 0;
-    HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
-    a.vs = buf<const T>(G->w1);
-    a.vn = buf<const T>(G->v);
-    a.out = buf<T>(G->w2);
-    a.mode = hj::kAverage;
-    a.clamp = clamp;
-    HJ_HIP(hj::launch_stage(a, G->sch.deriv, ball, S(G)));
+    st = launch_one_stage<T>(G, buf<const T>(G->v), nullptr, buf<T>(G->w1), hj::kPlain, 0, dt);
+    if (st != HJ_OK) return st;
+    st = launch_one_stage<T>(G, buf<const T>(G->w1), buf<const T>(G->v), buf<T>(G->w2), hj::kAverage, clamp, dt);
+    if (st != HJ_OK) return st;
     *launches += 2;
   }
   void *t = G->v;
@@ -455,9 +534,16 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   G->stream = static_cast<hipStream_t>(hip_stream);
   G->npts = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * grid->n[3];
   G->elem = scheme->precision == HJ_F32 ? 4 : 8;
-  std::vector<double> tab;
+  std::vector<double> tab, coef;
   build_table(G, tab);
+  build_coef(G, tab, coef);
   int64_t m = (int64_t)grid->n[2] * grid->n[3];
+  {
+    int run = scheme->precision == HJ_F32 ? hj::stream_run<float>() : hj::stream_run<double>();
+    G->stream_ok = bit(grid->periodic_mask, 3) && grid->n[3] % run == 0;
+    int64_t slab_runs = (int64_t)grid->n[1] * grid->n[2] * (grid->n[3] / run);
+    G->x_chunks = choose_x_chunks(grid->n[0], slab_runs);
+  }
 
   hipError_t e = hipGetDevice(&G->device);
   size_t bytes = G->npts * G->elem;
@@ -467,6 +553,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   if (e == hipSuccess) e = hipMalloc(&G->w2, bytes);
   if (e == hipSuccess && rk2) e = hipMalloc(&G->w1, bytes);
   if (e == hipSuccess) e = hipMalloc(&G->lut, 4 * m * G->elem);
+  if (e == hipSuccess) e = hipMalloc(&G->coef, 4 * m * G->elem);
   if (e == hipSuccess) e = hipMalloc(&G->lut64, 2 * m * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&G->amax_dev, 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&G->flag_dev, sizeof(int32_t));
@@ -478,11 +565,16 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     if (e == hipSuccess) {
       if (G->elem == 8) {
         e = hipMemcpyAsync(G->lut, tab.data(), 4 * m * 8, hipMemcpyHostToDevice, G->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(G->coef, coef.data(), 4 * m * 8, hipMemcpyHostToDevice, G->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
       } else {
-        std::vector<float> t32(4 * m);
-        for (int64_t i = 0; i < 4 * m; ++i) t32[i] = (float)tab[i];
+        std::vector<float> t32(4 * m), c32(4 * m);
+        for (int64_t i = 0; i < 4 * m; ++i) {
+          t32[i] = (float)tab[i];
+          c32[i] = (float)coef[i];
+        }
         e = hipMemcpyAsync(G->lut, t32.data(), 4 * m * 4, hipMemcpyHostToDevice, G->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(G->coef, c32.data(), 4 * m * 4, hipMemcpyHostToDevice, G->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
       }
     }

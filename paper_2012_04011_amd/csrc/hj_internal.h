@@ -42,6 +42,51 @@ struct StageArgs {
   int64_t npts;
 };
 
+// The streaming stage kernel (see hj_kernels.hip).  Each thread owns a run
+// of R consecutive theta nodes at one (y, v) and sweeps a chunk of x planes.
+// The right-hand side is written per axis as
+//   L_d = kp_d p+_d + km_d p-_d + sg_d |p+_d + p-_d|
+// with unscaled one-sided differences p' = h p:
+//   kp = (b + alpha) / (2h), km = (b - alpha) / (2h), sg = sig / (2h).
+// kp, km of x and y vary with (v, theta) (table `coef`: kp_x | km_x | kp_y |
+// km_y, each n[2] * n[3]); those of v and theta are uniform.
+template <typename T>
+struct StreamArgs {
+  const T *vs;
+  const T *vn;
+  const T *v0;
+  T *out;
+  const T *coef;
+  int32_t n[4];
+  uint32_t periodic_mask;
+  int32_t plane;           // n[1] * n[2] * n[3]: stride of x
+  int32_t row;             // n[2] * n[3]: stride of y
+  int32_t runs_per_row;    // n[3] / R
+  int32_t slab_runs;       // n[1] * n[2] * runs_per_row
+  int32_t blocks_per_chunk;
+  int32_t chunk_len;       // x planes per block
+  int32_t n_chunks;
+  T kp_v, km_v, kp_th, km_th;
+  T sg[4];
+  T half_inv_h[4];  // 1 / (2 h_d), for the ball term
+  T sig_ball;
+  uint32_t ball_mask;
+  T dt;
+  int32_t mode;
+  int32_t clamp;
+};
+
+constexpr int kStreamBlock = 256;
+
+// Run length of the streaming kernel per precision (16-byte vector loads).
+template <typename T>
+constexpr int stream_run() {
+  return sizeof(T) == 4 ? 4 : 2;
+}
+
+template <typename T>
+hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s);
+
 constexpr int kMaxCylindersPerLaunch = 32;
 
 template <typename T>

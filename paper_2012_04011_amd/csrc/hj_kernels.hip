@@ -164,6 +164,353 @@ __global__ __launch_bounds__(256) void stage_generic(StageArgs<T> a) {
   a.out[p] = finish(a, p, v[p], L);
 }
 
+// ---------------------------------------------------------------------------
+// Streaming stage kernel.
+//
+// Thread r of the grid owns a run of R consecutive theta nodes at one (y, v)
+// and sweeps a chunk of x planes in order.  Along x it keeps a register ring
+// of the stencil quantities (V_X, V_X+1, the first difference D_X-1/2, the
+// second difference Q_X and the ENO choice m_X-1/2), so each new plane costs
+// one 16-byte load and one new difference / second difference / choice.
+// Along theta the run shares its interface quantities between neighbouring
+// nodes (R + 1 first differences and choices for R nodes); the two halo
+// nodes on each side are 2-element vector loads (theta wraps).  Along v and y
+// the four neighbouring runs are 16-byte loads that the neighbouring threads
+// brought into the caches.  Blocks are numbered so that each XCD sweeps one
+// contiguous range of runs for one x chunk (their v and y neighbours then sit
+// in that XCD's L2), and the pointwise streams (V^n, V0, the output) use
+// non-temporal accesses so that they do not push V out of L2.
+// ---------------------------------------------------------------------------
+
+template <typename T, int R>
+struct VecT;
+template <>
+struct VecT<float, 4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct VecT<double, 2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+struct Vec2T {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T, int R>
+__device__ inline void load_run(const T *__restrict__ p, T (&r)[R]) {
+  typedef typename VecT<T, R>::type V;
+  V x = *reinterpret_cast<const V *>(p);
+#pragma unroll
+  for (int i = 0; i < R; ++i) r[i] = x[i];
+}
+
+template <typename T, int R>
+__device__ inline void load_run_nt(const T *__restrict__ p, T (&r)[R]) {
+  typedef typename VecT<T, R>::type V;
+  V x = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+  for (int i = 0; i < R; ++i) r[i] = x[i];
+}
+
+template <typename T, int R>
+__device__ inline void store_run_nt(T *__restrict__ p, const T (&r)[R]) {
+  typedef typename VecT<T, R>::type V;
+  V x;
+#pragma unroll
+  for (int i = 0; i < R; ++i) x[i] = r[i];
+  __builtin_nontemporal_store(x, reinterpret_cast<V *>(p));
+}
+
+template <typename T>
+__device__ inline void load_pair(const T *__restrict__ p, T &a, T &b) {
+  typedef typename Vec2T<T>::type V;
+  V x = *reinterpret_cast<const V *>(p);
+  a = x[0];
+  b = x[1];
+}
+
+// ENO choice between two second differences: the smaller magnitude, the
+// first one on a tie.  m_{k+1/2} = choose(Q_k, Q_{k+1}) is both the
+// correction of p+ at node k and of p- at node k+1.
+template <typename T>
+__device__ inline T choose(T a, T b) {
+  return fabs(a) <= fabs(b) ? a : b;
+}
+
+// Unscaled one-sided differences (h p-, h p+) from a five-node window.
+template <typename T, int DERIV>
+__device__ inline void window_diffs(T w0, T w1, T w2, T w3, T w4, T &pm, T &pp) {
+  if (DERIV == kUpwind1) {
+    pm = w2 - w1;
+    pp = w3 - w2;
+  } else {
+    T ql = second_diff(w0, w1, w2);
+    T qm = second_diff(w1, w2, w3);
+    T qr = second_diff(w2, w3, w4);
+    pm = (w2 - w1) + T(0.5) * choose(ql, qm);
+    pp = (w3 - w2) - T(0.5) * choose(qm, qr);
+  }
+}
+
+// L_d += kp p+ + km p- + sg |p+ + p-| (+ the axis' share of the ball term).
+template <typename T, bool SG, bool BALL>
+__device__ inline void accumulate(T &L, T &b2, T kp, T km, T sg, T pp, T pm, bool in_ball, T hih) {
+  L = fma(kp, pp, L);
+  L = fma(km, pm, L);
+  if (SG || BALL) {
+    T s = pp + pm;
+    if (SG) L = fma(sg, fabs(s), L);
+    if (BALL && in_ball) {
+      T pb = s * hih;
+      b2 = fma(pb, pb, b2);
+    }
+  }
+}
+
+// Ghost values of a non-periodic axis from the loaded window (neighbour runs
+// at -2, -1, +1, +2 were loaded with clamped indices): linear extrapolation
+// from the two end nodes, ghost k layers out = V_end + k (V_end - V_next).
+template <typename T, int DERIV>
+__device__ inline void fix_ghosts(int i, int n, T c, T &m2, T &m1, T &p1, T &p2) {
+  if (i < 2) {
+    if (i == 0) {
+      T d = c - p1;
+      m1 = c + d;
+      if (DERIV == kEno2) m2 = c + T(2) * d;
+    } else if (DERIV == kEno2) {
+      T d = m1 - c;
+      m2 = m1 + d;
+    }
+  }
+  if (i >= n - 2) {
+    if (i == n - 1) {
+      T d = c - m1;
+      p1 = c + d;
+      if (DERIV == kEno2) p2 = c + T(2) * d;
+    } else if (DERIV == kEno2) {
+      T d = p1 - c;
+      p2 = p1 + d;
+    }
+  }
+}
+
+__device__ inline int wrap_or_clamp(int i, int n, bool periodic) {
+  if (periodic) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// V at x plane xi (any integer within two planes of the grid) for the run at
+// in-plane offset off: a load on the grid, a wrapped load on a periodic x,
+// else the extrapolated ghost.  xi is uniform over the block.
+template <typename T, int R>
+__device__ inline void x_plane(const T *__restrict__ v, int xi, int nx, bool periodic, int plane, int off,
+                               T (&r)[R]) {
+  if (xi >= 0 && xi < nx) {
+    load_run<T, R>(v + xi * plane + off, r);
+  } else if (periodic) {
+    int w = xi < 0 ? xi + nx : xi - nx;
+    load_run<T, R>(v + w * plane + off, r);
+  } else {
+    int e = xi < 0 ? 0 : nx - 1, nb = xi < 0 ? 1 : nx - 2;
+    T k = T(xi < 0 ? -xi : xi - (nx - 1));
+    T ve[R], vb[R];
+    load_run<T, R>(v + e * plane + off, ve);
+    load_run<T, R>(v + nb * plane + off, vb);
+#pragma unroll
+    for (int j = 0; j < R; ++j) r[j] = ve[j] + k * (ve[j] - vb[j]);
+  }
+}
+
+template <typename T, int R, int DERIV, bool SG, bool BALL>
+__global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
+  const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
+  const int chunk = lb / a.blocks_per_chunk;
+  const int r = (lb - chunk * a.blocks_per_chunk) * kStreamBlock + (int)threadIdx.x;
+  if (r >= a.slab_runs) return;
+  const int nx = a.n[0], ny = a.n[1], nv = a.n[2], nth = a.n[3];
+  const bool perx = a.periodic_mask & 1u, pery = (a.periodic_mask >> 1) & 1u, perv = (a.periodic_mask >> 2) & 1u;
+  const int t = r % a.runs_per_row;
+  const int yv = r / a.runs_per_row;
+  const int v = yv % nv;
+  const int y = yv / nv;
+  const int th0 = t * R;
+  const int off = yv * nth + th0;
+  const int plane = a.plane;
+
+  // neighbour offsets within a plane
+  const int offl = yv * nth + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth);
+  const int offr = yv * nth + (th0 + R < nth ? th0 + R : th0 + R - nth);
+  int ov[4], oy[4];
+  {
+    const int o[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ov[k] = (y * nv + wrap_or_clamp(v + o[k], nv, perv)) * nth + th0;
+      oy[k] = (wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0;
+    }
+  }
+  T kpx[R], kmx[R], kpy[R], kmy[R];
+  {
+    const int c = v * nth + th0, m = nv * nth;
+    load_run<T, R>(a.coef + c, kpx);
+    load_run<T, R>(a.coef + m + c, kmx);
+    load_run<T, R>(a.coef + 2 * m + c, kpy);
+    load_run<T, R>(a.coef + 3 * m + c, kmy);
+  }
+  const bool ball_x = (a.ball_mask & 1u) != 0, ball_y = (a.ball_mask & 2u) != 0;
+  const bool ball_v = (a.ball_mask & 4u) != 0, ball_t = (a.ball_mask & 8u) != 0;
+
+  const T *__restrict__ vs = a.vs;
+  const int x0 = chunk * a.chunk_len;
+  const int x1 = min(nx, x0 + a.chunk_len);
+
+  // x ring: vx0 = V_X, vx1 = V_X+1 (ENO2), dxm = D_X-1/2, qx0 = Q_X and
+  // mxm = m_X-1/2 (ENO2)
+  T vx0[R], vx1[R], dxm[R], qx0[R], mxm[R];
+  if (DERIV == kEno2) {
+    T wm2[R], wm1[R];
+    x_plane<T, R>(vs, x0 - 2, nx, perx, plane, off, wm2);
+    x_plane<T, R>(vs, x0 - 1, nx, perx, plane, off, wm1);
+    x_plane<T, R>(vs, x0, nx, perx, plane, off, vx0);
+    x_plane<T, R>(vs, x0 + 1, nx, perx, plane, off, vx1);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      dxm[j] = vx0[j] - wm1[j];
+      T qm = second_diff(wm2[j], wm1[j], vx0[j]);
+      qx0[j] = second_diff(wm1[j], vx0[j], vx1[j]);
+      mxm[j] = choose(qm, qx0[j]);
+    }
+  } else {
+    T wm1[R];
+    x_plane<T, R>(vs, x0 - 1, nx, perx, plane, off, wm1);
+    x_plane<T, R>(vs, x0, nx, perx, plane, off, vx0);
+#pragma unroll
+    for (int j = 0; j < R; ++j) dxm[j] = vx0[j] - wm1[j];
+  }
+
+  for (int X = x0; X < x1; ++X) {
+    const int base = X * plane;
+    T L[R], b2[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      L[j] = T(0);
+      b2[j] = T(0);
+    }
+    // ---- x: advance the ring by one plane
+    {
+      T front[R];
+      x_plane<T, R>(vs, DERIV == kEno2 ? X + 2 : X + 1, nx, perx, plane, off, front);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        T pm, pp;
+        if (DERIV == kEno2) {
+          T dxp = vx1[j] - vx0[j];
+          T qx1 = second_diff(vx0[j], vx1[j], front[j]);
+          T mxp = choose(qx0[j], qx1);
+          pm = dxm[j] + T(0.5) * mxm[j];
+          pp = dxp - T(0.5) * mxp;
+          dxm[j] = dxp;
+          qx0[j] = qx1;
+          mxm[j] = mxp;
+        } else {
+          T dxp = front[j] - vx0[j];
+          pm = dxm[j];
+          pp = dxp;
+          dxm[j] = dxp;
+        }
+        accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
+      }
+      // shift after the other axes have used the current plane's centre
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (DERIV == kEno2) {
+          T tmp = vx0[j];
+          vx0[j] = vx1[j];
+          vx1[j] = front[j];
+          front[j] = tmp;  // front now holds V_X (the centre)
+        } else {
+          T tmp = vx0[j];
+          vx0[j] = front[j];
+          front[j] = tmp;
+        }
+      }
+      // ---- theta: run window u[0..R+3] with wrapped halos
+      T u[R + 4];
+      load_pair<T>(vs + base + offl, u[0], u[1]);
+      load_pair<T>(vs + base + offr, u[R + 2], u[R + 3]);
+#pragma unroll
+      for (int j = 0; j < R; ++j) u[j + 2] = front[j];
+      {
+        T dprev = u[2] - u[1];
+        T mprev = T(0);
+        if (DERIV == kEno2) mprev = choose(second_diff(u[0], u[1], u[2]), second_diff(u[1], u[2], u[3]));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          T dnext = u[j + 3] - u[j + 2];
+          T pm, pp;
+          if (DERIV == kEno2) {
+            T mnext = choose(second_diff(u[j + 1], u[j + 2], u[j + 3]), second_diff(u[j + 2], u[j + 3], u[j + 4]));
+            pm = dprev + T(0.5) * mprev;
+            pp = dnext - T(0.5) * mnext;
+            mprev = mnext;
+          } else {
+            pm = dprev;
+            pp = dnext;
+          }
+          dprev = dnext;
+          accumulate<T, true, BALL>(L[j], b2[j], a.kp_th, a.km_th, a.sg[3], pp, pm, ball_t, a.half_inv_h[3]);
+        }
+      }
+      // ---- v and y: neighbouring runs
+      T n2[R], n1[R], p1[R], p2[R];
+      if (DERIV == kEno2) load_run<T, R>(vs + base + ov[0], n2);
+      load_run<T, R>(vs + base + ov[1], n1);
+      load_run<T, R>(vs + base + ov[2], p1);
+      if (DERIV == kEno2) load_run<T, R>(vs + base + ov[3], p2);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (!perv) fix_ghosts<T, DERIV>(v, nv, front[j], n2[j], n1[j], p1[j], p2[j]);
+        T pm, pp;
+        window_diffs<T, DERIV>(n2[j], n1[j], front[j], p1[j], p2[j], pm, pp);
+        accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
+      }
+      if (DERIV == kEno2) load_run<T, R>(vs + base + oy[0], n2);
+      load_run<T, R>(vs + base + oy[1], n1);
+      load_run<T, R>(vs + base + oy[2], p1);
+      if (DERIV == kEno2) load_run<T, R>(vs + base + oy[3], p2);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (!pery) fix_ghosts<T, DERIV>(y, ny, front[j], n2[j], n1[j], p1[j], p2[j]);
+        T pm, pp;
+        window_diffs<T, DERIV>(n2[j], n1[j], front[j], p1[j], p2[j], pm, pp);
+        accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
+      }
+      // ---- update
+      T res[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        T Lj = L[j];
+        if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
+        res[j] = fma(a.dt, Lj, front[j]);
+      }
+      if (a.mode == kAverage) {
+        T vn[R];
+        load_run_nt<T, R>(a.vn + base + off, vn);
+#pragma unroll
+        for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
+      }
+      if (a.clamp) {
+        T t0[R];
+        load_run_nt<T, R>(a.v0 + base + off, t0);
+#pragma unroll
+        for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+      }
+      store_run_nt<T, R>(a.out + base + off, res);
+    }
+  }
+}
+
 // Target: one block per (x, y) pair computes the distance once and writes
 // it over the whole (v, theta) plane.
 template <typename T>
@@ -267,7 +614,27 @@ hipError_t launch_stage_d(const StageArgs<T> &a, bool ball, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int DERIV, bool SG, bool BALL>
+hipError_t launch_stream_v(const StreamArgs<T> &a, hipStream_t s) {
+  unsigned blocks = (unsigned)(a.blocks_per_chunk * a.n_chunks);
+  hipLaunchKernelGGL((stage_stream<T, stream_run<T>(), DERIV, SG, BALL>), dim3(blocks), dim3(kStreamBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DERIV>
+hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
+  bool sg = a.sg[0] != T(0) || a.sg[1] != T(0);
+  if (ball) return sg ? launch_stream_v<T, DERIV, true, true>(a, s) : launch_stream_v<T, DERIV, false, true>(a, s);
+  return sg ? launch_stream_v<T, DERIV, true, false>(a, s) : launch_stream_v<T, DERIV, false, false>(a, s);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s) {
+  if (deriv == kUpwind1) return launch_stream_d<T, kUpwind1>(a, ball, s);
+  return launch_stream_d<T, kEno2>(a, ball, s);
+}
 
 template <typename T>
 hipError_t launch_stage(const StageArgs<T> &a, int deriv, bool ball, hipStream_t s) {
@@ -305,6 +672,8 @@ hipError_t launch_nonfinite(const T *src, int64_t n, int32_t *flag, hipStream_t 
   return hipGetLastError();
 }
 
+template hipError_t launch_stream<float>(const StreamArgs<float> &, int, bool, hipStream_t);
+template hipError_t launch_stream<double>(const StreamArgs<double> &, int, bool, hipStream_t);
 template hipError_t launch_stage<float>(const StageArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_stage<double>(const StageArgs<double> &, int, bool, hipStream_t);
 template hipError_t launch_cylinders<float>(const CylinderArgs<float> &, hipStream_t);
