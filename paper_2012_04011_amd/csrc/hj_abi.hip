@@ -204,9 +204,10 @@ void build_coef(hj_grid *G, const std::vector<double> &tab, std::vector<double> 
   }
 }
 
-// Number of x chunks the streaming kernel splits the sweep into: enough
-// blocks to give every CU about five (256 CUs), but at least 8 planes per
-// chunk (each chunk re-reads up to 4 planes to start its ring).
+// Number of x chunks the streaming kernel splits the sweep into: about four
+// blocks per CU (256 CUs; 3 chunks on the 120x120x40x72 grid measured best
+// among 1..10), but at least 8 planes per chunk (each chunk re-reads up to 4
+// planes to start its ring).
 int choose_x_chunks(int nx, int64_t slab_runs) {
   const char *env = getenv("HJ_X_CHUNKS");
   if (env && atoi(env) > 0) {
@@ -214,7 +215,7 @@ int choose_x_chunks(int nx, int64_t slab_runs) {
     return c > nx ? nx : c;
   }
   int64_t bpc = (slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
-  int64_t want = (1280 + bpc - 1) / bpc;
+  int64_t want = (1000 + bpc - 1) / bpc;
   int64_t cap = nx / 8 > 1 ? nx / 8 : 1;
   int64_t c = want < cap ? want : cap;
   return c < 1 ? 1 : (int)c;
@@ -540,7 +541,10 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   int64_t m = (int64_t)grid->n[2] * grid->n[3];
   {
     int run = scheme->precision == HJ_F32 ? hj::stream_run<float>() : hj::stream_run<double>();
-    G->stream_ok = bit(grid->periodic_mask, 3) && grid->n[3] % run == 0;
+    // theta periodic and a whole number of runs per row; 32-bit byte
+    // offsets (buffer addressing) need each array below 4 GiB
+    G->stream_ok = bit(grid->periodic_mask, 3) && grid->n[3] % run == 0 &&
+                   G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
     int64_t slab_runs = (int64_t)grid->n[1] * grid->n[2] * (grid->n[3] / run);
     G->x_chunks = choose_x_chunks(grid->n[0], slab_runs);
   }

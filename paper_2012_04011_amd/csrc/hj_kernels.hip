@@ -322,34 +322,96 @@ __device__ inline void x_plane(const T *__restrict__ v, int xi, int nx, bool per
   }
 }
 
+// Raw buffer access: a 128-bit resource in SGPRs (base, byte range), a
+// per-lane byte offset and a wave-uniform byte offset.  Loads past the range
+// return zero and stores past it are dropped.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+constexpr int kCacheDefault = 0;
+constexpr int kCacheStream = 2;  // non-temporal
+
+template <typename T, int R, int AUX = kCacheDefault>
+__device__ inline void bload(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T (&r)[R]) {
+  typedef typename VecT<T, R>::type V;
+  V x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, AUX));
+#pragma unroll
+  for (int i = 0; i < R; ++i) r[i] = x[i];
+}
+
+template <typename T>
+__device__ inline void bload_pair(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T &a, T &b) {
+  typedef typename Vec2T<T>::type V;
+  V x;
+  if constexpr (sizeof(T) == 4)
+    x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, kCacheDefault));
+  else
+    x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, kCacheDefault));
+  a = x[0];
+  b = x[1];
+}
+
+// V at x plane xi (within two planes of the grid) for one run: on the grid,
+// wrapped on a periodic x axis, else extrapolated.  xi is block-uniform.
+template <typename T, int R>
+__device__ inline void x_plane_b(__amdgpu_buffer_rsrc_t rs, int xi, int nx, bool periodic, uint32_t pb, uint32_t voff,
+                                 T (&r)[R]) {
+  if (xi >= 0 && xi < nx) {
+    bload<T, R>(rs, voff, (uint32_t)xi * pb, r);
+  } else if (periodic) {
+    int w = xi < 0 ? xi + nx : xi - nx;
+    bload<T, R>(rs, voff, (uint32_t)w * pb, r);
+  } else {
+    int e = xi < 0 ? 0 : nx - 1, nb = xi < 0 ? 1 : nx - 2;
+    T k = T(xi < 0 ? -xi : xi - (nx - 1));
+    T ve[R], vb[R];
+    bload<T, R>(rs, voff, (uint32_t)e * pb, ve);
+    bload<T, R>(rs, voff, (uint32_t)nb * pb, vb);
+#pragma unroll
+    for (int j = 0; j < R; ++j) r[j] = ve[j] + k * (ve[j] - vb[j]);
+  }
+}
+
+// Ghost fix-up of one open axis for a whole run (see fix_ghosts).
+template <typename T, int R, int DERIV>
+__device__ inline void fix_run(int i, int n, const T (&c)[R], T (&m2)[R], T (&m1)[R], T (&p1)[R], T (&p2)[R]) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) fix_ghosts<T, DERIV>(i, n, c[j], m2[j], m1[j], p1[j], p2[j]);
+}
+
 template <typename T, int R, int DERIV, bool SG, bool BALL>
 __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
+  constexpr uint32_t E = sizeof(T);
   const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
   const int chunk = lb / a.blocks_per_chunk;
   const int r = (lb - chunk * a.blocks_per_chunk) * kStreamBlock + (int)threadIdx.x;
   if (r >= a.slab_runs) return;
   const int nx = a.n[0], ny = a.n[1], nv = a.n[2], nth = a.n[3];
   const bool perx = a.periodic_mask & 1u, pery = (a.periodic_mask >> 1) & 1u, perv = (a.periodic_mask >> 2) & 1u;
+  // runs are ordered theta-run fastest, then v, then y: a wave's 64 runs
+  // cover one contiguous stretch of a plane
   const int t = r % a.runs_per_row;
   const int yv = r / a.runs_per_row;
   const int v = yv % nv;
   const int y = yv / nv;
   const int th0 = t * R;
-  const int off = yv * nth + th0;
-  const int plane = a.plane;
-
-  // neighbour offsets within a plane
-  const int offl = yv * nth + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth);
-  const int offr = yv * nth + (th0 + R < nth ? th0 + R : th0 + R - nth);
-  int ov[4], oy[4];
+  const int rowoff = (y * nv + v) * nth;
+  const int offe = rowoff + th0;
+  const uint32_t oc = (uint32_t)offe * E;
+  const uint32_t ol = (uint32_t)(rowoff + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth)) * E;
+  const uint32_t orr = (uint32_t)(rowoff + (th0 + R < nth ? th0 + R : th0 + R - nth)) * E;
+  uint32_t ov[4], oy[4];
   {
     const int o[4] = {-2, -1, 1, 2};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      ov[k] = (y * nv + wrap_or_clamp(v + o[k], nv, perv)) * nth + th0;
-      oy[k] = (wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0;
+      ov[k] = (uint32_t)((y * nv + wrap_or_clamp(v + o[k], nv, perv)) * nth + th0) * E;
+      oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
     }
   }
+  const bool vedge = !perv && (v < 2 || v >= nv - 2);
+  const bool yedge = !pery && (y < 2 || y >= ny - 2);
   T kpx[R], kmx[R], kpy[R], kmy[R];
   {
     const int c = v * nth + th0, m = nv * nth;
@@ -361,19 +423,23 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
   const bool ball_x = (a.ball_mask & 1u) != 0, ball_y = (a.ball_mask & 2u) != 0;
   const bool ball_v = (a.ball_mask & 4u) != 0, ball_t = (a.ball_mask & 8u) != 0;
 
-  const T *__restrict__ vs = a.vs;
+  const uint32_t pb = (uint32_t)a.plane * E;  // bytes per x plane
+  const uint32_t total = pb * (uint32_t)nx;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vs, total);
+  const __amdgpu_buffer_rsrc_t rvn = make_rsrc(a.vn, a.mode == kAverage ? total : 0u);
+  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, a.clamp ? total : 0u);
   const int x0 = chunk * a.chunk_len;
   const int x1 = min(nx, x0 + a.chunk_len);
+  constexpr int FR = DERIV == kEno2 ? 2 : 1;  // the x front is plane X + FR
 
-  // x ring: vx0 = V_X, vx1 = V_X+1 (ENO2), dxm = D_X-1/2, qx0 = Q_X and
-  // mxm = m_X-1/2 (ENO2)
-  T vx0[R], vx1[R], dxm[R], qx0[R], mxm[R];
+  // x ring (see the description above) and the prefetched front
+  T vx0[R], vx1[R], dxm[R], qx0[R], mxm[R], pre[R];
   if (DERIV == kEno2) {
     T wm2[R], wm1[R];
-    x_plane<T, R>(vs, x0 - 2, nx, perx, plane, off, wm2);
-    x_plane<T, R>(vs, x0 - 1, nx, perx, plane, off, wm1);
-    x_plane<T, R>(vs, x0, nx, perx, plane, off, vx0);
-    x_plane<T, R>(vs, x0 + 1, nx, perx, plane, off, vx1);
+    x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
+    x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
+    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, vx0);
+    x_plane_b<T, R>(rs, x0 + 1, nx, perx, pb, oc, vx1);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       dxm[j] = vx0[j] - wm1[j];
@@ -383,131 +449,134 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
     }
   } else {
     T wm1[R];
-    x_plane<T, R>(vs, x0 - 1, nx, perx, plane, off, wm1);
-    x_plane<T, R>(vs, x0, nx, perx, plane, off, vx0);
+    x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
+    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, vx0);
 #pragma unroll
     for (int j = 0; j < R; ++j) dxm[j] = vx0[j] - wm1[j];
   }
+  x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, pre);
 
   for (int X = x0; X < x1; ++X) {
-    const int base = X * plane;
+    const uint32_t sX = (uint32_t)X * pb;
+    // ---- issue this plane's neighbour loads, then the next front
+    T u[R + 4];
+    T vn2[R], vn1[R], vp1[R], vp2[R], yn2[R], yn1[R], yp1[R], yp2[R];
+    bload_pair<T>(rs, ol, sX, u[0], u[1]);
+    bload_pair<T>(rs, orr, sX, u[R + 2], u[R + 3]);
+    if (DERIV == kEno2) bload<T, R>(rs, ov[0], sX, vn2);
+    bload<T, R>(rs, ov[1], sX, vn1);
+    bload<T, R>(rs, ov[2], sX, vp1);
+    if (DERIV == kEno2) bload<T, R>(rs, ov[3], sX, vp2);
+    if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX, yn2);
+    bload<T, R>(rs, oy[1], sX, yn1);
+    bload<T, R>(rs, oy[2], sX, yp1);
+    if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
+    T front[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) front[j] = pre[j];
+    if (X + 1 < x1) {
+      const int xf = X + 1 + FR;
+      if (xf < nx)
+        bload<T, R>(rs, oc, (uint32_t)xf * pb, pre);
+      else
+        x_plane_b<T, R>(rs, xf, nx, perx, pb, oc, pre);
+    }
     T L[R], b2[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       L[j] = T(0);
       b2[j] = T(0);
     }
-    // ---- x: advance the ring by one plane
-    {
-      T front[R];
-      x_plane<T, R>(vs, DERIV == kEno2 ? X + 2 : X + 1, nx, perx, plane, off, front);
+    // ---- x: advance the ring; c = V_X (centre)
+    T c[R];
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        T pm, pp;
-        if (DERIV == kEno2) {
-          T dxp = vx1[j] - vx0[j];
-          T qx1 = second_diff(vx0[j], vx1[j], front[j]);
-          T mxp = choose(qx0[j], qx1);
-          pm = dxm[j] + T(0.5) * mxm[j];
-          pp = dxp - T(0.5) * mxp;
-          dxm[j] = dxp;
-          qx0[j] = qx1;
-          mxm[j] = mxp;
-        } else {
-          T dxp = front[j] - vx0[j];
-          pm = dxm[j];
-          pp = dxp;
-          dxm[j] = dxp;
-        }
-        accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
+    for (int j = 0; j < R; ++j) {
+      T pm, pp;
+      c[j] = vx0[j];
+      if (DERIV == kEno2) {
+        T dxp = vx1[j] - vx0[j];
+        T qx1 = second_diff(vx0[j], vx1[j], front[j]);
+        T mxp = choose(qx0[j], qx1);
+        pm = dxm[j] + T(0.5) * mxm[j];
+        pp = dxp - T(0.5) * mxp;
+        dxm[j] = dxp;
+        qx0[j] = qx1;
+        mxm[j] = mxp;
+        vx0[j] = vx1[j];
+        vx1[j] = front[j];
+      } else {
+        T dxp = front[j] - vx0[j];
+        pm = dxm[j];
+        pp = dxp;
+        dxm[j] = dxp;
+        vx0[j] = front[j];
       }
-      // shift after the other axes have used the current plane's centre
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (DERIV == kEno2) {
-          T tmp = vx0[j];
-          vx0[j] = vx1[j];
-          vx1[j] = front[j];
-          front[j] = tmp;  // front now holds V_X (the centre)
-        } else {
-          T tmp = vx0[j];
-          vx0[j] = front[j];
-          front[j] = tmp;
-        }
-      }
-      // ---- theta: run window u[0..R+3] with wrapped halos
-      T u[R + 4];
-      load_pair<T>(vs + base + offl, u[0], u[1]);
-      load_pair<T>(vs + base + offr, u[R + 2], u[R + 3]);
-#pragma unroll
-      for (int j = 0; j < R; ++j) u[j + 2] = front[j];
-      {
-        T dprev = u[2] - u[1];
-        T mprev = T(0);
-        if (DERIV == kEno2) mprev = choose(second_diff(u[0], u[1], u[2]), second_diff(u[1], u[2], u[3]));
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          T dnext = u[j + 3] - u[j + 2];
-          T pm, pp;
-          if (DERIV == kEno2) {
-            T mnext = choose(second_diff(u[j + 1], u[j + 2], u[j + 3]), second_diff(u[j + 2], u[j + 3], u[j + 4]));
-            pm = dprev + T(0.5) * mprev;
-            pp = dnext - T(0.5) * mnext;
-            mprev = mnext;
-          } else {
-            pm = dprev;
-            pp = dnext;
-          }
-          dprev = dnext;
-          accumulate<T, true, BALL>(L[j], b2[j], a.kp_th, a.km_th, a.sg[3], pp, pm, ball_t, a.half_inv_h[3]);
-        }
-      }
-      // ---- v and y: neighbouring runs
-      T n2[R], n1[R], p1[R], p2[R];
-      if (DERIV == kEno2) load_run<T, R>(vs + base + ov[0], n2);
-      load_run<T, R>(vs + base + ov[1], n1);
-      load_run<T, R>(vs + base + ov[2], p1);
-      if (DERIV == kEno2) load_run<T, R>(vs + base + ov[3], p2);
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (!perv) fix_ghosts<T, DERIV>(v, nv, front[j], n2[j], n1[j], p1[j], p2[j]);
-        T pm, pp;
-        window_diffs<T, DERIV>(n2[j], n1[j], front[j], p1[j], p2[j], pm, pp);
-        accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
-      }
-      if (DERIV == kEno2) load_run<T, R>(vs + base + oy[0], n2);
-      load_run<T, R>(vs + base + oy[1], n1);
-      load_run<T, R>(vs + base + oy[2], p1);
-      if (DERIV == kEno2) load_run<T, R>(vs + base + oy[3], p2);
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (!pery) fix_ghosts<T, DERIV>(y, ny, front[j], n2[j], n1[j], p1[j], p2[j]);
-        T pm, pp;
-        window_diffs<T, DERIV>(n2[j], n1[j], front[j], p1[j], p2[j], pm, pp);
-        accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
-      }
-      // ---- update
-      T res[R];
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        T Lj = L[j];
-        if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
-        res[j] = fma(a.dt, Lj, front[j]);
-      }
-      if (a.mode == kAverage) {
-        T vn[R];
-        load_run_nt<T, R>(a.vn + base + off, vn);
-#pragma unroll
-        for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
-      }
-      if (a.clamp) {
-        T t0[R];
-        load_run_nt<T, R>(a.v0 + base + off, t0);
-#pragma unroll
-        for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
-      }
-      store_run_nt<T, R>(a.out + base + off, res);
+      accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
     }
+    // ---- theta: the run with its wrapped halos
+#pragma unroll
+    for (int j = 0; j < R; ++j) u[j + 2] = c[j];
+    {
+      T dprev = u[2] - u[1];
+      T mprev = T(0);
+      if (DERIV == kEno2) mprev = choose(second_diff(u[0], u[1], u[2]), second_diff(u[1], u[2], u[3]));
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        T dnext = u[j + 3] - u[j + 2];
+        T pm, pp;
+        if (DERIV == kEno2) {
+          T mnext = choose(second_diff(u[j + 1], u[j + 2], u[j + 3]), second_diff(u[j + 2], u[j + 3], u[j + 4]));
+          pm = dprev + T(0.5) * mprev;
+          pp = dnext - T(0.5) * mnext;
+          mprev = mnext;
+        } else {
+          pm = dprev;
+          pp = dnext;
+        }
+        dprev = dnext;
+        accumulate<T, true, BALL>(L[j], b2[j], a.kp_th, a.km_th, a.sg[3], pp, pm, ball_t, a.half_inv_h[3]);
+      }
+    }
+    // ---- v
+    if (vedge) fix_run<T, R, DERIV>(v, nv, c, vn2, vn1, vp1, vp2);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T pm, pp;
+      window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pm, pp);
+      accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
+    }
+    // ---- y
+    if (yedge) fix_run<T, R, DERIV>(y, ny, c, yn2, yn1, yp1, yp2);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T pm, pp;
+      window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pm, pp);
+      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
+    }
+    // ---- update
+    T res[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T Lj = L[j];
+      if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
+      res[j] = fma(a.dt, Lj, c[j]);
+    }
+    if (a.mode == kAverage) {
+      T vn[R];
+      bload<T, R, kCacheStream>(rvn, oc, sX, vn);
+#pragma unroll
+      for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
+    }
+    if (a.clamp) {
+      T t0[R];
+      bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+#pragma unroll
+      for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+    }
+    // a global (not buffer) store: with a register soffset the compiler puts
+    // no wait state between a 128-bit buffer store and the next write of its
+    // data registers, and outputs came out wrong at random under load
+    store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
   }
 }
 

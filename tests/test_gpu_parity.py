@@ -338,3 +338,54 @@ def test_large_120_one_step_operator(precision):
     else:
         assert bad.mean() <= 1e-5
         assert err.max() <= 1e-2
+
+
+@pytest.mark.parametrize("chunks", ["1", "7"])
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_one_step_random_input_multi_chunk(monkeypatch, chunks, precision):
+    """One ENO2 Euler step of the 60x60x20x36 car (disturbance 0.1) from a
+    rough input (the cylinder target plus 0.01 noise) with the x sweep split
+    into 1 and 7 chunks: every node within rounding of the oracle except FP32
+    near-tie ENO choices (<= 1e-5 of the nodes), and two launches bitwise
+    equal."""
+    from paper_2012_04011_amd import hj
+
+    monkeypatch.setenv("HJ_X_CHUNKS", chunks)
+    wl = W.ENO_60_DIST
+    sch = dict(wl.scheme, integrator="euler", clamp=False)
+    V0 = oracle.target_cylinders(wl.grid, *W.cylinders(0, wl.obstacles))
+    Vk = V0 + 0.01 * np.random.default_rng(0).standard_normal(V0.shape)
+    if precision == "f32":
+        Vk = Vk.astype(np.float32).astype(np.float64)
+    dt = oracle.cfl_dt(wl.grid, wl.dyn, 0.8, wl.horizon)
+    ref = oracle.step(wl.grid, wl.dyn, sch, V0, Vk, dt)
+    outs = []
+    for _ in range(2):
+        with hj.Grid(wl.grid, wl.dyn, sch, precision) as g:
+            g.set_target(V0)
+            g.set_value(Vk)
+            g.step(dt)
+            outs.append(g.value())
+    assert np.array_equal(outs[0], outs[1])
+    u = U32 if precision == "f32" else U64
+    bad = np.abs(outs[0] - ref) > 16 * u * np.maximum(np.abs(ref), 1.0)
+    if precision == "f64":
+        assert not bad.any()
+    else:
+        assert bad.mean() <= 1e-5, int(bad.sum())
+
+
+def test_large_120_determinism():
+    """Two 20-step FP32 runs of the benchmark workload are bitwise equal."""
+    from paper_2012_04011_amd import hj
+
+    wl = W.LARGE_120
+    cyl = W.cylinders(3, wl.obstacles)
+    outs = []
+    for _ in range(2):
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32") as g:
+            g.set_target_cylinders(*cyl)
+            for _ in range(20):
+                g.step()
+            outs.append(g.value(np.float32))
+    assert np.array_equal(outs[0], outs[1])
