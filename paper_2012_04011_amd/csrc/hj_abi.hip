@@ -56,7 +56,8 @@ struct hj_grid {
   void *w2 = nullptr;   // next value (swapped with v after a step)
   void *lut = nullptr;  // bx | by | ax | ay in the scheme's precision
   void *coef = nullptr;  // kp_x | km_x | kp_y | km_y (streaming kernel)
-  bool stream_ok = false;  // shape suits the streaming kernel
+  // stage kernel: 2 = plane (LDS), 1 = streaming, 0 = generic
+  int kernel = 0;
   int x_chunks = 1;
   double *lut64 = nullptr;  // ax | ay in FP64 for the CFL reduction
   double *amax_dev = nullptr;
@@ -204,18 +205,24 @@ void build_coef(hj_grid *G, const std::vector<double> &tab, std::vector<double> 
   }
 }
 
-// Number of x chunks the streaming kernel splits the sweep into: about four
-// blocks per CU (256 CUs; 3 chunks on the 120x120x40x72 grid measured best
-// among 1..10), but at least 8 planes per chunk (each chunk re-reads up to 4
-// planes to start its ring).
-int choose_x_chunks(int nx, int64_t slab_runs) {
+// Number of x chunks a sweep is split into.  Streaming kernel: about four
+// blocks of 256 threads per CU (256 CUs; 3 chunks on the 120x120x40x72 grid
+// measured best among 1..10).  Plane kernel (one block per y row and chunk):
+// about two blocks per CU.  Either way at least 8 planes per chunk (each
+// chunk re-reads up to 4 planes to start its ring).
+int choose_x_chunks(int nx, int ny, int64_t slab_runs, bool plane) {
   const char *env = getenv("HJ_X_CHUNKS");
   if (env && atoi(env) > 0) {
     int c = atoi(env);
     return c > nx ? nx : c;
   }
-  int64_t bpc = (slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
-  int64_t want = (1000 + bpc - 1) / bpc;
+  int64_t want;
+  if (plane) {
+    want = (512 + ny / 2) / ny;
+  } else {
+    int64_t bpc = (slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+    want = (1000 + bpc - 1) / bpc;
+  }
   int64_t cap = nx / 8 > 1 ? nx / 8 : 1;
   int64_t c = want < cap ? want : cap;
   return c < 1 ? 1 : (int)c;
@@ -434,7 +441,7 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   a.row = g.n[2] * g.n[3];
   a.runs_per_row = g.n[3] / run;
   a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
-  a.blocks_per_chunk = (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  a.blocks_per_chunk = G->kernel == 2 ? g.n[1] : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
   a.n_chunks = G->x_chunks;
   a.chunk_len = (g.n[0] + a.n_chunks - 1) / a.n_chunks;
   a.n_chunks = (g.n[0] + a.chunk_len - 1) / a.chunk_len;
@@ -456,7 +463,7 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
 template <typename T>
 hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mode, int clamp, double dt) {
   bool ball = G->ball_mask != 0;
-  if (G->stream_ok) {
+  if (G->kernel > 0) {
     hj::StreamArgs<T> a = stream_args<T>(G);
     a.vs = vs;
     a.vn = vn;
@@ -465,7 +472,10 @@ hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mod
     a.mode = mode;
     a.clamp = clamp;
     a.dt = (T)dt;
-    HJ_HIP(hj::launch_stream(a, G->sch.deriv, ball, S(G)));
+    if (G->kernel == 2)
+      HJ_HIP(hj::launch_plane(a, G->sch.deriv, ball, S(G)));
+    else
+      HJ_HIP(hj::launch_stream(a, G->sch.deriv, ball, S(G)));
     return HJ_OK;
   }
   hj::StageArgs<T> a = stage_args<T>(G);
@@ -543,12 +553,20 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     int run = scheme->precision == HJ_F32 ? hj::stream_run<float>() : hj::stream_run<double>();
     // theta periodic and a whole number of runs per row; 32-bit byte
     // offsets (buffer addressing) need each array below 4 GiB
-    G->stream_ok = bit(grid->periodic_mask, 3) && grid->n[3] % run == 0 &&
-                   G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
-    int64_t slab_runs = (int64_t)grid->n[1] * grid->n[2] * (grid->n[3] / run);
-    G->x_chunks = choose_x_chunks(grid->n[0], slab_runs);
+    bool stream_ok = bit(grid->periodic_mask, 3) && grid->n[3] % run == 0 &&
+                     G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
+    int64_t plane_runs = (int64_t)grid->n[2] * (grid->n[3] / run);
+    bool plane_ok = stream_ok && plane_runs <= hj::kPlaneMaxThreads &&
+                    2 * (int64_t)grid->n[2] * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
+    G->kernel = plane_ok ? 2 : (stream_ok ? 1 : 0);
+    const char *force = getenv("HJ_STAGE_KERNEL");
+    if (force) {
+      if (!strcmp(force, "generic")) G->kernel = 0;
+      if (!strcmp(force, "stream") && stream_ok) G->kernel = 1;
+    }
+    int64_t slab_runs = (int64_t)grid->n[1] * plane_runs;
+    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1], slab_runs, G->kernel == 2);
   }
-
   hipError_t e = hipGetDevice(&G->device);
   size_t bytes = G->npts * G->elem;
   bool rk2 = scheme->integrator == HJ_TVD_RK2;

@@ -471,6 +471,10 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
     bload<T, R>(rs, oy[1], sX, yn1);
     bload<T, R>(rs, oy[2], sX, yp1);
     if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
+    // pointwise streams of this plane (V^n, V0): issued now, used at the end
+    T vn[R], t0[R];
+    if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
+    if (a.clamp) bload<T, R, kCacheStream>(rv0, oc, sX, t0);
     T front[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) front[j] = pre[j];
@@ -562,14 +566,10 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
       res[j] = fma(a.dt, Lj, c[j]);
     }
     if (a.mode == kAverage) {
-      T vn[R];
-      bload<T, R, kCacheStream>(rvn, oc, sX, vn);
 #pragma unroll
       for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
     }
     if (a.clamp) {
-      T t0[R];
-      bload<T, R, kCacheStream>(rv0, oc, sX, t0);
 #pragma unroll
       for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
     }
@@ -577,6 +577,244 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
     // no wait state between a 128-bit buffer store and the next write of its
     // data registers, and outputs came out wrong at random under load
     store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plane kernel.  Block (y, x chunk) owns every run of the (v, theta) plane at
+// one y and sweeps the chunk's x planes.  Each thread keeps the x ring of its
+// run in registers; per plane it writes its centre run into a double-buffered
+// LDS copy of the plane, and after one barrier reads its theta halos and its
+// v neighbours from LDS.  Only the x front (prefetched one plane ahead) and
+// the four y-neighbour runs are global loads.
+// ---------------------------------------------------------------------------
+
+template <typename T, int R>
+__device__ inline void lds_run(const T *p, T (&r)[R]) {
+  typedef typename VecT<T, R>::type V;
+  V x = *reinterpret_cast<const V *>(p);
+#pragma unroll
+  for (int i = 0; i < R; ++i) r[i] = x[i];
+}
+
+template <typename T>
+__device__ inline void lds_pair(const T *p, T &a, T &b) {
+  typedef typename Vec2T<T>::type V;
+  V x = *reinterpret_cast<const V *>(p);
+  a = x[0];
+  b = x[1];
+}
+
+template <typename T, int R, int DERIV, bool SG, bool BALL>
+__global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T *lds = reinterpret_cast<T *>(lds_raw);
+  constexpr uint32_t E = sizeof(T);
+  const int nx = a.n[0], ny = a.n[1], nv = a.n[2], nth = a.n[3];
+  const int rpr = a.runs_per_row;
+  const int runs = nv * rpr;  // runs of one (v, theta) plane
+  const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
+  const int chunk = lb / ny;
+  const int y = lb - chunk * ny;
+  const bool active = (int)threadIdx.x < runs;
+  const int r = active ? (int)threadIdx.x : runs - 1;  // idle lanes shadow the last run
+  const bool perx = a.periodic_mask & 1u, pery = (a.periodic_mask >> 1) & 1u, perv = (a.periodic_mask >> 2) & 1u;
+  const int t = r % rpr;
+  const int v = r / rpr;
+  const int th0 = t * R;
+  const int pl = v * nth + th0;  // offset inside the (v, theta) plane
+  const int offe = y * nv * nth + pl;
+  const uint32_t oc = (uint32_t)offe * E;
+  uint32_t oy[4];
+  int lv[4];
+  {
+    const int o[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
+      lv[k] = wrap_or_clamp(v + o[k], nv, perv) * nth + th0;
+    }
+  }
+  const int ll = v * nth + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth);
+  const int lr = v * nth + (th0 + R < nth ? th0 + R : th0 + R - nth);
+  const bool vedge = !perv && (v < 2 || v >= nv - 2);
+  const bool yedge = !pery && (y < 2 || y >= ny - 2);
+  T kpx[R], kmx[R], kpy[R], kmy[R];
+  {
+    const int m = nv * nth;
+    load_run<T, R>(a.coef + pl, kpx);
+    load_run<T, R>(a.coef + m + pl, kmx);
+    load_run<T, R>(a.coef + 2 * m + pl, kpy);
+    load_run<T, R>(a.coef + 3 * m + pl, kmy);
+  }
+  const bool ball_x = (a.ball_mask & 1u) != 0, ball_y = (a.ball_mask & 2u) != 0;
+  const bool ball_v = (a.ball_mask & 4u) != 0, ball_t = (a.ball_mask & 8u) != 0;
+
+  const uint32_t pb = (uint32_t)a.plane * E;
+  const uint32_t total = pb * (uint32_t)nx;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vs, total);
+  const __amdgpu_buffer_rsrc_t rvn = make_rsrc(a.vn, a.mode == kAverage ? total : 0u);
+  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, a.clamp ? total : 0u);
+  const int x0 = chunk * a.chunk_len;
+  const int x1 = min(nx, x0 + a.chunk_len);
+  constexpr int FR = DERIV == kEno2 ? 2 : 1;
+  const int psz = nv * nth;  // values per LDS buffer
+
+  T vx0[R], vx1[R], dxm[R], qx0[R], mxm[R], pre[R];
+  if (DERIV == kEno2) {
+    T wm2[R], wm1[R];
+    x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
+    x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
+    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, vx0);
+    x_plane_b<T, R>(rs, x0 + 1, nx, perx, pb, oc, vx1);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      dxm[j] = vx0[j] - wm1[j];
+      T qm = second_diff(wm2[j], wm1[j], vx0[j]);
+      qx0[j] = second_diff(wm1[j], vx0[j], vx1[j]);
+      mxm[j] = choose(qm, qx0[j]);
+    }
+  } else {
+    T wm1[R];
+    x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
+    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, vx0);
+#pragma unroll
+    for (int j = 0; j < R; ++j) dxm[j] = vx0[j] - wm1[j];
+  }
+  x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, pre);
+
+  for (int X = x0; X < x1; ++X) {
+    const uint32_t sX = (uint32_t)X * pb;
+    T *buf = lds + ((X - x0) & 1) * psz;
+    // ---- global loads: y neighbours of this plane, then the next front
+    T yn2[R], yn1[R], yp1[R], yp2[R];
+    if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX, yn2);
+    bload<T, R>(rs, oy[1], sX, yn1);
+    bload<T, R>(rs, oy[2], sX, yp1);
+    if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
+    // pointwise streams of this plane (V^n, V0): issued now, used at the end
+    T vn[R], t0[R];
+    if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
+    if (a.clamp) bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+    T front[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) front[j] = pre[j];
+    if (X + 1 < x1) {
+      const int xf = X + 1 + FR;
+      if (xf < nx)
+        bload<T, R>(rs, oc, (uint32_t)xf * pb, pre);
+      else
+        x_plane_b<T, R>(rs, xf, nx, perx, pb, oc, pre);
+    }
+    // ---- publish the centre run; c = V_X
+    T c[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) c[j] = vx0[j];
+    if (active) {
+      typedef typename VecT<T, R>::type V;
+      V cv;
+#pragma unroll
+      for (int j = 0; j < R; ++j) cv[j] = c[j];
+      *reinterpret_cast<V *>(buf + pl) = cv;
+    }
+    T L[R], b2[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      L[j] = T(0);
+      b2[j] = T(0);
+    }
+    // ---- x: advance the ring (registers only, overlaps the barrier wait)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T pm, pp;
+      if (DERIV == kEno2) {
+        T dxp = vx1[j] - vx0[j];
+        T qx1 = second_diff(vx0[j], vx1[j], front[j]);
+        T mxp = choose(qx0[j], qx1);
+        pm = dxm[j] + T(0.5) * mxm[j];
+        pp = dxp - T(0.5) * mxp;
+        dxm[j] = dxp;
+        qx0[j] = qx1;
+        mxm[j] = mxp;
+        vx0[j] = vx1[j];
+        vx1[j] = front[j];
+      } else {
+        T dxp = front[j] - vx0[j];
+        pm = dxm[j];
+        pp = dxp;
+        dxm[j] = dxp;
+        vx0[j] = front[j];
+      }
+      accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
+    }
+    __syncthreads();
+    // ---- theta: halos from LDS
+    {
+      T u[R + 4];
+      lds_pair<T>(buf + ll, u[0], u[1]);
+      lds_pair<T>(buf + lr, u[R + 2], u[R + 3]);
+#pragma unroll
+      for (int j = 0; j < R; ++j) u[j + 2] = c[j];
+      T dprev = u[2] - u[1];
+      T mprev = T(0);
+      if (DERIV == kEno2) mprev = choose(second_diff(u[0], u[1], u[2]), second_diff(u[1], u[2], u[3]));
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        T dnext = u[j + 3] - u[j + 2];
+        T pm, pp;
+        if (DERIV == kEno2) {
+          T mnext = choose(second_diff(u[j + 1], u[j + 2], u[j + 3]), second_diff(u[j + 2], u[j + 3], u[j + 4]));
+          pm = dprev + T(0.5) * mprev;
+          pp = dnext - T(0.5) * mnext;
+          mprev = mnext;
+        } else {
+          pm = dprev;
+          pp = dnext;
+        }
+        dprev = dnext;
+        accumulate<T, true, BALL>(L[j], b2[j], a.kp_th, a.km_th, a.sg[3], pp, pm, ball_t, a.half_inv_h[3]);
+      }
+    }
+    // ---- v: neighbours from LDS
+    {
+      T vn2[R], vn1[R], vp1[R], vp2[R];
+      if (DERIV == kEno2) lds_run<T, R>(buf + lv[0], vn2);
+      lds_run<T, R>(buf + lv[1], vn1);
+      lds_run<T, R>(buf + lv[2], vp1);
+      if (DERIV == kEno2) lds_run<T, R>(buf + lv[3], vp2);
+      if (vedge) fix_run<T, R, DERIV>(v, nv, c, vn2, vn1, vp1, vp2);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        T pm, pp;
+        window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pm, pp);
+        accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
+      }
+    }
+    // ---- y: neighbours from global memory
+    if (yedge) fix_run<T, R, DERIV>(y, ny, c, yn2, yn1, yp1, yp2);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T pm, pp;
+      window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pm, pp);
+      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
+    }
+    // ---- update
+    T res[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T Lj = L[j];
+      if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
+      res[j] = fma(a.dt, Lj, c[j]);
+    }
+    if (a.mode == kAverage) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
+    }
+    if (a.clamp) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+    }
+    if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
   }
 }
 
@@ -697,7 +935,30 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
   return sg ? launch_stream_v<T, DERIV, true, false>(a, s) : launch_stream_v<T, DERIV, false, false>(a, s);
 }
 
+template <typename T, int DERIV, bool SG, bool BALL>
+hipError_t launch_plane_v(const StreamArgs<T> &a, hipStream_t s) {
+  int runs = a.n[2] * a.runs_per_row;
+  int threads = (runs + 63) / 64 * 64;
+  size_t lds = 2 * (size_t)a.n[2] * a.n[3] * sizeof(T);
+  unsigned blocks = (unsigned)(a.n[1] * a.n_chunks);
+  hipLaunchKernelGGL((stage_plane<T, stream_run<T>(), DERIV, SG, BALL>), dim3(blocks), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DERIV>
+hipError_t launch_plane_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
+  bool sg = a.sg[0] != T(0) || a.sg[1] != T(0);
+  if (ball) return sg ? launch_plane_v<T, DERIV, true, true>(a, s) : launch_plane_v<T, DERIV, false, true>(a, s);
+  return sg ? launch_plane_v<T, DERIV, true, false>(a, s) : launch_plane_v<T, DERIV, false, false>(a, s);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_plane(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s) {
+  if (deriv == kUpwind1) return launch_plane_d<T, kUpwind1>(a, ball, s);
+  return launch_plane_d<T, kEno2>(a, ball, s);
+}
 
 template <typename T>
 hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s) {
@@ -742,6 +1003,8 @@ hipError_t launch_nonfinite(const T *src, int64_t n, int32_t *flag, hipStream_t 
 }
 
 template hipError_t launch_stream<float>(const StreamArgs<float> &, int, bool, hipStream_t);
+template hipError_t launch_plane<float>(const StreamArgs<float> &, int, bool, hipStream_t);
+template hipError_t launch_plane<double>(const StreamArgs<double> &, int, bool, hipStream_t);
 template hipError_t launch_stream<double>(const StreamArgs<double> &, int, bool, hipStream_t);
 template hipError_t launch_stage<float>(const StageArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_stage<double>(const StageArgs<double> &, int, bool, hipStream_t);
