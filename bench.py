@@ -41,14 +41,15 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def algorithmic_bytes_per_launch(npts: int, elem: int, integrator: str) -> float:
-    """Bytes a stage must move with ideal on-chip reuse (ghosts excluded).
-    Euler: read V, read V0, write V' (3 arrays).  TVD-RK2: stage 1 reads V^n
-    and writes V^1 (2 arrays); stage 2 reads V^1, V^n, V0 and writes V^(n+1)
-    (4 arrays); both stages run the same kernel, so the average launch moves
-    3 arrays."""
-    arrays = 3.0 if integrator == "euler" else (2.0 + 4.0) / 2.0
-    return arrays * elem * npts
+def algorithmic_bytes_per_launch(npts: int, info: dict, integrator: str) -> float:
+    """Bytes a stage must move with ideal on-chip reuse (ghosts excluded),
+    from the library's byte model of the mode that ran: each array read once
+    and written once per stage.  TVD-RK2: stage 1 reads V^n and writes V^1;
+    stage 2 reads V^1 and V^n, reads V0 unless the target is the Nx*Ny table
+    of a cylinder target (constant over v, theta), and writes V^(n+1).  Both
+    stages run the same kernel, so a launch moves half a step's bytes."""
+    launches = 1 if integrator == "euler" else 2
+    return info["bytes_per_point_step"] * npts / launches
 
 
 def measured_traffic(npts_expected: int):
@@ -143,13 +144,13 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = g.profile()
+    launch = g.launch_info()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     g.close()
 
     steps_per_solve = info["steps"]
     value = npts * steps_per_solve * args.steps / wall
-    elem = 4 if wl.precision == "f32" else 8
-    bpl = algorithmic_bytes_per_launch(npts, elem, wl.scheme["integrator"])
+    bpl = algorithmic_bytes_per_launch(npts, launch, wl.scheme["integrator"])
     avg_launch_s = prof["loop_ms"] / 1e3 / prof["step_launches"]
     achieved = bpl / avg_launch_s / 1e9
     traffic = measured_traffic(npts)
@@ -175,6 +176,9 @@ def main() -> int:
             "steps_per_solve": steps_per_solve,
             "dt": info["dt"],
             "obstacles": wl.obstacles,
+            "stage_kernel": launch["kernel"],
+            "x_chunks": launch["x_chunks"],
+            "target": "xy table (cylinders)" if launch["target_xy"] else "4D V0",
         },
         "roofline": {
             "bound": "hbm",
@@ -185,6 +189,7 @@ def main() -> int:
             "traffic": traffic,
             "kernel": "stage kernel (both TVD-RK2 stages)",
             "bytes_per_launch": bpl,
+            "bytes_per_point_step": launch["bytes_per_point_step"],
             "avg_launch_us": avg_launch_s * 1e6,
             "launches_timed": prof["step_launches"],
         },

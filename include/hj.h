@@ -200,6 +200,31 @@ hj_status hj_set_profiling(hj_grid *g, int32_t enable);
 /* Read the step-loop timing (synchronises the stream). */
 hj_status hj_get_profile(hj_grid *g, hj_profile *out);
 
+/* How the time step runs on this handle.  kernel: 2 = LDS plane kernel, 1 =
+ * streaming kernel, 0 = one-thread-per-node kernel (chosen by grid shape,
+ * then by hj_autotune).  x_chunks: how many pieces each x sweep is split
+ * into.  target_xy: 1 if the target is constant over (v, theta) (set by
+ * hj_set_target_cylinders) and the clamp reads an Nx*Ny table instead of
+ * the 4D V0.  bytes_per_point_step: algorithmic HBM bytes one full step moves
+ * per grid node in this mode (each array read once and written once per
+ * stage). */
+typedef struct {
+  int32_t kernel, x_chunks, target_xy, autotuned;
+  double bytes_per_point_step;
+} hj_launch_info;
+
+hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
+
+/* Time the candidate launch configurations (stage kernel that fits the
+ * shape, x-chunk counts 1..8) on the handle's current buffers and keep the
+ * fastest; a few milliseconds, synchronises.  The result of a solve does
+ * not depend on the choice (every candidate evaluates each node with the
+ * same arithmetic).  hj_solve_brt calls it on first use unless disabled by
+ * hj_set_autotune(g, 0) or fixed by the HJ_X_CHUNKS / HJ_STAGE_KERNEL
+ * environment variables.  Requires a target (HJ_ERR_NOT_READY). */
+hj_status hj_autotune(hj_grid *g);
+hj_status hj_set_autotune(hj_grid *g, int32_t enable);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *hj_last_error(void);
 

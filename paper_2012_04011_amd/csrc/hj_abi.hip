@@ -59,6 +59,11 @@ struct hj_grid {
   // stage kernel: 2 = plane (LDS), 1 = streaming, 0 = generic
   int kernel = 0;
   int x_chunks = 1;
+  bool plane_ok = false, stream_ok = false;
+  bool launch_fixed = false;   // kernel / chunks forced by the environment
+  bool autotune_on = true, autotuned = false;
+  void *v0xy = nullptr;        // target as an n0 x n1 table when constant over (v, theta)
+  bool target_xy = false;
   double *lut64 = nullptr;  // ax | ay in FP64 for the CFL reduction
   double *amax_dev = nullptr;
   int32_t *flag_dev = nullptr;
@@ -236,7 +241,7 @@ T *buf(void *p) {
 }
 
 void free_all(hj_grid *G) {
-  void *ptrs[] = {G->v0, G->v, G->w1, G->w2, G->lut, G->coef, G->lut64, G->amax_dev, G->flag_dev};
+  void *ptrs[] = {G->v0, G->v, G->w1, G->w2, G->lut, G->coef, G->v0xy, G->lut64, G->amax_dev, G->flag_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (G->amax_host) (void)hipHostFree(G->amax_host);
@@ -446,6 +451,7 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   a.chunk_len = (g.n[0] + a.n_chunks - 1) / a.n_chunks;
   a.n_chunks = (g.n[0] + a.chunk_len - 1) / a.chunk_len;
   a.coef = buf<const T>(G->coef);
+  a.v0xy = G->target_xy ? buf<const T>(G->v0xy) : nullptr;
   // uniform v and theta coefficients: b = bv / bth, alpha = av / ath
   a.kp_v = (T)((G->bv + G->av) / (2.0 * G->h[2]));
   a.km_v = (T)((G->bv - G->av) / (2.0 * G->h[2]));
@@ -523,6 +529,72 @@ hj_status reset_value(hj_grid *G) {
   return HJ_OK;
 }
 
+// Time `reps` full steps of the current configuration on scratch buffers:
+// stage 1 reads V and writes w1, stage 2 reads w1 and V and writes w2 (no
+// swap), so V is left as it was.  Returns milliseconds per step.
+template <typename T>
+hj_status time_config(hj_grid *G, int reps, hipEvent_t e0, hipEvent_t e1, float *ms) {
+  hj_status st;
+  int clamp = G->sch.clamp == HJ_CLAMP_MIN_V0;
+  const T *v = buf<const T>(G->v);
+  auto one = [&]() -> hj_status {
+    if (G->sch.integrator == HJ_EULER)
+      return launch_one_stage<T>(G, v, nullptr, buf<T>(G->w2), hj::kPlain, clamp, G->dt_cfl);
+    hj_status s1 = launch_one_stage<T>(G, v, nullptr, buf<T>(G->w1), hj::kPlain, 0, G->dt_cfl);
+    if (s1 != HJ_OK) return s1;
+    return launch_one_stage<T>(G, buf<const T>(G->w1), v, buf<T>(G->w2), hj::kAverage, clamp, G->dt_cfl);
+  };
+  if ((st = one()) != HJ_OK) return st;  // warm-up
+  HJ_HIP(hipEventRecord(e0, S(G)));
+  for (int i = 0; i < reps; ++i)
+    if ((st = one()) != HJ_OK) return st;
+  HJ_HIP(hipEventRecord(e1, S(G)));
+  HJ_HIP(hipEventSynchronize(e1));
+  HJ_HIP(hipEventElapsedTime(ms, e0, e1));
+  *ms /= reps;
+  return HJ_OK;
+}
+
+hj_status autotune(hj_grid *G) {
+  hj_status st;
+  if ((st = ensure_dt(G)) != HJ_OK) return st;
+  if (isinf(G->dt_cfl) || (!G->plane_ok && !G->stream_ok)) {
+    G->autotuned = true;
+    return HJ_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HJ_HIP(hipEventCreate(&e0));
+  HJ_HIP(hipEventCreate(&e1));
+  int best_k = G->kernel, best_c = G->x_chunks;
+  float best = INFINITY;
+  int kernels[2] = {2, 1};
+  int cap = G->g.n[0] / 4 > 1 ? G->g.n[0] / 4 : 1;
+  for (int kk = 0; kk < 2 && st == HJ_OK; ++kk) {
+    int k = kernels[kk];
+    if ((k == 2 && !G->plane_ok) || (k == 1 && !G->stream_ok)) continue;
+    for (int c = 1; c <= 8 && c <= cap; ++c) {
+      G->kernel = k;
+      G->x_chunks = c;
+      float ms = 0;
+      st = G->elem == 4 ? time_config<float>(G, 2, e0, e1, &ms) : time_config<double>(G, 2, e0, e1, &ms);
+      if (st != HJ_OK) break;
+      if (getenv("HJ_AUTOTUNE_VERBOSE"))
+        fprintf(stderr, "hj_autotune: kernel %d chunks %d: %.1f us per step\n", k, c, ms * 1e3);
+      if (ms < best) {
+        best = ms;
+        best_k = k;
+        best_c = c;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  G->kernel = best_k;
+  G->x_chunks = best_c;
+  if (st == HJ_OK) G->autotuned = true;
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -558,12 +630,16 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     int64_t plane_runs = (int64_t)grid->n[2] * (grid->n[3] / run);
     bool plane_ok = stream_ok && plane_runs <= hj::kPlaneMaxThreads &&
                     2 * (int64_t)grid->n[2] * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
+    G->plane_ok = plane_ok;
+    G->stream_ok = stream_ok;
     G->kernel = plane_ok ? 2 : (stream_ok ? 1 : 0);
     const char *force = getenv("HJ_STAGE_KERNEL");
     if (force) {
       if (!strcmp(force, "generic")) G->kernel = 0;
       if (!strcmp(force, "stream") && stream_ok) G->kernel = 1;
+      G->launch_fixed = true;
     }
+    if (getenv("HJ_X_CHUNKS")) G->launch_fixed = true;
     int64_t slab_runs = (int64_t)grid->n[1] * plane_runs;
     G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1], slab_runs, G->kernel == 2);
   }
@@ -576,6 +652,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   if (e == hipSuccess && rk2) e = hipMalloc(&G->w1, bytes);
   if (e == hipSuccess) e = hipMalloc(&G->lut, 4 * m * G->elem);
   if (e == hipSuccess) e = hipMalloc(&G->coef, 4 * m * G->elem);
+  if (e == hipSuccess) e = hipMalloc(&G->v0xy, (size_t)grid->n[0] * grid->n[1] * G->elem);
   if (e == hipSuccess) e = hipMalloc(&G->lut64, 2 * m * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&G->amax_dev, 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&G->flag_dev, sizeof(int32_t));
@@ -631,6 +708,7 @@ hj_status hj_set_target(hj_grid *G, const void *v0, int32_t dtype, int32_t where
   if ((st = import_array(G, G->v0, v0, dtype, where)) != HJ_OK) return st;
   if ((st = reset_value(G)) != HJ_OK) return st;
   G->has_target = true;
+  G->target_xy = false;
   return HJ_OK;
 }
 
@@ -654,6 +732,7 @@ hj_status hj_set_target_cylinders(hj_grid *G, const double *cx, const double *cy
       memset(&a, 0, sizeof a);
       a.v0 = buf<float>(G->v0);
       a.v = last ? buf<float>(G->v) : nullptr;
+      a.v0xy = buf<float>(G->v0xy);
       a.n0 = G->g.n[0];
       a.n1 = G->g.n[1];
       a.plane = (int64_t)G->g.n[2] * G->g.n[3];
@@ -674,6 +753,7 @@ hj_status hj_set_target_cylinders(hj_grid *G, const double *cx, const double *cy
       memset(&a, 0, sizeof a);
       a.v0 = buf<double>(G->v0);
       a.v = last ? buf<double>(G->v) : nullptr;
+      a.v0xy = buf<double>(G->v0xy);
       a.n0 = G->g.n[0];
       a.n1 = G->g.n[1];
       a.plane = (int64_t)G->g.n[2] * G->g.n[3];
@@ -692,6 +772,7 @@ hj_status hj_set_target_cylinders(hj_grid *G, const double *cx, const double *cy
     }
   }
   G->has_target = true;
+  G->target_xy = true;
   return HJ_OK;
 }
 
@@ -733,6 +814,8 @@ hj_status hj_solve_brt(hj_grid *G, double horizon, hj_solve_info *info) {
     dt_last = horizon - (double)(n - 1) * dt;
   }
   if ((st = reset_value(G)) != HJ_OK) return st;
+  if (n > 0 && G->autotune_on && !G->autotuned && !G->launch_fixed)
+    if ((st = autotune(G)) != HJ_OK) return st;
   bool timed = G->profiling && n > 0;
   hipEvent_t ev_b = nullptr, ev_e = nullptr;
   if (timed) {
@@ -801,6 +884,43 @@ hj_status hj_set_value(hj_grid *G, const void *v, int32_t dtype, int32_t where) 
   if ((st = all_finite(G, v, dtype, where, &ok)) != HJ_OK) return st;
   if (!ok) return fail(HJ_ERR_NONFINITE, "value contains NaN or infinity");
   return import_array(G, G->v, v, dtype, where);
+}
+
+hj_status hj_get_launch_info(hj_grid *G, hj_launch_info *out) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output");
+  out->kernel = G->kernel;
+  out->x_chunks = G->x_chunks;
+  out->target_xy = G->target_xy && G->kernel > 0;
+  out->autotuned = G->autotuned;
+  // arrays per stage: read the stencil input, write the output; stage 2 of
+  // TVD-RK2 also reads V^n; the clamp reads V0 unless it is the xy table
+  double arrays;
+  bool v0full = G->sch.clamp == HJ_CLAMP_MIN_V0 && !out->target_xy;
+  if (G->sch.integrator == HJ_EULER)
+    arrays = 2 + (v0full ? 1 : 0);
+  else
+    arrays = 2 + 3 + (v0full ? 1 : 0);
+  out->bytes_per_point_step = arrays * (double)G->elem;
+  return HJ_OK;
+}
+
+hj_status hj_autotune(hj_grid *G) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if (G->launch_fixed) return HJ_OK;
+  G->autotuned = false;
+  return autotune(G);
+}
+
+hj_status hj_set_autotune(hj_grid *G, int32_t enable) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  G->autotune_on = enable != 0;
+  return HJ_OK;
 }
 
 hj_status hj_get_num_points(hj_grid *G, int64_t *n) {

@@ -57,6 +57,7 @@ struct StreamArgs {
   const T *v0;
   T *out;
   const T *coef;
+  const T *v0xy;  // target as an n[0] x n[1] table (constant over v, theta), or null
   int32_t n[4];
   uint32_t periodic_mask;
   int32_t plane;           // n[1] * n[2] * n[3]: stride of x
@@ -102,6 +103,7 @@ template <typename T>
 struct CylinderArgs {
   T *v0;
   T *v;  // also written (V := V0); may equal nullptr
+  T *v0xy;  // the n0 x n1 table of the target
   int32_t n0, n1;
   int64_t plane;  // nodes per (x, y) pair: n[2] * n[3]
   T lo0, h0, lo1, h1;

@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
   const uint32_t total = pb * (uint32_t)nx;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vs, total);
   const __amdgpu_buffer_rsrc_t rvn = make_rsrc(a.vn, a.mode == kAverage ? total : 0u);
-  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, a.clamp ? total : 0u);
+  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, (a.clamp && !a.v0xy) ? total : 0u);
   const int x0 = chunk * a.chunk_len;
   const int x1 = min(nx, x0 + a.chunk_len);
   constexpr int FR = DERIV == kEno2 ? 2 : 1;  // the x front is plane X + FR
@@ -474,7 +474,15 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
     // pointwise streams of this plane (V^n, V0): issued now, used at the end
     T vn[R], t0[R];
     if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
-    if (a.clamp) bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+    if (a.clamp) {
+      if (a.v0xy) {
+        T tv = a.v0xy[X * ny + y];
+#pragma unroll
+        for (int j = 0; j < R; ++j) t0[j] = tv;
+      } else {
+        bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+      }
+    }
     T front[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) front[j] = pre[j];
@@ -654,7 +662,7 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   const uint32_t total = pb * (uint32_t)nx;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vs, total);
   const __amdgpu_buffer_rsrc_t rvn = make_rsrc(a.vn, a.mode == kAverage ? total : 0u);
-  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, a.clamp ? total : 0u);
+  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, (a.clamp && !a.v0xy) ? total : 0u);
   const int x0 = chunk * a.chunk_len;
   const int x1 = min(nx, x0 + a.chunk_len);
   constexpr int FR = DERIV == kEno2 ? 2 : 1;
@@ -695,7 +703,16 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     // pointwise streams of this plane (V^n, V0): issued now, used at the end
     T vn[R], t0[R];
     if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
-    if (a.clamp) bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+    if (a.clamp) {
+      if (a.v0xy) {
+        // every run of the block shares (x, y): one scalar load per plane
+        T tv = a.v0xy[X * ny + y];
+#pragma unroll
+        for (int j = 0; j < R; ++j) t0[j] = tv;
+      } else {
+        bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+      }
+    }
     T front[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) front[j] = pre[j];
@@ -831,16 +848,16 @@ __global__ __launch_bounds__(256) void cylinders_kernel(CylinderArgs<T> a) {
     T dist = sqrt(dx * dx + dy * dy) - a.r[o];
     best = dist < best ? dist : best;
   }
+  if (a.combine) {
+    T old = a.v0xy[ij];
+    best = old < best ? old : best;
+  }
   int64_t base = (int64_t)ij * a.plane;
   for (int64_t q = threadIdx.x; q < a.plane; q += blockDim.x) {
-    T val = best;
-    if (a.combine) {
-      T old = a.v0[base + q];
-      val = old < val ? old : val;
-    }
-    a.v0[base + q] = val;
-    if (a.v) a.v[base + q] = val;
+    a.v0[base + q] = best;
+    if (a.v) a.v[base + q] = best;
   }
+  if (threadIdx.x == 0) a.v0xy[ij] = best;
 }
 
 __device__ inline double wave_max(double x) {

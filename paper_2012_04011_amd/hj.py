@@ -38,7 +38,8 @@ STATUS_NAMES = {0: "HJ_OK", 1: "HJ_ERR_INVALID_ARG", 2: "HJ_ERR_OUT_OF_MEMORY", 
 EXPORTED = [
     "hj_grid_create", "hj_grid_destroy", "hj_set_target", "hj_set_target_cylinders", "hj_solve_brt",
     "hj_step", "hj_get_cfl_dt", "hj_get_alpha_max", "hj_get_value", "hj_get_target", "hj_set_value",
-    "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_last_error", "hj_version",
+    "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_get_launch_info", "hj_autotune",
+    "hj_set_autotune", "hj_last_error", "hj_version",
 ]
 
 
@@ -67,6 +68,14 @@ class hj_scheme_desc(ctypes.Structure):
 class hj_solve_info(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("dt", ctypes.c_double), ("dt_last", ctypes.c_double),
                 ("t_final", ctypes.c_double)]
+
+
+class hj_launch_info(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("x_chunks", ctypes.c_int32), ("target_xy", ctypes.c_int32),
+                ("autotuned", ctypes.c_int32), ("bytes_per_point_step", ctypes.c_double)]
+
+
+KERNEL_NAMES = {0: "generic", 1: "stream", 2: "plane"}
 
 
 class hj_profile(ctypes.Structure):
@@ -102,6 +111,9 @@ def load_library(path: str = LIB_PATH):
         "hj_get_num_points": [vp, P(i64)],
         "hj_set_profiling": [vp, i32],
         "hj_get_profile": [vp, P(hj_profile)],
+        "hj_get_launch_info": [vp, P(hj_launch_info)],
+        "hj_autotune": [vp],
+        "hj_set_autotune": [vp, i32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -279,6 +291,21 @@ def hj_get_profile(h: int) -> dict:
     return {"solves": p.solves, "step_launches": p.step_launches, "loop_ms": p.loop_ms}
 
 
+def hj_get_launch_info(h: int) -> dict:
+    li = hj_launch_info()
+    _check(load_library().hj_get_launch_info(h, ctypes.byref(li)), "hj_get_launch_info")
+    return {"kernel": KERNEL_NAMES.get(li.kernel, li.kernel), "x_chunks": li.x_chunks, "target_xy": bool(li.target_xy),
+            "autotuned": bool(li.autotuned), "bytes_per_point_step": li.bytes_per_point_step}
+
+
+def hj_autotune(h: int) -> None:
+    _check(load_library().hj_autotune(h), "hj_autotune")
+
+
+def hj_set_autotune(h: int, enable: bool) -> None:
+    _check(load_library().hj_set_autotune(h, 1 if enable else 0), "hj_set_autotune")
+
+
 def hj_last_error() -> str:
     return load_library().hj_last_error().decode()
 
@@ -359,3 +386,12 @@ class Grid:
 
     def profile(self) -> dict:
         return hj_get_profile(self.handle)
+
+    def launch_info(self) -> dict:
+        return hj_get_launch_info(self.handle)
+
+    def autotune(self):
+        hj_autotune(self.handle)
+
+    def set_autotune(self, enable: bool):
+        hj_set_autotune(self.handle, enable)

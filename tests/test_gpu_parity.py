@@ -427,3 +427,53 @@ def test_each_stage_kernel_one_step(monkeypatch, kernel, shape, deriv, integ, pr
         assert not bad.any(), (int(bad.sum()), float(np.abs(V - ref).max()))
     else:
         assert bad.mean() <= 1e-4, int(bad.sum())
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_kernels_and_target_forms_bitwise_equal(monkeypatch, precision):
+    """The plane and streaming kernels and every x-chunking evaluate each node
+    with the same arithmetic, and the clamp gives the same result from the
+    cylinder target's x-y table as from the full 4D target: all bitwise
+    equal (so the autotuner's choice cannot change a result)."""
+    from paper_2012_04011_amd import hj
+
+    wl = W.ENO_60_DIST
+    cyl = W.cylinders(2, wl.obstacles)
+    outs = {}
+    for kernel, chunks, form in [("plane", "3", "xy"), ("plane", "7", "xy"), ("stream", "2", "xy"),
+                                 ("stream", "5", "4d"), ("plane", "4", "4d")]:
+        monkeypatch.setenv("HJ_X_CHUNKS", chunks)
+        if kernel == "stream":
+            monkeypatch.setenv("HJ_STAGE_KERNEL", "stream")
+        else:
+            monkeypatch.delenv("HJ_STAGE_KERNEL", raising=False)
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, precision) as g:
+            g.set_target_cylinders(*cyl)
+            if form == "4d":
+                g.set_target(g.target(np.float32 if precision == "f32" else np.float64))
+            info = g.launch_info()
+            assert info["kernel"] == kernel
+            assert info["target_xy"] == (form == "xy")
+            for _ in range(6):
+                g.step()
+            outs[(kernel, chunks, form)] = g.value()
+    ref = next(iter(outs.values()))
+    for k, v in outs.items():
+        assert np.array_equal(v, ref), k
+
+
+def test_autotune_and_launch_info():
+    from paper_2012_04011_amd import hj
+
+    wl = W.ENO_60_DIST
+    with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32") as g:
+        with pytest.raises(hj.HJError):
+            g.autotune()  # no target yet
+        g.set_target_cylinders(*W.cylinders(0, wl.obstacles))
+        before = g.launch_info()
+        assert not before["autotuned"] and before["bytes_per_point_step"] == 20.0
+        g.solve_brt(0.1)
+        after = g.launch_info()
+        assert after["autotuned"] and after["kernel"] in ("plane", "stream") and 1 <= after["x_chunks"] <= 8
+        g.set_target(g.target())
+        assert g.launch_info()["bytes_per_point_step"] == 24.0
