@@ -15,6 +15,13 @@ with HIP events on the stream the kernels run on) and the FP64 CPU oracle
 timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+HBM traffic of the stage kernel (the roofline's `traffic`) comes from two
+rocprofv3 counter runs of this script (FETCH_SIZE, then WRITE_SIZE), each
+scaled by what the same counter reads for a plain device copy of known size:
+
+    python bench.py --copy-calibration          # the copy, under --pmc
+    python bench.py --summarize-traffic DIR     # DIR/{stage,copy}_{fetch,write}
 """
 
 from __future__ import annotations
@@ -65,6 +72,94 @@ def measured_traffic(npts_expected: int):
     return t.get("bytes_per_launch")
 
 
+COPY_MIB = 512
+
+
+def copy_calibration() -> int:
+    """A plain device-to-device copy of COPY_MIB MiB, five times: the known
+    byte count that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    n = COPY_MIB * 2**20 // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "dispatches": 5}}),
+          flush=True)
+    return 0
+
+
+def _counter_rows(run_dir: str, counter: str):
+    """(dispatch id, kernel name, value) of one counter from a rocprofv3
+    --output-format csv run directory."""
+    import csv
+    import glob
+
+    out = []
+    for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def summarize_traffic(root: str, last: int = 200) -> int:
+    """Per-launch HBM bytes of the stage kernel from the counter runs under
+    root (stage_fetch, stage_write: this script's default step under
+    --pmc FETCH_SIZE / WRITE_SIZE; copy_fetch, copy_write: --copy-calibration).
+    Counters are KiB per dispatch; each is scaled by copy bytes / copy counter.
+    The last `last` stage dispatches (alternating TVD-RK2 stages 1 and 2 of
+    the timed solve) are averaged.  Writes the JSON that the benchmark reads
+    and prints a text summary."""
+    import numpy as np
+
+    from paper_2012_04011_amd import workloads as W
+
+    copy_bytes = COPY_MIB * 2**20
+    res = {}
+    for counter, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        stage = [r for r in _counter_rows(os.path.join(root, "stage_" + key), counter) if "stage_" in r[1]]
+        copy = [r for r in _counter_rows(os.path.join(root, "copy_" + key), counter)
+                if "stage_" not in r[1] and "copy" in r[1].lower()]
+        if len(stage) < last or not copy:
+            print(f"summarize-traffic: {key}: {len(stage)} stage and {len(copy)} copy dispatches found",
+                  file=sys.stderr)
+            return 1
+        v = np.array([r[2] for r in stage[-last:]])
+        kib_copy = float(np.median([r[2] for r in copy]))
+        factor = copy_bytes / (kib_copy * 1024.0)
+        res[key] = {"stage1_kib": float(v[0::2].mean()), "stage2_kib": float(v[1::2].mean()),
+                    "copy_kib": kib_copy, "factor": factor, "kernel": stage[-1][1]}
+    f, w = res["fetch"], res["write"]
+    s1 = (f["stage1_kib"] * f["factor"] + w["stage1_kib"] * w["factor"]) * 1024.0
+    s2 = (f["stage2_kib"] * f["factor"] + w["stage2_kib"] * w["factor"]) * 1024.0
+    out = {
+        "kernel_source_sha256_16": kernel_source_hash(),
+        "points": W.LARGE_120.points,
+        "bytes_per_launch": (s1 + s2) / 2.0,
+        "stage1_bytes": s1,
+        "stage2_bytes": s2,
+        "fetch": f,
+        "write": w,
+        "copy_bytes": copy_bytes,
+    }
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"kernel: {f['kernel']}")
+    print(f"copy of {copy_bytes} B: FETCH_SIZE {f['copy_kib']:.1f} KiB (x{f['factor']:.3f}), "
+          f"WRITE_SIZE {w['copy_kib']:.1f} KiB (x{w['factor']:.3f})")
+    for i, b in ((1, s1), (2, s2)):
+        print(f"stage {i}: FETCH_SIZE {f[f'stage{i}_kib']:.1f} KiB, WRITE_SIZE {w[f'stage{i}_kib']:.1f} KiB "
+              f"-> {b / 1e6:.1f} MB per launch (calibrated)")
+    print(f"mean per launch: {out['bytes_per_launch'] / 1e6:.1f} MB; wrote {os.path.relpath(TRAFFIC_FILE, ROOT)}")
+    return 0
+
+
 def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     """The FP64 oracle on the host cores: whole RK2 steps of the same
     workload from its seed-0 target, as many as fit the time budget."""
@@ -103,7 +198,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--summarize-traffic", metavar="DIR")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        return summarize_traffic(args.summarize_traffic)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split is "
               "design-only", file=sys.stderr)
@@ -118,6 +217,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.copy_calibration:
+        return copy_calibration()
     hj.load_library()
     torch.cuda.set_device(0)
     wl = W.LARGE_120

@@ -576,7 +576,7 @@ hj_status autotune(hj_grid *G) {
       G->kernel = k;
       G->x_chunks = c;
       float ms = 0;
-      st = G->elem == 4 ? time_config<float>(G, 2, e0, e1, &ms) : time_config<double>(G, 2, e0, e1, &ms);
+      st = G->elem == 4 ? time_config<float>(G, 5, e0, e1, &ms) : time_config<double>(G, 5, e0, e1, &ms);
       if (st != HJ_OK) break;
       if (getenv("HJ_AUTOTUNE_VERBOSE"))
         fprintf(stderr, "hj_autotune: kernel %d chunks %d: %.1f us per step\n", k, c, ms * 1e3);
