@@ -225,6 +225,64 @@ hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
 hj_status hj_autotune(hj_grid *g);
 hj_status hj_set_autotune(hj_grid *g, int32_t enable);
 
+/* ---- Batched solves ------------------------------------------------------
+ * Many independent BRT re-solves (different grids, obstacle sets and
+ * horizons) run together on one device.  The paper solves one grid at a
+ * time; a batch instance computes exactly what hj_solve_brt computes for its
+ * handle (bitwise the same V), since every node's update depends only on the
+ * previous step of its own grid (Algorithm 2, one sweep per step). */
+typedef struct hj_batch hj_batch;
+
+enum {
+  HJ_BATCH_LAUNCHES = 0,   /* one launch per (step, stage) over every instance still running */
+  HJ_BATCH_GRAPH = 1,      /* the same launches, captured once as a hipGraph and replayed */
+  HJ_BATCH_PERSISTENT = 2  /* one persistent launch for the whole batch (work queue) */
+};
+
+typedef struct {
+  int32_t m;                  /* instances */
+  int32_t x_planes;           /* x planes per tile (tile = 256 runs of theta nodes x x_planes) */
+  int32_t persistent_blocks;  /* blocks of the last persistent launch */
+  int32_t graph_nodes;        /* kernel nodes of the cached graph (0: none) */
+  int64_t tiles_per_sweep;    /* tiles of one stage over all instances */
+  int64_t work_items;         /* tiles over all stages of the last solve */
+  int64_t points;             /* grid nodes over all instances */
+} hj_batch_info;
+
+/* Group m (1..256) grid handles.  They must share precision, derivative
+ * scheme, integrator, device and stream, and have a periodic theta axis;
+ * grids, dynamics, obstacle sets and clamp may differ.  The handles stay
+ * owned by the caller and must outlive the batch; while a batch call runs,
+ * no other call may use them.  Errors: HJ_ERR_INVALID_ARG (null, repeated
+ * handle, m out of range), HJ_ERR_UNSUPPORTED (mixed schemes, streams or a
+ * non-periodic theta). */
+hj_status hj_batch_create(hj_grid *const *grids, int32_t m, hj_batch **out);
+hj_status hj_batch_destroy(hj_batch *b);
+
+/* Solve instance j over horizons[j] (finite, >= 0; m entries) from its
+ * current target, exactly as hj_solve_brt(grids[j], horizons[j]) would, and
+ * leave V in its handle; infos (m entries) may be NULL.  Launch-mode and
+ * graph-mode calls are stream-ordered and return without waiting; the
+ * persistent mode synchronises the stream to read the work queue's error
+ * flag.  HJ_ERR_NOT_READY if an instance has no target; HJ_ERR_DEVICE if a
+ * persistent tile waited past the spin limit (values then undefined). */
+hj_status hj_batch_solve(hj_batch *b, const double *horizons, int32_t mode, hj_solve_info *infos);
+
+/* Tile shape: x planes per tile for every instance (0 = the default, 16). */
+hj_status hj_batch_set_tile(hj_batch *b, int32_t x_planes);
+
+/* Polls a persistent tile makes of its dependency counter before it gives up
+ * and raises the error flag (default 2^21, about a second; 0 = give up at
+ * once).  The kernel always ends. */
+hj_status hj_batch_set_spin_limit(hj_batch *b, int64_t polls);
+
+/* Time complete batch solves (horizons, mode) for each candidate tile
+ * length (4, 8, 12, 16, 24, 32, 48, 80 x planes), keep the fastest and
+ * report it.  Synchronises; leaves every instance holding its solve. */
+hj_status hj_batch_autotune(hj_batch *b, const double *horizons, int32_t mode, int32_t *x_planes_out);
+
+hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *hj_last_error(void);
 

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/hj.h"
@@ -408,6 +409,20 @@ hj_status ensure_dt(hj_grid *G) {
   return HJ_OK;
 }
 
+// Fixed horizon: n = ceil(T / dt) steps of the CFL step dt, the last one
+// shortened to T - (n - 1) dt (a zero CFL sum, i.e. nothing moves, makes one
+// step of the whole horizon).  Needs ensure_dt.
+void schedule(const hj_grid *G, double horizon, int64_t *n, double *dt, double *dt_last) {
+  *dt = isinf(G->dt_cfl) ? horizon : G->dt_cfl;
+  *n = 0;
+  *dt_last = 0.0;
+  if (horizon > 0.0) {
+    *n = (int64_t)ceil(horizon / *dt);
+    if (*n < 1) *n = 1;
+    *dt_last = horizon - (double)(*n - 1) * *dt;
+  }
+}
+
 template <typename T>
 hj::StageArgs<T> stage_args(hj_grid *G) {
   hj::StageArgs<T> a;
@@ -439,11 +454,12 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   hj::StreamArgs<T> a;
   memset(&a, 0, sizeof a);
   const hj_grid_desc &g = G->g;
-  const int run = hj::stream_run<T>();
+  const int run = hj::run_length((int)sizeof(T), g.n[3]);
   for (int d = 0; d < 4; ++d) a.n[d] = g.n[d];
   a.periodic_mask = g.periodic_mask;
   a.plane = g.n[1] * g.n[2] * g.n[3];
   a.row = g.n[2] * g.n[3];
+  a.run = run;
   a.runs_per_row = g.n[3] / run;
   a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
   a.blocks_per_chunk = G->kernel == 2 ? g.n[1] : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
@@ -622,11 +638,10 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   build_coef(G, tab, coef);
   int64_t m = (int64_t)grid->n[2] * grid->n[3];
   {
-    int run = scheme->precision == HJ_F32 ? hj::stream_run<float>() : hj::stream_run<double>();
-    // theta periodic and a whole number of runs per row; 32-bit byte
-    // offsets (buffer addressing) need each array below 4 GiB
-    bool stream_ok = bit(grid->periodic_mask, 3) && grid->n[3] % run == 0 &&
-                     G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
+    int run = hj::run_length(G->elem, grid->n[3]);
+    // theta periodic; 32-bit byte offsets (buffer addressing) need each
+    // array below 4 GiB
+    bool stream_ok = bit(grid->periodic_mask, 3) && G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
     int64_t plane_runs = (int64_t)grid->n[2] * (grid->n[3] / run);
     bool plane_ok = stream_ok && plane_runs <= hj::kPlaneMaxThreads &&
                     2 * (int64_t)grid->n[2] * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
@@ -803,16 +818,9 @@ hj_status hj_solve_brt(hj_grid *G, double horizon, hj_solve_info *info) {
   if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
   if ((st = set_device(G)) != HJ_OK) return st;
   if ((st = ensure_dt(G)) != HJ_OK) return st;
-  // fixed horizon: n = ceil(T / dt) steps, the last shortened (a zero CFL
-  // sum, i.e. nothing moves, makes one step of the whole horizon)
-  double dt = isinf(G->dt_cfl) ? horizon : G->dt_cfl;
-  int64_t n = 0;
-  double dt_last = 0.0;
-  if (horizon > 0.0) {
-    n = (int64_t)ceil(horizon / dt);
-    if (n < 1) n = 1;
-    dt_last = horizon - (double)(n - 1) * dt;
-  }
+  double dt, dt_last;
+  int64_t n;
+  schedule(G, horizon, &n, &dt, &dt_last);
   if ((st = reset_value(G)) != HJ_OK) return st;
   if (n > 0 && G->autotune_on && !G->autotuned && !G->launch_fixed)
     if ((st = autotune(G)) != HJ_OK) return st;
@@ -948,6 +956,437 @@ hj_status hj_get_profile(hj_grid *G, hj_profile *out) {
   if ((st = set_device(G)) != HJ_OK) return st;
   if ((st = fold_events(G)) != HJ_OK) return st;
   *out = G->prof;
+  return HJ_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched solves
+// ===========================================================================
+
+struct hj_batch {
+  std::vector<hj_grid *> g;
+  int m = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream the graph is captured on
+  int device = 0;
+  size_t elem = 4;
+  int deriv = 0;
+  bool rk2 = false, sg = false, ball = false;
+  int32_t x_planes = 0;  // 0: automatic
+  int64_t spin_limit = (int64_t)1 << 21;
+  int cus = 0;
+
+  void *inst_dev = nullptr;   // BatchInst<T>[m], sorted by step count
+  void *inst_host = nullptr;  // pinned staging of the same
+  int32_t *ints_dev = nullptr;   // tile_end[m] | start[nphase + 1] | active[nphase]
+  int32_t *ints_host = nullptr;  // pinned
+  size_t ints_cap = 0;           // entries
+  hipEvent_t staged = nullptr;   // the last upload from the pinned buffers
+  hj::BatchQueue *queue = nullptr;
+  int32_t *err_host = nullptr;   // pinned
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gkey;
+  int32_t graph_nodes = 0;
+
+  hj_batch_info info = {};
+};
+
+namespace {
+
+void batch_free(hj_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  void *dev[] = {b->inst_dev, b->ints_dev, b->queue};
+  for (void *p : dev)
+    if (p) (void)hipFree(p);
+  void *host[] = {b->inst_host, b->ints_host, b->err_host};
+  for (void *p : host)
+    if (p) (void)hipHostFree(p);
+}
+
+constexpr int32_t kBatchDefaultXPlanes = 16;
+
+int32_t batch_x_planes(const hj_batch *b) { return b->x_planes > 0 ? b->x_planes : kBatchDefaultXPlanes; }
+
+// x chunks of a grid in a batch: ceil(N_x / x planes per tile)
+int batch_chunks(const hj_batch *b, const hj_grid *G) {
+  int xp = batch_x_planes(b);
+  return (G->g.n[0] + xp - 1) / xp;
+}
+
+template <typename T>
+hj::StreamArgs<T> batch_stream_args(hj_grid *G, int n_chunks) {
+  hj::StreamArgs<T> a = stream_args<T>(G);
+  a.blocks_per_chunk = (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  int nx = G->g.n[0];
+  if (n_chunks > nx) n_chunks = nx;
+  a.chunk_len = (nx + n_chunks - 1) / n_chunks;
+  a.n_chunks = (nx + a.chunk_len - 1) / a.chunk_len;
+  return a;
+}
+
+struct BatchPlan {
+  std::vector<int> order;      // sorted position -> instance
+  std::vector<int64_t> steps;  // per instance
+  std::vector<double> dt, dt_last;
+  std::vector<int32_t> tiles;  // per sorted position
+  std::vector<int32_t> tile_end, start, active;
+  int nphase = 0, pps = 1;
+};
+
+// Step schedules, the sorted order and the host tables of one batch solve.
+template <typename T>
+hj_status batch_plan(hj_batch *b, const double *horizons, BatchPlan *P) {
+  hj_status st;
+  const int m = b->m;
+  P->steps.resize(m);
+  P->dt.resize(m);
+  P->dt_last.resize(m);
+  int64_t points = 0;
+  for (int j = 0; j < m; ++j) {
+    hj_grid *G = b->g[j];
+    if ((st = ensure_dt(G)) != HJ_OK) return st;
+    schedule(G, horizons[j], &P->steps[j], &P->dt[j], &P->dt_last[j]);
+    if (P->steps[j] > ((int64_t)1 << 24)) return fail(HJ_ERR_INVALID_ARG, "instance %d: %lld steps", j, (long long)P->steps[j]);
+    points += G->npts;
+  }
+  P->order.resize(m);
+  for (int j = 0; j < m; ++j) P->order[j] = j;
+  std::stable_sort(P->order.begin(), P->order.end(), [&](int x, int y) { return P->steps[x] > P->steps[y]; });
+  P->pps = b->rk2 ? 2 : 1;
+  int64_t maxn = P->steps[P->order[0]];
+  P->nphase = (int)(maxn * P->pps);
+  hj::BatchInst<T> *inst = static_cast<hj::BatchInst<T> *>(b->inst_host);
+  P->tiles.resize(m);
+  P->tile_end.resize(m);
+  int64_t acc = 0;
+  for (int i = 0; i < m; ++i) {
+    const int j = P->order[i];
+    hj_grid *G = b->g[j];
+    hj::BatchInst<T> &in = inst[i];
+    memset(&in, 0, sizeof in);
+    in.a = batch_stream_args<T>(G, batch_chunks(b, G));
+    in.v0 = buf<const T>(G->v0);
+    in.va = buf<T>(G->v);
+    in.vb = buf<T>(G->w2);
+    in.w1 = b->rk2 ? buf<T>(G->w1) : nullptr;
+    in.dt = (T)P->dt[j];
+    in.dt_last = (T)P->dt_last[j];
+    in.steps = (int32_t)P->steps[j];
+    in.rk2 = b->rk2 ? 1 : 0;
+    in.clamp = G->sch.clamp == HJ_CLAMP_MIN_V0 ? 1 : 0;
+    in.tiles = in.a.blocks_per_chunk * in.a.n_chunks;
+    P->tiles[i] = in.tiles;
+    acc += in.tiles;
+    if (acc >= ((int64_t)1 << 30)) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
+    P->tile_end[i] = (int32_t)acc;
+  }
+  P->active.resize(P->nphase);
+  P->start.resize(P->nphase + 1);
+  int64_t items = 0;
+  int act = m;
+  for (int p = 0; p < P->nphase; ++p) {
+    int64_t k = p / P->pps;
+    while (act > 0 && P->steps[P->order[act - 1]] <= k) --act;
+    P->active[p] = act;
+    P->start[p] = (int32_t)items;
+    items += P->tile_end[act - 1];
+    if (items >= ((int64_t)1 << 31) - 1) return fail(HJ_ERR_UNSUPPORTED, "batch work list too long");
+  }
+  P->start[P->nphase] = (int32_t)items;
+  b->info.tiles_per_sweep = acc;
+  b->info.work_items = items;
+  b->info.points = points;
+  return HJ_OK;
+}
+
+// Upload the instance table and the int tables (tile_end | start | active)
+// from the pinned staging buffers (which must not be rewritten before the
+// copy has run: the caller waits on b->staged first).
+template <typename T>
+hj_status batch_upload(hj_batch *b, const BatchPlan &P) {
+  size_t need = (size_t)b->m + P.start.size() + P.active.size();
+  if (need > b->ints_cap) {
+    HJ_HIP(hipStreamSynchronize(b->stream));  // earlier launches may still read the old tables
+    if (b->ints_dev) HJ_HIP(hipFree(b->ints_dev));
+    if (b->ints_host) HJ_HIP(hipHostFree(b->ints_host));
+    b->ints_dev = nullptr;
+    b->ints_host = nullptr;
+    b->ints_cap = 0;
+    HJ_HIP(hipMalloc(&b->ints_dev, need * sizeof(int32_t)));
+    HJ_HIP(hipHostMalloc(&b->ints_host, need * sizeof(int32_t), 0));
+    b->ints_cap = need;
+  }
+  int32_t *h = b->ints_host;
+  memcpy(h, P.tile_end.data(), b->m * sizeof(int32_t));
+  memcpy(h + b->m, P.start.data(), P.start.size() * sizeof(int32_t));
+  memcpy(h + b->m + P.start.size(), P.active.data(), P.active.size() * sizeof(int32_t));
+  HJ_HIP(hipMemcpyAsync(b->ints_dev, h, need * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+  HJ_HIP(hipMemcpyAsync(b->inst_dev, b->inst_host, b->m * sizeof(hj::BatchInst<T>), hipMemcpyHostToDevice,
+                        b->stream));
+  HJ_HIP(hipEventRecord(b->staged, b->stream));
+  return HJ_OK;
+}
+
+// One launch per (step, stage), each over the instances still running.
+template <typename T>
+hj_status batch_enqueue_launches(hj_batch *b, const BatchPlan &P, hipStream_t s, int32_t *nodes) {
+  const hj::BatchInst<T> *inst = static_cast<const hj::BatchInst<T> *>(b->inst_dev);
+  *nodes = 0;
+  for (int p = 0; p < P.nphase; ++p) {
+    int act = P.active[p];
+    HJ_HIP(hj::launch_multi<T>(inst, b->ints_dev, act, P.tile_end[act - 1], p / P.pps, p % P.pps, b->deriv, b->sg,
+                               b->ball, s));
+    *nodes += 1;
+  }
+  return HJ_OK;
+}
+
+template <typename T>
+hj_status batch_solve_t(hj_batch *b, const double *horizons, int32_t mode, hj_solve_info *infos) {
+  hj_status st;
+  HJ_HIP(hipEventSynchronize(b->staged));  // the pinned tables are free again
+  BatchPlan P;
+  if ((st = batch_plan<T>(b, horizons, &P)) != HJ_OK) return st;
+  if (P.nphase > 0) {
+    if ((st = batch_upload<T>(b, P)) != HJ_OK) return st;
+    if (mode == HJ_BATCH_LAUNCHES) {
+      int32_t nodes;
+      if ((st = batch_enqueue_launches<T>(b, P, b->stream, &nodes)) != HJ_OK) return st;
+    } else if (mode == HJ_BATCH_GRAPH) {
+      std::vector<int64_t> key;
+      key.push_back(P.pps);
+      for (int i = 0; i < b->m; ++i) {
+        key.push_back(P.steps[P.order[i]]);
+        key.push_back(P.tiles[i]);
+      }
+      if (!b->gexec || key != b->gkey) {
+        if (b->gexec) HJ_HIP(hipGraphExecDestroy(b->gexec));
+        if (b->graph) HJ_HIP(hipGraphDestroy(b->graph));
+        b->gexec = nullptr;
+        b->graph = nullptr;
+        b->gkey.clear();
+        HJ_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        int32_t nodes = 0;
+        st = batch_enqueue_launches<T>(b, P, b->cap, &nodes);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap, &gr);
+        if (st != HJ_OK) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return st;
+        }
+        HJ_HIP(e);
+        b->graph = gr;
+        HJ_HIP(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+        b->gkey = key;
+        b->graph_nodes = nodes;
+      }
+      HJ_HIP(hipGraphLaunch(b->gexec, b->stream));
+    } else {
+      hj::PersistArgs<T> pa;
+      pa.inst = static_cast<const hj::BatchInst<T> *>(b->inst_dev);
+      pa.tile_end = b->ints_dev;
+      pa.start = b->ints_dev + b->m;
+      pa.active = b->ints_dev + b->m + P.start.size();
+      pa.queue = b->queue;
+      pa.nphase = P.nphase;
+      pa.phases_per_step = P.pps;
+      pa.spin_limit = b->spin_limit;
+      int per_cu = hj::persistent_blocks_per_cu<T>(b->deriv, b->sg, b->ball);
+      int64_t blocks = (int64_t)per_cu * b->cus;
+      if (blocks > b->info.work_items) blocks = b->info.work_items;
+      if (blocks < 1) blocks = 1;
+      b->info.persistent_blocks = (int32_t)blocks;
+      HJ_HIP(hj::launch_batch_reset(b->queue, b->m, b->stream));
+      HJ_HIP(hj::launch_persistent<T>(pa, (int)blocks, b->deriv, b->sg, b->ball, b->stream));
+      HJ_HIP(hipMemcpyAsync(b->err_host, &b->queue->error, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+      HJ_HIP(hipStreamSynchronize(b->stream));
+      if (*b->err_host != 0)
+        return fail(HJ_ERR_DEVICE,
+                    "persistent batch: a tile waited longer than the spin limit for its previous phase; the "
+                    "instances' values are undefined");
+    }
+  }
+  // each instance's result is V^n: V0 (n = 0), vb (n odd: now becomes v) or va
+  for (int j = 0; j < b->m; ++j) {
+    hj_grid *G = b->g[j];
+    int64_t n = P.steps[j];
+    if (n == 0) {
+      HJ_HIP(hj::launch_copy<T>(buf<T>(G->v), buf<const T>(G->v0), G->npts, b->stream));
+    } else if (n & 1) {
+      void *t = G->v;
+      G->v = G->w2;
+      G->w2 = t;
+    }
+    if (infos) {
+      infos[j].steps = n;
+      infos[j].dt = P.dt[j];
+      infos[j].dt_last = P.dt_last[j];
+      infos[j].t_final = horizons[j];
+    }
+  }
+  b->info.graph_nodes = b->graph_nodes;
+  return HJ_OK;
+}
+
+hj_status check_batch(hj_batch *b) {
+  if (!b) return fail(HJ_ERR_INVALID_ARG, "null batch");
+  return HJ_OK;
+}
+
+hj_status check_horizons(const hj_batch *b, const double *horizons) {
+  if (!horizons) return fail(HJ_ERR_INVALID_ARG, "null horizons");
+  for (int j = 0; j < b->m; ++j)
+    if (!isfinite(horizons[j]) || horizons[j] < 0)
+      return fail(HJ_ERR_INVALID_ARG, "horizon %d must be finite and >= 0", j);
+  for (int j = 0; j < b->m; ++j)
+    if (!b->g[j]->has_target) return fail(HJ_ERR_NOT_READY, "instance %d has no target", j);
+  return HJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hj_status hj_batch_create(hj_grid *const *grids, int32_t m, hj_batch **out) {
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output handle pointer");
+  *out = nullptr;
+  if (!grids || m < 1 || m > hj::kMaxBatch)
+    return fail(HJ_ERR_INVALID_ARG, "need 1..%d grid handles (got %d)", hj::kMaxBatch, m);
+  hj_grid *G0 = grids[0];
+  for (int j = 0; j < m; ++j) {
+    hj_grid *G = grids[j];
+    if (!G) return fail(HJ_ERR_INVALID_ARG, "grid %d is null", j);
+    for (int i = 0; i < j; ++i)
+      if (grids[i] == G) return fail(HJ_ERR_INVALID_ARG, "grid %d appears twice", j);
+    if (G->elem != G0->elem || G->sch.deriv != G0->sch.deriv || G->sch.integrator != G0->sch.integrator)
+      return fail(HJ_ERR_UNSUPPORTED, "grid %d: a batch needs one precision, derivative and integrator", j);
+    if (G->device != G0->device || G->stream != G0->stream)
+      return fail(HJ_ERR_UNSUPPORTED, "grid %d: a batch needs one device and one stream", j);
+    if (!G->stream_ok)
+      return fail(HJ_ERR_UNSUPPORTED, "grid %d: batched solves need a periodic theta axis and < 4 GiB arrays", j);
+  }
+  hj_batch *b = new (std::nothrow) hj_batch;
+  if (!b) return fail(HJ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->g.assign(grids, grids + m);
+  b->m = m;
+  b->stream = G0->stream;
+  b->device = G0->device;
+  b->elem = G0->elem;
+  b->deriv = G0->sch.deriv;
+  b->rk2 = G0->sch.integrator == HJ_TVD_RK2;
+  for (hj_grid *G : b->g) {
+    if (G->sig[0] != 0.0 || G->sig[1] != 0.0) b->sg = true;
+    if (G->ball_mask != 0) b->ball = true;
+  }
+  hipError_t e = hipSetDevice(b->device);
+  size_t inst_bytes = (size_t)m * (b->elem == 4 ? sizeof(hj::BatchInst<float>) : sizeof(hj::BatchInst<double>));
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&b->inst_dev, inst_bytes);
+  if (e == hipSuccess) e = hipHostMalloc(&b->inst_host, inst_bytes, 0);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->queue, sizeof(hj::BatchQueue));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&b->err_host, sizeof(int32_t), 0);
+  if (e == hipSuccess) e = hipEventRecord(b->staged, b->stream);
+  if (e != hipSuccess) {
+    batch_free(b);
+    delete b;
+    return fail(e == hipErrorOutOfMemory ? HJ_ERR_OUT_OF_MEMORY : HJ_ERR_DEVICE, "hj_batch_create: %s",
+                hipGetErrorString(e));
+  }
+  b->info.m = m;
+  *out = b;
+  return HJ_OK;
+}
+
+hj_status hj_batch_destroy(hj_batch *b) {
+  if (!b) return HJ_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  batch_free(b);
+  delete b;
+  return HJ_OK;
+}
+
+hj_status hj_batch_solve(hj_batch *b, const double *horizons, int32_t mode, hj_solve_info *infos) {
+  hj_status st = check_batch(b);
+  if (st != HJ_OK) return st;
+  if (mode != HJ_BATCH_LAUNCHES && mode != HJ_BATCH_GRAPH && mode != HJ_BATCH_PERSISTENT)
+    return fail(HJ_ERR_INVALID_ARG, "unknown batch mode %d", mode);
+  if ((st = check_horizons(b, horizons)) != HJ_OK) return st;
+  HJ_HIP(hipSetDevice(b->device));
+  return b->elem == 4 ? batch_solve_t<float>(b, horizons, mode, infos) : batch_solve_t<double>(b, horizons, mode, infos);
+}
+
+hj_status hj_batch_set_tile(hj_batch *b, int32_t x_planes) {
+  hj_status st = check_batch(b);
+  if (st != HJ_OK) return st;
+  if (x_planes < 0) return fail(HJ_ERR_INVALID_ARG, "x_planes must be >= 0");
+  b->x_planes = x_planes;
+  return HJ_OK;
+}
+
+hj_status hj_batch_set_spin_limit(hj_batch *b, int64_t polls) {
+  hj_status st = check_batch(b);
+  if (st != HJ_OK) return st;
+  if (polls < 0) return fail(HJ_ERR_INVALID_ARG, "spin limit must be >= 0");
+  b->spin_limit = polls;
+  return HJ_OK;
+}
+
+hj_status hj_batch_autotune(hj_batch *b, const double *horizons, int32_t mode, int32_t *x_planes_out) {
+  hj_status st = check_batch(b);
+  if (st != HJ_OK) return st;
+  if (mode != HJ_BATCH_LAUNCHES && mode != HJ_BATCH_GRAPH && mode != HJ_BATCH_PERSISTENT)
+    return fail(HJ_ERR_INVALID_ARG, "unknown batch mode %d", mode);
+  if ((st = check_horizons(b, horizons)) != HJ_OK) return st;
+  HJ_HIP(hipSetDevice(b->device));
+  const int32_t cand[] = {4, 8, 12, 16, 24, 32, 48, 80};
+  hipEvent_t e0, e1;
+  HJ_HIP(hipEventCreate(&e0));
+  HJ_HIP(hipEventCreate(&e1));
+  int32_t keep = b->x_planes, best_t = 0;
+  float best = INFINITY;
+  for (int32_t t : cand) {
+    b->x_planes = t;
+    for (int rep = 0; rep < 2 && st == HJ_OK; ++rep) {  // the first run may capture a graph
+      if ((st = hipEventRecord(e0, b->stream) == hipSuccess ? HJ_OK : HJ_ERR_DEVICE) != HJ_OK) break;
+      st = b->elem == 4 ? batch_solve_t<float>(b, horizons, mode, nullptr) : batch_solve_t<double>(b, horizons, mode, nullptr);
+      if (st != HJ_OK) break;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = HJ_ERR_DEVICE;
+    }
+    if (st != HJ_OK) break;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HJ_OK) {
+    b->x_planes = keep;
+    return st == HJ_ERR_DEVICE ? fail(HJ_ERR_DEVICE, "hj_batch_autotune: device error") : st;
+  }
+  b->x_planes = best_t;
+  if (x_planes_out) *x_planes_out = best_t;
+  return HJ_OK;
+}
+
+hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out) {
+  hj_status st = check_batch(b);
+  if (st != HJ_OK) return st;
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output");
+  b->info.x_planes = batch_x_planes(b);
+  *out = b->info;
   return HJ_OK;
 }
 

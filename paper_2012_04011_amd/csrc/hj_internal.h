@@ -62,6 +62,7 @@ struct StreamArgs {
   uint32_t periodic_mask;
   int32_t plane;           // n[1] * n[2] * n[3]: stride of x
   int32_t row;             // n[2] * n[3]: stride of y
+  int32_t run;             // R, theta nodes per thread (run_length)
   int32_t runs_per_row;    // n[3] / R
   int32_t slab_runs;       // n[1] * n[2] * runs_per_row
   int32_t blocks_per_chunk;
@@ -79,10 +80,13 @@ struct StreamArgs {
 
 constexpr int kStreamBlock = 256;
 
-// Run length of the streaming kernel per precision (16-byte vector loads).
-template <typename T>
-constexpr int stream_run() {
-  return sizeof(T) == 4 ? 4 : 2;
+// Run length (theta nodes per thread) of the streaming and plane kernels:
+// the longest of 4 (FP32; 2 in FP64), 2 and 1 that divides N_theta, so runs
+// are 16-byte, 8-byte or single-element loads.
+inline int run_length(int elem, int nth) {
+  int r = elem == 4 ? 4 : 2;
+  while (r > 1 && nth % r != 0) r /= 2;
+  return r;
 }
 
 template <typename T>
@@ -96,6 +100,70 @@ constexpr int kPlaneMaxLdsBytes = 64 * 1024;
 
 template <typename T>
 hipError_t launch_plane(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s);
+
+// ---- batched solves -------------------------------------------------------
+// Instance j of a batch: the streaming-kernel description of its grid (the
+// per-phase fields vs, vn, out, dt, mode and clamp are filled in by the
+// kernels) and its time schedule.  Step k reads V^k and writes V^(k+1):
+// V^0 is the target V0 itself, V^k for k >= 1 lives in va (k even) or vb
+// (k odd).  Stage 1 of a TVD-RK2 step writes w1.
+template <typename T>
+struct BatchInst {
+  StreamArgs<T> a;
+  const T *v0;
+  T *va, *vb, *w1;
+  T dt, dt_last;   // steps 0 .. n-2 use dt, step n-1 dt_last
+  int32_t steps;   // n
+  int32_t rk2;     // 1: TVD-RK2 (two phases per step), 0: Euler (one)
+  int32_t clamp;   // min(V0, .) after the last stage of a step
+  int32_t tiles;   // blocks of one phase: a.blocks_per_chunk * a.n_chunks
+};
+
+constexpr int kMaxBatch = 256;
+
+// Device state of the persistent batch kernel: the next work item, an error
+// flag (a dependency wait ran out of spins) and, per instance, the number of
+// its tiles completed so far (over all phases).
+struct BatchQueue {
+  int32_t next;
+  int32_t error;
+  int32_t pad[2];
+  int32_t done[kMaxBatch];
+};
+
+// The persistent kernel's work list: phase p (step p / phases_per_step,
+// stage p % phases_per_step) holds the tiles of its first active[p]
+// instances (instances are sorted by step count, longest first), items
+// start[p] .. start[p+1]-1; tile_end[j] = tiles of instances 0..j.
+template <typename T>
+struct PersistArgs {
+  const BatchInst<T> *inst;
+  const int32_t *tile_end;
+  const int32_t *start;   // nphase + 1 entries
+  const int32_t *active;  // nphase entries
+  BatchQueue *queue;
+  int32_t nphase;
+  int32_t phases_per_step;
+  int64_t spin_limit;     // polls of a dependency before giving up
+};
+
+// One launch of phase (k, stage) over the first ninst instances (their
+// tiles are blocks 0 .. tile_end[ninst-1]-1, XCD-contiguous).
+template <typename T>
+hipError_t launch_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int k, int stage,
+                        int deriv, bool sg, bool ball, hipStream_t s);
+
+// The whole batch in one launch of `blocks` persistent blocks.
+template <typename T>
+hipError_t launch_persistent(const PersistArgs<T> &p, int blocks, int deriv, bool sg, bool ball, hipStream_t s);
+
+// Resident blocks per CU of the persistent kernel (occupancy).
+template <typename T>
+int persistent_blocks_per_cu(int deriv, bool sg, bool ball);
+
+// queue->next = queue->error = 0, done[0..m) = 0 (a kernel, so that the
+// sequence can be captured in a graph).
+hipError_t launch_batch_reset(BatchQueue *queue, int m, hipStream_t s);
 
 constexpr int kMaxCylindersPerLaunch = 32;
 

@@ -183,14 +183,8 @@ __global__ __launch_bounds__(256) void stage_generic(StageArgs<T> a) {
 // ---------------------------------------------------------------------------
 
 template <typename T, int R>
-struct VecT;
-template <>
-struct VecT<float, 4> {
-  typedef float type __attribute__((ext_vector_type(4)));
-};
-template <>
-struct VecT<double, 2> {
-  typedef double type __attribute__((ext_vector_type(2)));
+struct VecT {
+  typedef T type __attribute__((ext_vector_type(R)));
 };
 template <typename T>
 struct Vec2T {
@@ -335,7 +329,13 @@ constexpr int kCacheStream = 2;  // non-temporal
 template <typename T, int R, int AUX = kCacheDefault>
 __device__ inline void bload(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T (&r)[R]) {
   typedef typename VecT<T, R>::type V;
-  V x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, AUX));
+  V x;
+  if constexpr (sizeof(V) == 16)
+    x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, AUX));
+  else if constexpr (sizeof(V) == 8)
+    x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, AUX));
+  else
+    x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, AUX));
 #pragma unroll
   for (int i = 0; i < R; ++i) r[i] = x[i];
 }
@@ -350,6 +350,36 @@ __device__ inline void bload_pair(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint
     x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, kCacheDefault));
   a = x[0];
   b = x[1];
+}
+
+template <typename T>
+__device__ inline void bload_one(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T &a) {
+  T r[1];
+  bload<T, 1>(rs, voff, soff, r);
+  a = r[0];
+}
+
+// Element offsets (from `base`, the start of the theta row) of the theta
+// halo of the run starting at th0.  R >= 2 (N_theta a multiple of R, so
+// even): h[0] = first of the pair (th0-2, th0-1), h[2] = first of the pair
+// (th0+R, th0+R+1), each pair contiguous after wrapping.  R = 1: h[k] = the
+// wrapped th0-2, th0-1, th0+1, th0+2 (N_theta >= 3).
+template <int R>
+__device__ inline void theta_halo_offsets(int base, int th0, int nth, uint32_t (&h)[4]) {
+  if constexpr (R >= 2) {
+    h[0] = (uint32_t)(base + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth));
+    h[2] = (uint32_t)(base + (th0 + R < nth ? th0 + R : th0 + R - nth));
+    h[1] = h[0] + 1;
+    h[3] = h[2] + 1;
+  } else {
+    const int o[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int t = th0 + o[k];
+      t = t < 0 ? t + nth : (t >= nth ? t - nth : t);
+      h[k] = (uint32_t)(base + t);
+    }
+  }
 }
 
 // V at x plane xi (within two planes of the grid) for one run: on the grid,
@@ -380,10 +410,11 @@ __device__ inline void fix_run(int i, int n, const T (&c)[R], T (&m2)[R], T (&m1
   for (int j = 0; j < R; ++j) fix_ghosts<T, DERIV>(i, n, c[j], m2[j], m1[j], p1[j], p2[j]);
 }
 
+// One tile of the streaming kernel: logical block lb of the launch that `a`
+// describes (blocks_per_chunk run blocks per x chunk, chunk-major).
 template <typename T, int R, int DERIV, bool SG, bool BALL>
-__global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
+__device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
   constexpr uint32_t E = sizeof(T);
-  const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
   const int chunk = lb / a.blocks_per_chunk;
   const int r = (lb - chunk * a.blocks_per_chunk) * kStreamBlock + (int)threadIdx.x;
   if (r >= a.slab_runs) return;
@@ -399,8 +430,10 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
   const int rowoff = (y * nv + v) * nth;
   const int offe = rowoff + th0;
   const uint32_t oc = (uint32_t)offe * E;
-  const uint32_t ol = (uint32_t)(rowoff + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth)) * E;
-  const uint32_t orr = (uint32_t)(rowoff + (th0 + R < nth ? th0 + R : th0 + R - nth)) * E;
+  // theta halos: two aligned pairs (runs of 2 or 4 on an even N_theta), or
+  // four single nodes, each wrapped (runs of 1)
+  uint32_t oh[4];
+  theta_halo_offsets<R>(rowoff, th0, nth, oh);
   uint32_t ov[4], oy[4];
   {
     const int o[4] = {-2, -1, 1, 2};
@@ -461,8 +494,15 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
     // ---- issue this plane's neighbour loads, then the next front
     T u[R + 4];
     T vn2[R], vn1[R], vp1[R], vp2[R], yn2[R], yn1[R], yp1[R], yp2[R];
-    bload_pair<T>(rs, ol, sX, u[0], u[1]);
-    bload_pair<T>(rs, orr, sX, u[R + 2], u[R + 3]);
+    if constexpr (R >= 2) {
+      bload_pair<T>(rs, oh[0] * E, sX, u[0], u[1]);
+      bload_pair<T>(rs, oh[2] * E, sX, u[R + 2], u[R + 3]);
+    } else {
+      bload_one<T>(rs, oh[0] * E, sX, u[0]);
+      bload_one<T>(rs, oh[1] * E, sX, u[1]);
+      bload_one<T>(rs, oh[2] * E, sX, u[3]);
+      bload_one<T>(rs, oh[3] * E, sX, u[4]);
+    }
     if (DERIV == kEno2) bload<T, R>(rs, ov[0], sX, vn2);
     bload<T, R>(rs, ov[1], sX, vn1);
     bload<T, R>(rs, ov[2], sX, vp1);
@@ -588,6 +628,11 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
   }
 }
 
+template <typename T, int R, int DERIV, bool SG, bool BALL>
+__global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
+  stream_tile<T, R, DERIV, SG, BALL>(a, (int)xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // Plane kernel.  Block (y, x chunk) owns every run of the (v, theta) plane at
 // one y and sweeps the chunk's x planes.  Each thread keeps the x ring of its
@@ -643,8 +688,8 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       lv[k] = wrap_or_clamp(v + o[k], nv, perv) * nth + th0;
     }
   }
-  const int ll = v * nth + (th0 >= 2 ? th0 - 2 : th0 - 2 + nth);
-  const int lr = v * nth + (th0 + R < nth ? th0 + R : th0 + R - nth);
+  uint32_t lh[4];  // theta halos inside the LDS plane (see the streaming kernel)
+  theta_halo_offsets<R>(v * nth, th0, nth, lh);
   const bool vedge = !perv && (v < 2 || v >= nv - 2);
   const bool yedge = !pery && (y < 2 || y >= ny - 2);
   T kpx[R], kmx[R], kpy[R], kmy[R];
@@ -768,8 +813,15 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     // ---- theta: halos from LDS
     {
       T u[R + 4];
-      lds_pair<T>(buf + ll, u[0], u[1]);
-      lds_pair<T>(buf + lr, u[R + 2], u[R + 3]);
+      if constexpr (R >= 2) {
+        lds_pair<T>(buf + lh[0], u[0], u[1]);
+        lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
+      } else {
+        u[0] = buf[lh[0]];
+        u[1] = buf[lh[1]];
+        u[3] = buf[lh[2]];
+        u[4] = buf[lh[3]];
+      }
 #pragma unroll
       for (int j = 0; j < R; ++j) u[j + 2] = c[j];
       T dprev = u[2] - u[1];
@@ -938,11 +990,20 @@ hipError_t launch_stage_d(const StageArgs<T> &a, bool ball, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int R, int DERIV, bool SG, bool BALL>
+hipError_t launch_stream_r(const StreamArgs<T> &a, hipStream_t s) {
+  unsigned blocks = (unsigned)(a.blocks_per_chunk * a.n_chunks);
+  hipLaunchKernelGGL((stage_stream<T, R, DERIV, SG, BALL>), dim3(blocks), dim3(kStreamBlock), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int DERIV, bool SG, bool BALL>
 hipError_t launch_stream_v(const StreamArgs<T> &a, hipStream_t s) {
-  unsigned blocks = (unsigned)(a.blocks_per_chunk * a.n_chunks);
-  hipLaunchKernelGGL((stage_stream<T, stream_run<T>(), DERIV, SG, BALL>), dim3(blocks), dim3(kStreamBlock), 0, s, a);
-  return hipGetLastError();
+  if (a.run == 1) return launch_stream_r<T, 1, DERIV, SG, BALL>(a, s);
+  if (a.run == 2) return launch_stream_r<T, 2, DERIV, SG, BALL>(a, s);
+  if constexpr (sizeof(T) == 4)
+    if (a.run == 4) return launch_stream_r<T, 4, DERIV, SG, BALL>(a, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int DERIV>
@@ -952,14 +1013,23 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
   return sg ? launch_stream_v<T, DERIV, true, false>(a, s) : launch_stream_v<T, DERIV, false, false>(a, s);
 }
 
-template <typename T, int DERIV, bool SG, bool BALL>
-hipError_t launch_plane_v(const StreamArgs<T> &a, hipStream_t s) {
+template <typename T, int R, int DERIV, bool SG, bool BALL>
+hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
   int runs = a.n[2] * a.runs_per_row;
   int threads = (runs + 63) / 64 * 64;
   size_t lds = 2 * (size_t)a.n[2] * a.n[3] * sizeof(T);
   unsigned blocks = (unsigned)(a.n[1] * a.n_chunks);
-  hipLaunchKernelGGL((stage_plane<T, stream_run<T>(), DERIV, SG, BALL>), dim3(blocks), dim3(threads), lds, s, a);
+  hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int DERIV, bool SG, bool BALL>
+hipError_t launch_plane_v(const StreamArgs<T> &a, hipStream_t s) {
+  if (a.run == 1) return launch_plane_r<T, 1, DERIV, SG, BALL>(a, s);
+  if (a.run == 2) return launch_plane_r<T, 2, DERIV, SG, BALL>(a, s);
+  if constexpr (sizeof(T) == 4)
+    if (a.run == 4) return launch_plane_r<T, 4, DERIV, SG, BALL>(a, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int DERIV>
@@ -967,6 +1037,134 @@ hipError_t launch_plane_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
   bool sg = a.sg[0] != T(0) || a.sg[1] != T(0);
   if (ball) return sg ? launch_plane_v<T, DERIV, true, true>(a, s) : launch_plane_v<T, DERIV, false, true>(a, s);
   return sg ? launch_plane_v<T, DERIV, true, false>(a, s) : launch_plane_v<T, DERIV, false, false>(a, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves.  Every instance of a batch runs the streaming kernel's
+// tiles; which arrays a tile reads and writes follows from its phase.
+// ---------------------------------------------------------------------------
+
+// The per-phase fields of instance `in` at step k, stage `stage`.
+template <typename T>
+__device__ inline void phase_args(StreamArgs<T> &a, const BatchInst<T> &in, int k, int stage) {
+  const T *cur = k == 0 ? in.v0 : ((k & 1) ? in.vb : in.va);
+  T *nxt = (k & 1) ? in.va : in.vb;
+  a.dt = k == in.steps - 1 ? in.dt_last : in.dt;
+  a.v0 = in.v0;
+  if (!in.rk2) {
+    a.vs = cur;
+    a.vn = nullptr;
+    a.out = nxt;
+    a.mode = kPlain;
+    a.clamp = in.clamp;
+  } else if (stage == 0) {
+    a.vs = cur;
+    a.vn = nullptr;
+    a.out = in.w1;
+    a.mode = kPlain;
+    a.clamp = 0;
+  } else {
+    a.vs = in.w1;
+    a.vn = cur;
+    a.out = nxt;
+    a.mode = kAverage;
+    a.clamp = in.clamp;
+  }
+}
+
+// The run length differs between instances: dispatch inside the kernel (the
+// choice is uniform over a block).
+template <typename T, int DERIV, bool SG, bool BALL>
+__device__ inline void tile_any_run(const StreamArgs<T> &a, int lb) {
+  if (a.run == 1) {
+    stream_tile<T, 1, DERIV, SG, BALL>(a, lb);
+  } else if (a.run == 2) {
+    stream_tile<T, 2, DERIV, SG, BALL>(a, lb);
+  } else if constexpr (sizeof(T) == 4) {
+    stream_tile<T, 4, DERIV, SG, BALL>(a, lb);
+  }
+}
+
+// First j in [0, n) with end[j] > x (end ascending, end[n-1] > x).
+__device__ inline int find_end(const int32_t *__restrict__ end, int n, int x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (end[mid] > x)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+template <typename T, int DERIV, bool SG, bool BALL>
+__global__ __launch_bounds__(kStreamBlock) void stage_multi(const BatchInst<T> *__restrict__ inst,
+                                                             const int32_t *__restrict__ tile_end, int ninst, int k,
+                                                             int stage) {
+  const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = find_end(tile_end, ninst, lb);
+  StreamArgs<T> a = inst[j].a;
+  phase_args(a, inst[j], k, stage);
+  tile_any_run<T, DERIV, SG, BALL>(a, lb - (j > 0 ? tile_end[j - 1] : 0));
+}
+
+// The persistent batch kernel.  Each block takes work items in order from a
+// global counter; an item is one tile of one instance in one phase.  Before
+// a tile runs, every tile of the instance's previous phase must be complete
+// (the tile reads x-, y-, v- and theta-neighbours that other tiles wrote),
+// which the instance's completion counter shows.  Items are ordered by
+// phase, so an item only waits for items taken before it, by blocks that are
+// running: the queue always drains.  A wait gives up after spin_limit polls
+// and raises the error flag, after which every block leaves, so the kernel
+// ends in every case.
+template <typename T, int DERIV, bool SG, bool BALL>
+__global__ __launch_bounds__(kStreamBlock) void stage_persistent(PersistArgs<T> p) {
+  __shared__ int32_t s_item, s_abort;
+  BatchQueue *q = p.queue;
+  const int32_t total = p.start[p.nphase];
+  int ph = 0;  // phase of the last item (items of a block only increase)
+  for (;;) {
+    if (threadIdx.x == 0) s_item = __hip_atomic_fetch_add(&q->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int32_t item = s_item;
+    if (item >= total) break;
+    while (item >= p.start[ph + 1]) ++ph;
+    const int32_t local = item - p.start[ph];
+    const int j = find_end(p.tile_end, p.active[ph], local);
+    const int tile = local - (j > 0 ? p.tile_end[j - 1] : 0);
+    if (threadIdx.x == 0) {
+      const int32_t need = ph * p.inst[j].tiles;
+      int ok = 1;
+      int64_t spins = 0;
+      while (__hip_atomic_load(&q->done[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (__hip_atomic_load(&q->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > p.spin_limit) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!ok) __hip_atomic_store(&q->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_abort = !ok;
+    }
+    __syncthreads();
+    if (s_abort) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the previous phase's results
+    StreamArgs<T> a = p.inst[j].a;
+    phase_args(a, p.inst[j], ph / p.phases_per_step, ph % p.phases_per_step);
+    tile_any_run<T, DERIV, SG, BALL>(a, tile);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this tile's stores
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&q->done[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void batch_reset_kernel(BatchQueue *q, int m) {
+  for (int i = threadIdx.x; i < m; i += blockDim.x) q->done[i] = 0;
+  if (threadIdx.x == 0) {
+    q->next = 0;
+    q->error = 0;
+  }
 }
 
 }  // namespace
@@ -1019,6 +1217,103 @@ hipError_t launch_nonfinite(const T *src, int64_t n, int32_t *flag, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename T, int DERIV, bool SG, bool BALL>
+static hipError_t launch_multi_v(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int k,
+                                 int stage, hipStream_t s) {
+  hipLaunchKernelGGL((stage_multi<T, DERIV, SG, BALL>), dim3(blocks), dim3(kStreamBlock), 0, s, inst, tile_end, ninst,
+                     k, stage);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int k, int stage,
+                        int deriv, bool sg, bool ball, hipStream_t s) {
+#define HJ_MULTI(D, G, B) return launch_multi_v<T, D, G, B>(inst, tile_end, ninst, blocks, k, stage, s)
+  if (deriv == kUpwind1) {
+    if (ball) {
+      if (sg) HJ_MULTI(kUpwind1, true, true);
+      HJ_MULTI(kUpwind1, false, true);
+    }
+    if (sg) HJ_MULTI(kUpwind1, true, false);
+    HJ_MULTI(kUpwind1, false, false);
+  }
+  if (ball) {
+    if (sg) HJ_MULTI(kEno2, true, true);
+    HJ_MULTI(kEno2, false, true);
+  }
+  if (sg) HJ_MULTI(kEno2, true, false);
+  HJ_MULTI(kEno2, false, false);
+#undef HJ_MULTI
+}
+
+template <typename T, int DERIV, bool SG, bool BALL>
+static hipError_t launch_persistent_v(const PersistArgs<T> &p, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((stage_persistent<T, DERIV, SG, BALL>), dim3(blocks), dim3(kStreamBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+template <typename T, int DERIV, bool SG, bool BALL>
+static int persistent_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stage_persistent<T, DERIV, SG, BALL>, kStreamBlock, 0) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+template <typename T>
+hipError_t launch_persistent(const PersistArgs<T> &p, int blocks, int deriv, bool sg, bool ball, hipStream_t s) {
+#define HJ_PERS(D, G, B) return launch_persistent_v<T, D, G, B>(p, blocks, s)
+  if (deriv == kUpwind1) {
+    if (ball) {
+      if (sg) HJ_PERS(kUpwind1, true, true);
+      HJ_PERS(kUpwind1, false, true);
+    }
+    if (sg) HJ_PERS(kUpwind1, true, false);
+    HJ_PERS(kUpwind1, false, false);
+  }
+  if (ball) {
+    if (sg) HJ_PERS(kEno2, true, true);
+    HJ_PERS(kEno2, false, true);
+  }
+  if (sg) HJ_PERS(kEno2, true, false);
+  HJ_PERS(kEno2, false, false);
+#undef HJ_PERS
+}
+
+template <typename T>
+int persistent_blocks_per_cu(int deriv, bool sg, bool ball) {
+#define HJ_OCC(D, G, B) return persistent_occupancy<T, D, G, B>()
+  if (deriv == kUpwind1) {
+    if (ball) {
+      if (sg) HJ_OCC(kUpwind1, true, true);
+      HJ_OCC(kUpwind1, false, true);
+    }
+    if (sg) HJ_OCC(kUpwind1, true, false);
+    HJ_OCC(kUpwind1, false, false);
+  }
+  if (ball) {
+    if (sg) HJ_OCC(kEno2, true, true);
+    HJ_OCC(kEno2, false, true);
+  }
+  if (sg) HJ_OCC(kEno2, true, false);
+  HJ_OCC(kEno2, false, false);
+#undef HJ_OCC
+}
+
+hipError_t launch_batch_reset(BatchQueue *queue, int m, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, s, queue, m);
+  return hipGetLastError();
+}
+
+template hipError_t launch_multi<float>(const BatchInst<float> *, const int32_t *, int, int, int, int, int, bool, bool,
+                                        hipStream_t);
+template hipError_t launch_multi<double>(const BatchInst<double> *, const int32_t *, int, int, int, int, int, bool,
+                                         bool, hipStream_t);
+template hipError_t launch_persistent<float>(const PersistArgs<float> &, int, int, bool, bool, hipStream_t);
+template hipError_t launch_persistent<double>(const PersistArgs<double> &, int, int, bool, bool, hipStream_t);
+template int persistent_blocks_per_cu<float>(int, bool, bool);
+template int persistent_blocks_per_cu<double>(int, bool, bool);
 template hipError_t launch_stream<float>(const StreamArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_plane<float>(const StreamArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_plane<double>(const StreamArgs<double> &, int, bool, hipStream_t);

@@ -31,6 +31,8 @@ HJ_EULER, HJ_TVD_RK2 = 0, 1
 HJ_CLAMP_NONE, HJ_CLAMP_MIN_V0 = 0, 1
 HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
 HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
+HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT = 0, 1, 2
+BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT}
 
 STATUS_NAMES = {0: "HJ_OK", 1: "HJ_ERR_INVALID_ARG", 2: "HJ_ERR_OUT_OF_MEMORY", 3: "HJ_ERR_DEVICE",
                 4: "HJ_ERR_NOT_READY", 5: "HJ_ERR_NONFINITE", 6: "HJ_ERR_UNSUPPORTED"}
@@ -39,7 +41,8 @@ EXPORTED = [
     "hj_grid_create", "hj_grid_destroy", "hj_set_target", "hj_set_target_cylinders", "hj_solve_brt",
     "hj_step", "hj_get_cfl_dt", "hj_get_alpha_max", "hj_get_value", "hj_get_target", "hj_set_value",
     "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_get_launch_info", "hj_autotune",
-    "hj_set_autotune", "hj_last_error", "hj_version",
+    "hj_set_autotune", "hj_batch_create", "hj_batch_destroy", "hj_batch_solve", "hj_batch_set_tile",
+    "hj_batch_set_spin_limit", "hj_batch_autotune", "hj_batch_get_info", "hj_last_error", "hj_version",
 ]
 
 
@@ -78,6 +81,12 @@ class hj_launch_info(ctypes.Structure):
 KERNEL_NAMES = {0: "generic", 1: "stream", 2: "plane"}
 
 
+class hj_batch_info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("x_planes", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
+                ("graph_nodes", ctypes.c_int32), ("tiles_per_sweep", ctypes.c_int64),
+                ("work_items", ctypes.c_int64), ("points", ctypes.c_int64)]
+
+
 class hj_profile(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_int64), ("step_launches", ctypes.c_int64), ("loop_ms", ctypes.c_double)]
 
@@ -93,6 +102,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"HIP library {path} is not built; run `python -m paper_2012_04011_amd.build` "
                           "(or __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime; loading it first makes libhj.so bind
+    # to that one, so that torch tensors, streams and this library share one
+    # runtime in the process whatever is imported first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
@@ -114,6 +130,13 @@ def load_library(path: str = LIB_PATH):
         "hj_get_launch_info": [vp, P(hj_launch_info)],
         "hj_autotune": [vp],
         "hj_set_autotune": [vp, i32],
+        "hj_batch_create": [P(vp), i32, P(vp)],
+        "hj_batch_destroy": [vp],
+        "hj_batch_solve": [vp, P(dbl), i32, P(hj_solve_info)],
+        "hj_batch_set_tile": [vp, i32],
+        "hj_batch_set_spin_limit": [vp, i64],
+        "hj_batch_autotune": [vp, P(dbl), i32, P(i32)],
+        "hj_batch_get_info": [vp, P(hj_batch_info)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -306,6 +329,50 @@ def hj_set_autotune(h: int, enable: bool) -> None:
     _check(load_library().hj_set_autotune(h, 1 if enable else 0), "hj_set_autotune")
 
 
+def hj_batch_create(handles) -> int:
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    out = ctypes.c_void_p()
+    _check(_lib.hj_batch_create(arr, len(handles), ctypes.byref(out)), "hj_batch_create")
+    return out.value
+
+
+def hj_batch_destroy(b: int) -> None:
+    _check(_lib.hj_batch_destroy(b), "hj_batch_destroy")
+
+
+def _horizons(h, m: int):
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (m,)))
+    return h, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def hj_batch_solve(b: int, m: int, horizons, mode: str = "launches") -> list:
+    h, hp = _horizons(horizons, m)
+    infos = (hj_solve_info * m)()
+    _check(_lib.hj_batch_solve(b, hp, BATCH_MODES[mode], infos), "hj_batch_solve")
+    return [{"steps": i.steps, "dt": i.dt, "dt_last": i.dt_last, "t_final": i.t_final} for i in infos]
+
+
+def hj_batch_set_tile(b: int, x_planes: int) -> None:
+    _check(_lib.hj_batch_set_tile(b, int(x_planes)), "hj_batch_set_tile")
+
+
+def hj_batch_set_spin_limit(b: int, polls: int) -> None:
+    _check(_lib.hj_batch_set_spin_limit(b, int(polls)), "hj_batch_set_spin_limit")
+
+
+def hj_batch_autotune(b: int, m: int, horizons, mode: str = "launches") -> int:
+    h, hp = _horizons(horizons, m)
+    out = ctypes.c_int32()
+    _check(_lib.hj_batch_autotune(b, hp, BATCH_MODES[mode], ctypes.byref(out)), "hj_batch_autotune")
+    return out.value
+
+
+def hj_batch_get_info(b: int) -> dict:
+    i = hj_batch_info()
+    _check(_lib.hj_batch_get_info(b, ctypes.byref(i)), "hj_batch_get_info")
+    return {f: getattr(i, f) for f, _ in hj_batch_info._fields_}
+
+
 def hj_last_error() -> str:
     return load_library().hj_last_error().decode()
 
@@ -395,3 +462,43 @@ class Grid:
 
     def set_autotune(self, enable: bool):
         hj_set_autotune(self.handle, enable)
+
+
+class Batch:
+    """Grids solved together (see hj_batch_create); holds references to them."""
+
+    def __init__(self, grids):
+        self.grids = list(grids)
+        self.handle = hj_batch_create([g.handle for g in self.grids])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hj_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, horizons, mode: str = "launches") -> list:
+        return hj_batch_solve(self.handle, len(self.grids), horizons, mode)
+
+    def set_tile(self, x_planes: int):
+        hj_batch_set_tile(self.handle, x_planes)
+
+    def set_spin_limit(self, polls: int):
+        hj_batch_set_spin_limit(self.handle, polls)
+
+    def autotune(self, horizons, mode: str = "launches") -> int:
+        return hj_batch_autotune(self.handle, len(self.grids), horizons, mode)
+
+    def info(self) -> dict:
+        return hj_batch_get_info(self.handle)

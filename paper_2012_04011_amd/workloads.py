@@ -120,3 +120,40 @@ LARGE_120_COARSE = Workload(
 )
 
 WORKLOADS = {w.name: w for w in (PLAIN_40, ENO_60_DIST, LARGE_120, LARGE_120_COARSE)}
+
+
+@dataclass
+class Instance:
+    """One problem of a batch: grid, dynamics, scheme, obstacle set, horizon."""
+    grid: dict
+    dyn: dict
+    scheme: dict
+    cylinders: tuple
+    horizon: float
+
+    @property
+    def points(self) -> int:
+        n = self.grid["n"]
+        return int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+
+
+def batch_instances(count: int = 64, seed0: int = 1000, sizes=((30, 80), (30, 80), (12, 24), (18, 48)),
+                    obstacles=(1, 8), horizon=(0.5, 2.0)) -> list:
+    """Uneven batch: instance i draws, from default_rng(seed0 + i) in this
+    order, its axis sizes (independent uniform integers in `sizes`, ends
+    included), its obstacle count (uniform in `obstacles`) and its horizon
+    (uniform in `horizon`); its cylinders are cylinders(seed0 + i, m) for that count m.
+    4D car without disturbance, ENO2 + TVD-RK2."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        n = [int(rng.integers(lo, hi + 1)) for lo, hi in sizes]
+        m = int(rng.integers(obstacles[0], obstacles[1] + 1))
+        T = float(rng.uniform(*horizon))
+        out.append(Instance(car_grid(*n), car_dynamics(), scheme("eno2", "rk2"), cylinders(seed0 + i, m), T))
+    return out
+
+
+# 64 uneven instances, 30x30x12x18 .. 80x80x24x48, 1-8 cylinders,
+# horizons in [0.5, 2] s, FP32 ENO2 + TVD-RK2 (the batched workload).
+BATCH_64 = dict(count=64, seed0=1000)

@@ -120,3 +120,25 @@ def test_null_arguments(lib):
     assert lib.hj_set_target(None, None, 0, 0) == hj.HJ_ERR_INVALID_ARG
     assert lib.hj_grid_destroy(None) == hj.HJ_OK
     assert "null" in hj.hj_last_error()
+
+
+def test_batch_null_and_range_arguments(lib):
+    """Batch calls validate their arguments before touching the device."""
+    out = ctypes.c_void_p()
+    assert lib.hj_batch_create(None, 1, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.hj_batch_create(arr, 1, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_create(arr, 0, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_create(arr, 257, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_create(arr, 1, None) == hj.HJ_ERR_INVALID_ARG
+    h = (ctypes.c_double * 1)(1.0)
+    assert lib.hj_batch_solve(None, h, 0, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_set_tile(None, 8) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_set_spin_limit(None, 8) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_autotune(None, h, 0, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_get_info(None, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_batch_destroy(None) == hj.HJ_OK
+
+
+def test_batch_info_layout():
+    assert ctypes.sizeof(hj.hj_batch_info) == 40

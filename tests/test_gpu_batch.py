@@ -1,0 +1,197 @@
+"""Batched solves through the C ABI (hj_batch_*): every instance of a batch
+must equal the single-grid solve of the same handle bit for bit (the batch
+kernels evaluate each node with the single-grid kernels' arithmetic), in all
+three modes (one launch per step and stage; the same launches replayed from
+a hipGraph; one persistent launch); and the batch must match the oracle."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_04011_amd import workloads as W
+
+from helpers import assert_f32_close, assert_f64_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_04011_amd import hj
+
+    hj.load_library()
+
+MODES = ["launches", "graph", "persistent"]
+
+
+def small_batch(precision: str):
+    """Six uneven instances: theta runs of 4, 2 and 1, horizons giving 0, 1
+    and many steps, with and without a disturbance in FP64 (a batch mixes
+    dynamics freely)."""
+    shapes = [(14, 12, 6, 16), (11, 13, 5, 18), (9, 10, 7, 19), (12, 9, 5, 21), (10, 11, 6, 8), (8, 8, 4, 3)]
+    horizons = [0.6, 0.35, 0.0, 0.5, 0.01, 0.45]
+    out = []
+    for i, (n, T) in enumerate(zip(shapes, horizons)):
+        dyn = W.car_dynamics(d_max=0.1 if (precision == "f64" and i % 2) else 0.0)
+        out.append(W.Instance(W.car_grid(*n), dyn, W.scheme("eno2", "rk2"), W.cylinders(40 + i, 1 + i % 4), T))
+    return out
+
+
+def make_grids(hj, insts, precision):
+    grids = []
+    for ins in insts:
+        g = hj.Grid(ins.grid, ins.dyn, ins.scheme, precision)
+        g.set_target_cylinders(*ins.cylinders)
+        grids.append(g)
+    return grids
+
+
+def single_solutions(hj, insts, precision):
+    vals, infos = [], []
+    for ins in insts:
+        with hj.Grid(ins.grid, ins.dyn, ins.scheme, precision) as g:
+            g.set_target_cylinders(*ins.cylinders)
+            infos.append(g.solve_brt(ins.horizon))
+            vals.append(g.value(np.float64))
+    return vals, infos
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_equals_single_solves(mode, precision):
+    from paper_2012_04011_amd import hj
+
+    insts = small_batch(precision)
+    ref, ref_infos = single_solutions(hj, insts, precision)
+    grids = make_grids(hj, insts, precision)
+    with hj.Batch(grids) as b:
+        for tile in (16, 5):  # two tile shapes, the second re-plans (and re-captures the graph)
+            for g, ins in zip(grids, insts):
+                g.set_target_cylinders(*ins.cylinders)
+            b.set_tile(tile)
+            infos = b.solve([i.horizon for i in insts], mode)
+            for j, g in enumerate(grids):
+                assert infos[j]["steps"] == ref_infos[j]["steps"]
+                assert infos[j]["dt"] == ref_infos[j]["dt"] and infos[j]["dt_last"] == ref_infos[j]["dt_last"]
+                assert np.array_equal(g.value(np.float64), ref[j]), (mode, tile, j)
+        info = b.info()
+        assert info["m"] == len(insts) and info["x_planes"] == 5
+        assert info["points"] == sum(i.points for i in insts)
+        if mode == "graph":
+            assert info["graph_nodes"] == 2 * max(r["steps"] for r in ref_infos)
+        if mode == "persistent":
+            assert info["persistent_blocks"] >= 1
+    for g in grids:
+        g.close()
+
+
+def test_batch_graph_replays_with_new_targets():
+    """The captured graph is replayed (same step counts) with new obstacle
+    sets and eager work in between; every replay equals the single solves."""
+    from paper_2012_04011_amd import hj
+
+    insts = small_batch("f32")
+    grids = make_grids(hj, insts, "f32")
+    with hj.Batch(grids) as b:
+        for rep in range(3):
+            moved = [W.Instance(i.grid, i.dyn, i.scheme, W.cylinders(100 * rep + j, 3), i.horizon)
+                     for j, i in enumerate(insts)]
+            for g, ins in zip(grids, moved):
+                g.set_target_cylinders(*ins.cylinders)
+            b.solve([i.horizon for i in moved], "graph")
+            ref, _ = single_solutions(hj, moved, "f32")  # eager solves between replays
+            for j, g in enumerate(grids):
+                assert np.array_equal(g.value(np.float64), ref[j]), (rep, j)
+    for g in grids:
+        g.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_matches_oracle(precision):
+    from paper_2012_04011_amd import hj
+
+    insts = small_batch(precision)[:4]
+    grids = make_grids(hj, insts, precision)
+    with hj.Batch(grids) as b:
+        infos = b.solve([i.horizon for i in insts], "persistent")
+    for ins, g, info in zip(insts, grids, infos):
+        V0 = oracle.target_cylinders(ins.grid, *ins.cylinders)
+        ref, oinfo = oracle.solve(ins.grid, ins.dyn, ins.scheme, V0, ins.horizon)
+        assert info["steps"] == oinfo["steps"]
+        V = g.value(np.float64)
+        if precision == "f64":
+            assert_f64_close(V, ref)
+        else:
+            assert_f32_close(V, ref, ins.grid, "eno2")
+        g.close()
+
+
+def test_batch_persistent_spin_limit_error_path():
+    """A spin limit of 0 makes a tile give up as soon as its dependency is
+    not yet met: the kernel still ends, the call reports a device error (or,
+    if no tile ever had to wait, the results are right), and the next solve
+    with the default limit is correct."""
+    from paper_2012_04011_amd import hj
+
+    insts = small_batch("f32")
+    ref, _ = single_solutions(hj, insts, "f32")
+    grids = make_grids(hj, insts, "f32")
+    with hj.Batch(grids) as b:
+        b.set_spin_limit(0)
+        try:
+            b.solve([i.horizon for i in insts], "persistent")
+            for j, g in enumerate(grids):
+                assert np.array_equal(g.value(np.float64), ref[j])
+        except hj.HJError as e:
+            assert e.status == hj.HJ_ERR_DEVICE
+        b.set_spin_limit(1 << 21)
+        for g, ins in zip(grids, insts):
+            g.set_target_cylinders(*ins.cylinders)
+        b.solve([i.horizon for i in insts], "persistent")
+        for j, g in enumerate(grids):
+            assert np.array_equal(g.value(np.float64), ref[j])
+    for g in grids:
+        g.close()
+
+
+def test_batch_autotune_picks_a_candidate():
+    from paper_2012_04011_amd import hj
+
+    insts = small_batch("f32")
+    ref, _ = single_solutions(hj, insts, "f32")
+    grids = make_grids(hj, insts, "f32")
+    with hj.Batch(grids) as b:
+        t = b.autotune([i.horizon for i in insts], "launches")
+        assert t in (4, 8, 12, 16, 24, 32, 48, 80) and b.info()["x_planes"] == t
+        for j, g in enumerate(grids):
+            assert np.array_equal(g.value(np.float64), ref[j])
+    for g in grids:
+        g.close()
+
+
+def test_batch_64_uneven_sampled():
+    """The 64-instance uneven batch (30x30x12x18 .. 80x80x24x48, 1-8
+    cylinders, horizons 0.5-2 s) in one persistent launch: four instances
+    (the largest, the smallest, the longest and the shortest horizon) equal
+    their single-grid solves bit for bit."""
+    from paper_2012_04011_amd import hj
+
+    insts = W.batch_instances(**W.BATCH_64)
+    grids = make_grids(hj, insts, "f32")
+    with hj.Batch(grids) as b:
+        infos = b.solve([i.horizon for i in insts], "persistent")
+        assert b.info()["points"] == sum(i.points for i in insts)
+    pick = {int(np.argmax([i.points for i in insts])), int(np.argmin([i.points for i in insts])),
+            int(np.argmax([i.horizon for i in insts])), int(np.argmin([i.horizon for i in insts]))}
+    sub = [insts[j] for j in sorted(pick)]
+    ref, ref_infos = single_solutions(hj, sub, "f32")
+    for r, ri, j in zip(ref, ref_infos, sorted(pick)):
+        assert infos[j]["steps"] == ri["steps"]
+        assert np.array_equal(grids[j].value(np.float64), r), j
+    for g in grids:
+        g.close()

@@ -391,8 +391,13 @@ def test_large_120_determinism():
     assert np.array_equal(outs[0], outs[1])
 
 
+# N_theta 24, 36, 16, 8: runs of 4 (FP32) / 2 (FP64); 18 and 22: runs of 2;
+# 19, 3: runs of 1 (each theta halo node loaded on its own)
 KERNEL_SHAPES = [((40, 40, 20, 24), "upwind1", "euler"), ((60, 60, 20, 36), "eno2", "rk2"),
-                 ((17, 13, 9, 16), "eno2", "euler"), ((12, 11, 6, 8), "upwind1", "rk2")]
+                 ((17, 13, 9, 16), "eno2", "euler"), ((12, 11, 6, 8), "upwind1", "rk2"),
+                 ((14, 12, 7, 18), "eno2", "rk2"), ((11, 10, 6, 19), "eno2", "euler"),
+                 ((9, 9, 5, 3), "upwind1", "rk2"), ((10, 8, 5, 22), "upwind1", "euler"),
+                 ((13, 11, 6, 21), "eno2", "rk2")]
 
 
 @pytest.mark.parametrize("kernel", ["plane", "stream", "generic"])
@@ -421,6 +426,7 @@ def test_each_stage_kernel_one_step(monkeypatch, kernel, shape, deriv, integ, pr
         g.set_value(Vk)
         g.step(dt)
         V = g.value()
+        assert g.launch_info()["kernel"] == kernel
     u = U32 if precision == "f32" else U64
     bad = np.abs(V - ref) > 16 * u * np.maximum(np.abs(ref), 1.0)
     if precision == "f64" or deriv == "upwind1":
@@ -460,6 +466,45 @@ def test_kernels_and_target_forms_bitwise_equal(monkeypatch, precision):
     ref = next(iter(outs.values()))
     for k, v in outs.items():
         assert np.array_equal(v, ref), k
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("nth", [18, 19, 21])
+def test_short_runs_kernels_bitwise_and_solve(monkeypatch, precision, nth):
+    """Grids whose N_theta is not a multiple of 4 run the plane and streaming
+    kernels with runs of 2 or 1 theta nodes: bitwise equal across kernels and
+    x-chunkings, and a short ENO2 + TVD-RK2 solve with a disturbance matches
+    the oracle."""
+    from paper_2012_04011_amd import hj
+
+    grid = W.car_grid(22, 20, 8, nth)
+    dyn = W.car_dynamics(d_max=0.1)
+    sch = W.scheme("eno2", "rk2")
+    cyl = W.cylinders(11, 4)
+    horizon = 0.3
+    outs = {}
+    info = None
+    for kernel, chunks in [("plane", "1"), ("plane", "3"), ("stream", "2"), ("stream", "1")]:
+        monkeypatch.setenv("HJ_X_CHUNKS", chunks)
+        if kernel == "stream":
+            monkeypatch.setenv("HJ_STAGE_KERNEL", "stream")
+        else:
+            monkeypatch.delenv("HJ_STAGE_KERNEL", raising=False)
+        with hj.Grid(grid, dyn, sch, precision) as g:
+            g.set_target_cylinders(*cyl)
+            assert g.launch_info()["kernel"] == kernel
+            info = g.solve_brt(horizon)
+            outs[(kernel, chunks)] = g.value(np.float64)
+    V = next(iter(outs.values()))
+    for k, v in outs.items():
+        assert np.array_equal(v, V), k
+    V0 = oracle.target_cylinders(grid, *cyl)
+    ref, oinfo = oracle.solve(grid, dyn, sch, V0, horizon)
+    assert info["steps"] == oinfo["steps"]
+    if precision == "f64":
+        assert_f64_close(V, ref)
+    else:
+        assert_f32_close(V, ref, grid, "eno2")
 
 
 def test_autotune_and_launch_info():
