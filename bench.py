@@ -15,6 +15,8 @@ with HIP events on the stream the kernels run on) and the FP64 CPU oracle
 timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --workload batch64     # the uneven 64-instance batch
+    python bench.py --workload serve       # the Poisson re-solve stream, served and one at a time
 
 HBM traffic of the stage kernel (the roofline's `traffic`) comes from two
 rocprofv3 counter runs of this script (FETCH_SIZE, then WRITE_SIZE), each
@@ -160,6 +162,198 @@ def summarize_traffic(root: str, last: int = 200) -> int:
     return 0
 
 
+def bench_batch(args) -> int:
+    """The uneven 64-instance batch: every mode of hj_batch_solve beside the
+    same solves run one grid at a time, fixed 16-plane tiles beside the
+    autotuned tile length.  One JSON line; throughput is whole-batch
+    point-steps over the graph-mode solve time."""
+    import numpy as np
+    import torch
+
+    from paper_2012_04011_amd import hj
+    from paper_2012_04011_amd import workloads as W
+
+    hj.load_library()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    insts = W.batch_instances(**W.BATCH_64)
+    H = [i.horizon for i in insts]
+    grids = []
+    for ins in insts:
+        g = hj.Grid(ins.grid, ins.dyn, ins.scheme, "f32", stream)
+        g.set_target_cylinders(*ins.cylinders)
+        g.set_autotune(False)
+        grids.append(g)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return t
+
+    one = timed(lambda: [g.solve_brt(h) for g, h in zip(grids, H)], max(1, args.steps // 3))
+    b = hj.Batch(grids)
+    infos = b.solve(H, "launches")
+    point_steps = sum(i.points * f["steps"] for i, f in zip(insts, infos))
+    res = {}
+    b.set_tile(16)
+    for mode in ("launches", "graph", "persistent"):
+        res[mode] = timed(lambda: b.solve(H, mode), max(1, args.steps // 3))
+    tuned = b.autotune(H, "graph")
+    res["graph_tuned"] = timed(lambda: b.solve(H, "graph"), args.steps)
+    info = b.info()
+    b.close()
+    for g in grids:
+        g.close()
+    t = res["graph_tuned"]
+    ms = float(np.median(t))
+    value = point_steps / (ms / 1e3)
+    bpps = 20.0  # FP32 TVD-RK2 with the cylinder x-y target (see the single-grid byte model)
+    achieved = value * bpps / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (64 seeded uneven instances)",
+        "config": {
+            "workload": "batch: 64 uneven car4d instances 30x30x12x18..80x80x24x48, 1-8 cylinders, horizons "
+                        "0.5-2 s, ENO2+TVD-RK2 FP32",
+            "points": info["points"], "point_steps": point_steps, "mode": "graph",
+            "x_planes_autotuned": tuned, "tiles_per_sweep": info["tiles_per_sweep"],
+            "graph_nodes": info["graph_nodes"],
+        },
+        "modes_ms": {
+            "one_grid_at_a_time": float(np.median(one)),
+            "launches_fixed16": float(np.median(res["launches"])),
+            "graph_fixed16": float(np.median(res["graph"])),
+            "persistent_fixed16": float(np.median(res["persistent"])),
+            "graph_autotuned": ms,
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "batched stage kernel (whole solve, both stages)", "bytes_per_point_step": bpps},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args) -> int:
+    """A Poisson stream of re-solves (20 per second, 70 % on 60x60x20x36 and
+    30 % on 100x100x24x48, 1-3 obstacle changes each, horizon 1.5 s) played
+    in real time, twice: through the continuous-batching server, and one
+    request at a time (first in, first out, each solved alone on its class's
+    resident grid).  Latency = completion seen on the host - arrival."""
+    import numpy as np
+    import torch
+
+    from paper_2012_04011_amd import hj
+    from paper_2012_04011_amd import workloads as W
+
+    hj.load_library()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n_req = max(20, args.requests)
+    sch = W.scheme("eno2", "rk2")
+
+    def play_server(reqs):
+        lat, done, idmap = [], 0, {}
+        with hj.Server(sch, "f32", hbm_budget=args.hbm_budget, max_inflight=64, stream=stream) as srv:
+            # warm one slot per class (first-use allocation and CFL step)
+            for c, g in enumerate(W.SERVE_GRIDS):
+                rid = srv.submit(g, W.car_dynamics(), W.cylinders(70 + c, 3), 0.01)
+                while not srv.poll():
+                    srv.tick()
+                srv.take(rid)
+            t0 = time.perf_counter()
+            nxt = 0
+            while done < n_req:
+                now = time.perf_counter() - t0
+                while nxt < n_req and reqs[nxt].arrival <= now:
+                    r = reqs[nxt]
+                    idmap[srv.submit(r.grid, r.dyn, r.cylinders, r.horizon)] = r.arrival
+                    nxt += 1
+                st = srv.stats()
+                if st["running"] or st["queued"]:
+                    srv.tick()
+                for rid in srv.poll():
+                    lat.append(time.perf_counter() - t0 - idmap.pop(rid))
+                    srv.take(rid)
+                    done += 1
+                if not (st["running"] or st["queued"]) and nxt < n_req:
+                    time.sleep(max(0.0, min(0.0005, reqs[nxt].arrival - (time.perf_counter() - t0))))
+            wall = time.perf_counter() - t0
+            stats = srv.stats()
+        return np.array(lat) * 1e3, wall, stats
+
+    def play_alone(reqs):
+        grids = [hj.Grid(g, W.car_dynamics(), sch, "f32", stream) for g in W.SERVE_GRIDS]
+        for c, g in enumerate(grids):
+            g.set_autotune(False)
+            g.set_target_cylinders(*W.cylinders(70 + c, 3))
+            g.solve_brt(0.01)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            while time.perf_counter() - t0 < r.arrival:
+                time.sleep(0.0002)
+            g = grids[r.cls]
+            g.set_target_cylinders(*r.cylinders)
+            g.solve_brt(r.horizon)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0 - r.arrival)
+        wall = time.perf_counter() - t0
+        for g in grids:
+            g.close()
+        return np.array(lat) * 1e3, wall
+
+    reqs = W.serving_requests(n_req, rate=20.0)
+    lat_s, wall_s, stats = play_server(reqs)
+    lat_a, wall_a = play_alone(reqs)
+    # the same stream compressed 6x (120 requests per second): one request
+    # at a time then queues, the server batches
+    fast = W.serving_requests(n_req, rate=120.0)
+    lat_s6, wall_s6, _ = play_server(fast)
+    lat_a6, wall_a6 = play_alone(fast)
+    steps = {0: None, 1: None}
+    for c, g in enumerate(W.SERVE_GRIDS):
+        with hj.Grid(g, W.car_dynamics(), sch, "f32", stream) as h:
+            h.set_target_cylinders(*W.cylinders(70 + c, 3))
+            steps[c] = h.solve_brt(1.5)["steps"]
+    point_steps = sum(int(np.prod(r.grid["n"])) * steps[r.cls] for r in reqs)
+    pct = lambda a, q: float(np.percentile(a, q))
+    out = {
+        "metric": METRIC, "value": point_steps / wall_s, "unit": UNIT, "n_gpus": 1, "steps": n_req, "warmup": 2,
+        "ms_per_step": wall_s / n_req * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded Poisson re-solve stream)",
+        "config": {
+            "workload": "serving: Poisson 20 req/s, 70/30 mix of 60x60x20x36 (82 steps) and 100x100x24x48 (121 "
+                        "steps), 1-3 obstacle changes per request, horizon 1.5 s, ENO2+TVD-RK2 FP32",
+            "requests": n_req, "point_steps": point_steps, "hbm_budget": args.hbm_budget,
+        },
+        "latency_ms": {
+            "server": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99), "max": float(lat_s.max())},
+            "one_at_a_time": {"p50": pct(lat_a, 50), "p99": pct(lat_a, 99), "max": float(lat_a.max())},
+            "deadline_ms": 200.0,
+            "server_within_deadline": float(np.mean(lat_s <= 200.0)),
+        },
+        "throughput": {"server_req_per_s": n_req / wall_s, "one_at_a_time_req_per_s": n_req / wall_a},
+        "stress_120_req_per_s": {
+            "server": {"p50": pct(lat_s6, 50), "p99": pct(lat_s6, 99), "req_per_s": n_req / wall_s6},
+            "one_at_a_time": {"p50": pct(lat_a6, 50), "p99": pct(lat_a6, 99), "req_per_s": n_req / wall_a6},
+        },
+        "server_stats": stats,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     """The FP64 oracle on the host cores: whole RK2 steps of the same
     workload from its seed-0 target, as many as fit the time budget."""
@@ -199,6 +393,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--workload", choices=["large120", "batch64", "serve"], default="large120")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
+    ap.add_argument("--hbm-budget", type=int, default=8 << 30, help="serve: slot memory budget in bytes")
     ap.add_argument("--summarize-traffic", metavar="DIR")
     args = ap.parse_args()
     if args.summarize_traffic:
@@ -219,6 +416,10 @@ def main() -> int:
         return 1
     if args.copy_calibration:
         return copy_calibration()
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     hj.load_library()
     torch.cuda.set_device(0)
     wl = W.LARGE_120

@@ -283,6 +283,64 @@ hj_status hj_batch_autotune(hj_batch *b, const double *horizons, int32_t mode, i
 
 hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);
 
+/* ---- Serving: continuous batching of re-solves ----------------------------
+ * The paper's use is a robot re-solving its BRT whenever the obstacle map
+ * changes (section "Hardware Correctness": V0 handed to the solver, the BRT
+ * read back).  A server keeps grids resident on the device ("slots": the
+ * handle's arrays, table and CFL step) and steps every admitted request
+ * together: each tick admits queued requests (first in, first out) while
+ * fewer than max_inflight run and a slot is free or the budget allows a new
+ * one, then advances every running request by a few time steps: grids of
+ * fewer than 4 Mi nodes share one launch per stage and step (each at its own
+ * step), larger ones fill the device alone and step with their own tuned
+ * stage kernel.  Every request restarts from its own
+ * V0 and gets exactly the V of hj_solve_brt on a fresh handle (bitwise). */
+typedef struct hj_server hj_server;
+
+typedef struct {
+  hj_scheme_desc scheme; /* one scheme for all requests */
+  int64_t hbm_budget;    /* device bytes the slots may hold (0 = no limit); idle slots are freed to fit */
+  int32_t max_inflight;  /* most requests stepping together (1..256) */
+  int32_t x_planes;      /* tile length in x planes (0 = cut x so each launch has ~1024 blocks) */
+  int32_t steps_per_tick; /* time steps one tick enqueues for the running requests (0 = 4); at most
+                           * two ticks are in flight, so new requests wait for <= 2 ticks */
+  int32_t reserved;      /* 0 */
+} hj_server_desc;
+
+typedef struct {
+  int64_t submitted, admitted, completed, ticks;
+  int32_t running, queued, slots, pad;
+  int64_t slot_bytes; /* device bytes held by slots */
+} hj_server_stats;
+
+/* All work goes to hip_stream (borrowed; NULL = the null stream). */
+hj_status hj_server_create(const hj_server_desc *desc, void *hip_stream, hj_server **out);
+hj_status hj_server_destroy(hj_server *s);
+
+/* Queue a re-solve of the BRT of the union of m cylinders (cx, cy, r:
+ * centres and radii, copied) on `grid` with `dyn`, over `horizon`.  Nothing
+ * runs until hj_server_tick.  HJ_ERR_OUT_OF_MEMORY if one slot of this grid
+ * is larger than the whole budget. */
+hj_status hj_server_submit(hj_server *s, const hj_grid_desc *grid, const hj_dynamics_desc *dyn, const double *cx,
+                           const double *cy, const double *r, int32_t m, double horizon, int64_t *id);
+
+/* Admit, then advance every running request by up to steps_per_tick time
+ * steps (one launch per stage and step over the requests still short of
+ * their horizon; stream-ordered, returns without waiting).  Requests that
+ * arrive meanwhile join at the next tick.  *running = requests still
+ * stepping. */
+hj_status hj_server_tick(hj_server *s, int32_t *running);
+
+/* Ids (up to cap) of requests whose V is complete on the device (event
+ * queries; never waits). */
+hj_status hj_server_poll(hj_server *s, int64_t *ids, int32_t cap, int32_t *n);
+
+/* Copy a complete request's V (layout of hj_get_value; out may be NULL to
+ * drop it) and give its slot back.  HJ_ERR_NOT_READY until poll lists it. */
+hj_status hj_server_take(hj_server *s, int64_t id, void *out, int32_t dtype, int32_t where);
+
+hj_status hj_server_get_stats(hj_server *s, hj_server_stats *out);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *hj_last_error(void);
 

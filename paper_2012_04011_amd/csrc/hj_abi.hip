@@ -10,6 +10,8 @@
 
 #include <string>
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <vector>
 
 #include "../../include/hj.h"
@@ -1011,6 +1013,8 @@ void batch_free(hj_batch *b) {
 }
 
 constexpr int32_t kBatchDefaultXPlanes = 16;
+constexpr int64_t kServerBlocks = 1024;
+constexpr int64_t kServerAlonePoints = (int64_t)4 << 20;  // grids this large step on their own kernel
 
 int32_t batch_x_planes(const hj_batch *b) { return b->x_planes > 0 ? b->x_planes : kBatchDefaultXPlanes; }
 
@@ -1387,6 +1391,473 @@ hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out) {
   if (!out) return fail(HJ_ERR_INVALID_ARG, "null output");
   b->info.x_planes = batch_x_planes(b);
   *out = b->info;
+  return HJ_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching of re-solves
+// ===========================================================================
+
+struct hj_server {
+  hj_server_desc d;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t elem = 4;
+
+  struct Slot {
+    hj_grid *g = nullptr;
+    int64_t bytes = 0;
+    bool busy = false;
+    int64_t last_use = 0;
+  };
+  std::vector<Slot> slots;
+  int64_t slot_bytes = 0;
+
+  struct Req {
+    hj_grid_desc g;
+    hj_dynamics_desc dyn;
+    std::vector<double> cx, cy, r;
+    double horizon = 0;
+    int state = 0;  // 0 queued, 1 running, 2 finishing (event pending), 3 complete
+    int slot = -1;
+    int64_t n = 0, k = 0;
+    double dt = 0, dt_last = 0;
+    hipEvent_t ev = nullptr;
+  };
+  std::map<int64_t, Req> reqs;
+  std::deque<int64_t> queue;
+  std::vector<int64_t> running;
+  int64_t next_id = 1;
+
+  static const int kRing = 2;  // device tables (ticks) in flight: bounds how far the host runs ahead
+  void *inst_host[kRing] = {}, *inst_dev[kRing] = {};
+  int32_t *tile_host[kRing] = {}, *tile_dev[kRing] = {};
+  hipEvent_t ring_ev[kRing] = {};
+  int ring = 0;
+  std::vector<hipEvent_t> ev_free;
+
+  hj_server_stats stats = {};
+};
+
+namespace {
+
+void server_free(hj_server *S) {
+  for (auto &kv : S->reqs)
+    if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
+  for (hipEvent_t e : S->ev_free) (void)hipEventDestroy(e);
+  for (auto &sl : S->slots)
+    if (sl.g) (void)hj_grid_destroy(sl.g);
+  for (int i = 0; i < hj_server::kRing; ++i) {
+    if (S->ring_ev[i]) (void)hipEventDestroy(S->ring_ev[i]);
+    if (S->inst_dev[i]) (void)hipFree(S->inst_dev[i]);
+    if (S->tile_dev[i]) (void)hipFree(S->tile_dev[i]);
+    if (S->inst_host[i]) (void)hipHostFree(S->inst_host[i]);
+    if (S->tile_host[i]) (void)hipHostFree(S->tile_host[i]);
+  }
+}
+
+bool same_problem(const hj_grid *G, const hj_grid_desc &g, const hj_dynamics_desc &dyn) {
+  return memcmp(&G->g, &g, sizeof g) == 0 && memcmp(&G->dyn, &dyn, sizeof dyn) == 0;
+}
+
+// Device bytes a slot of this grid holds (the handle's arrays).
+int64_t slot_bytes_of(const hj_server *S, const hj_grid_desc &g) {
+  int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2] * g.n[3];
+  int arrays = S->d.scheme.integrator == HJ_TVD_RK2 ? 4 : 3;
+  int64_t m = (int64_t)g.n[2] * g.n[3];
+  return (int64_t)S->elem * (arrays * n + 8 * m + (int64_t)g.n[0] * g.n[1]) + 16 * m;
+}
+
+hj_status server_event(hj_server *S, hipEvent_t *e) {
+  if (!S->ev_free.empty()) {
+    *e = S->ev_free.back();
+    S->ev_free.pop_back();
+    return HJ_OK;
+  }
+  HJ_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return HJ_OK;
+}
+
+// A slot for request q: a free slot of the same problem, else a new one
+// within the budget (destroying idle slots, least recently used first).
+// Returns -1 in *slot when the request has to wait.
+hj_status server_find_slot(hj_server *S, hj_server::Req &q, int *slot) {
+  *slot = -1;
+  int best = -1;
+  for (size_t i = 0; i < S->slots.size(); ++i) {
+    const auto &sl = S->slots[i];
+    if (sl.g && !sl.busy && same_problem(sl.g, q.g, q.dyn)) {
+      if (best < 0 || sl.last_use > S->slots[best].last_use) best = (int)i;
+    }
+  }
+  if (best >= 0) {
+    *slot = best;
+    return HJ_OK;
+  }
+  int64_t need = slot_bytes_of(S, q.g);
+  while (S->d.hbm_budget > 0 && S->slot_bytes + need > S->d.hbm_budget) {
+    int victim = -1;
+    for (size_t i = 0; i < S->slots.size(); ++i) {
+      const auto &sl = S->slots[i];
+      if (sl.g && !sl.busy && (victim < 0 || sl.last_use < S->slots[victim].last_use)) victim = (int)i;
+    }
+    if (victim < 0) return HJ_OK;  // everything is in use: wait
+    hj_status st = hj_grid_destroy(S->slots[victim].g);
+    if (st != HJ_OK) return st;
+    S->slot_bytes -= S->slots[victim].bytes;
+    S->slots[victim] = hj_server::Slot();
+  }
+  hj_grid *G = nullptr;
+  hj_status st = hj_grid_create(&q.g, &q.dyn, &S->d.scheme, S->stream, &G);
+  if (st != HJ_OK) return st;
+  G->autotune_on = false;
+  hj_server::Slot sl;
+  sl.g = G;
+  sl.bytes = need;
+  S->slot_bytes += need;
+  for (size_t i = 0; i < S->slots.size(); ++i)
+    if (!S->slots[i].g) {
+      S->slots[i] = sl;
+      *slot = (int)i;
+      return HJ_OK;
+    }
+  S->slots.push_back(sl);
+  *slot = (int)S->slots.size() - 1;
+  return HJ_OK;
+}
+
+hj_status server_admit(hj_server *S) {
+  hj_status st;
+  while (!S->queue.empty() && (int)S->running.size() < S->d.max_inflight) {
+    const int64_t id = S->queue.front();
+    hj_server::Req &q = S->reqs[id];
+    int slot;
+    if ((st = server_find_slot(S, q, &slot)) != HJ_OK) return st;
+    if (slot < 0) break;  // head of the queue waits for memory
+    hj_grid *G = S->slots[slot].g;
+    if ((st = hj_set_target_cylinders(G, q.cx.data(), q.cy.data(), q.r.data(), (int32_t)q.cx.size())) != HJ_OK)
+      return st;
+    if ((st = ensure_dt(G)) != HJ_OK) return st;
+    schedule(G, q.horizon, &q.n, &q.dt, &q.dt_last);
+    S->slots[slot].busy = true;
+    S->slots[slot].last_use = S->stats.ticks;
+    q.slot = slot;
+    q.k = 0;
+    S->queue.pop_front();
+    S->stats.admitted += 1;
+    if (q.n == 0) {  // V = V0, already written with the target
+      if ((st = server_event(S, &q.ev)) != HJ_OK) return st;
+      HJ_HIP(hipEventRecord(q.ev, S->stream));
+      q.state = 2;
+    } else {
+      q.state = 1;
+      S->running.push_back(id);
+    }
+  }
+  return HJ_OK;
+}
+
+// One step of request q at its step k + s on its own handle (the handle's
+// stage kernel and chunking; the buffer roles follow the batch convention:
+// V^0 = V0, V^k in v (k even) or w2 (k odd)).
+template <typename T>
+hj_status server_step_alone(hj_server *S, hj_server::Req &q, int64_t k) {
+  hj_grid *G = S->slots[q.slot].g;
+  const T *cur = k == 0 ? buf<const T>(G->v0) : ((k & 1) ? buf<const T>(G->w2) : buf<const T>(G->v));
+  T *nxt = (k & 1) ? buf<T>(G->v) : buf<T>(G->w2);
+  const double dt = k == q.n - 1 ? q.dt_last : q.dt;
+  const int clamp = S->d.scheme.clamp == HJ_CLAMP_MIN_V0;
+  if (S->d.scheme.integrator == HJ_EULER) return launch_one_stage<T>(G, cur, nullptr, nxt, hj::kPlain, clamp, dt);
+  hj_status st = launch_one_stage<T>(G, cur, nullptr, buf<T>(G->w1), hj::kPlain, 0, dt);
+  if (st != HJ_OK) return st;
+  return launch_one_stage<T>(G, buf<const T>(G->w1), cur, nxt, hj::kAverage, clamp, dt);
+}
+
+template <typename T>
+hj_status server_step(hj_server *S) {
+  const int m = (int)S->running.size();
+  if (m == 0) return HJ_OK;
+  const int r = S->ring;
+  S->ring = (r + 1) % hj_server::kRing;
+  HJ_HIP(hipEventSynchronize(S->ring_ev[r]));  // this ring slot's previous launches are done
+  // longest remaining first, so the requests still stepping at step s of
+  // this tick are a prefix of each group
+  std::stable_sort(S->running.begin(), S->running.end(), [&](int64_t x, int64_t y) {
+    const hj_server::Req &a = S->reqs[x], &b = S->reqs[y];
+    return a.n - a.k > b.n - b.k;
+  });
+  const int64_t spt = S->d.steps_per_tick > 0 ? S->d.steps_per_tick : 4;
+  // large grids fill the device alone and step on their own handle's
+  // kernel; the others share one launch per stage and step
+  std::vector<int> big, small;
+  for (int i = 0; i < m; ++i) {
+    const hj_grid *G = S->slots[S->reqs[S->running[i]].slot].g;
+    (G->npts >= kServerAlonePoints ? big : small).push_back(i);
+  }
+  hj::BatchInst<T> *inst = static_cast<hj::BatchInst<T> *>(S->inst_host[r]);
+  int32_t *tile_end = S->tile_host[r];
+  // tile length: the server's, else x cut so that one launch over the small
+  // requests has about kServerBlocks blocks
+  int64_t row_blocks = 0;
+  for (int i : small) {
+    const hj_grid *G = S->slots[S->reqs[S->running[i]].slot].g;
+    int run = hj::run_length((int)sizeof(T), G->g.n[3]);
+    row_blocks += ((int64_t)G->g.n[1] * G->g.n[2] * (G->g.n[3] / run) + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  }
+  const int64_t want = row_blocks > 0 ? (kServerBlocks + row_blocks - 1) / row_blocks : 1;
+  bool sg = false, ball = false;
+  int64_t acc = 0;
+  std::vector<int64_t> remain(m);
+  for (int i = 0; i < m; ++i) {
+    hj_server::Req &q = S->reqs[S->running[i]];
+    remain[i] = q.n - q.k;
+  }
+  for (size_t u = 0; u < small.size(); ++u) {
+    hj_server::Req &q = S->reqs[S->running[small[u]]];
+    hj_grid *G = S->slots[q.slot].g;
+    hj::BatchInst<T> &in = inst[u];
+    memset(&in, 0, sizeof in);
+    int chunks;
+    if (S->d.x_planes > 0) {
+      chunks = (G->g.n[0] + S->d.x_planes - 1) / S->d.x_planes;
+    } else {
+      int cap = G->g.n[0] / 4 > 1 ? G->g.n[0] / 4 : 1;
+      chunks = (int)(want < cap ? want : cap);
+    }
+    in.a = batch_stream_args<T>(G, chunks);
+    in.v0 = buf<const T>(G->v0);
+    in.va = buf<T>(G->v);
+    in.vb = buf<T>(G->w2);
+    in.w1 = S->d.scheme.integrator == HJ_TVD_RK2 ? buf<T>(G->w1) : nullptr;
+    in.dt = (T)q.dt;
+    in.dt_last = (T)q.dt_last;
+    in.steps = (int32_t)q.n;
+    in.k = (int32_t)q.k;
+    in.rk2 = S->d.scheme.integrator == HJ_TVD_RK2 ? 1 : 0;
+    in.clamp = S->d.scheme.clamp == HJ_CLAMP_MIN_V0 ? 1 : 0;
+    in.tiles = in.a.blocks_per_chunk * in.a.n_chunks;
+    acc += in.tiles;
+    tile_end[u] = (int32_t)acc;
+    if (G->sig[0] != 0.0 || G->sig[1] != 0.0) sg = true;
+    if (G->ball_mask != 0) ball = true;
+  }
+  if (acc >= ((int64_t)1 << 31)) return fail(HJ_ERR_UNSUPPORTED, "too many tiles in one tick");
+  if (!small.empty()) {
+    HJ_HIP(hipMemcpyAsync(S->tile_dev[r], tile_end, small.size() * sizeof(int32_t), hipMemcpyHostToDevice, S->stream));
+    HJ_HIP(hipMemcpyAsync(S->inst_dev[r], inst, small.size() * sizeof(hj::BatchInst<T>), hipMemcpyHostToDevice,
+                          S->stream));
+  }
+  const hj::BatchInst<T> *di = static_cast<const hj::BatchInst<T> *>(S->inst_dev[r]);
+  const int stages = S->d.scheme.integrator == HJ_TVD_RK2 ? 2 : 1;
+  const int64_t nsteps = remain[0] < spt ? remain[0] : spt;
+  int act = (int)small.size();
+  for (int64_t s = 0; s < nsteps; ++s) {
+    // requests that took their last step at s - 1: their V is final once
+    // the launches enqueued so far have run
+    for (int i = 0; i < m; ++i)
+      if (remain[i] == s) {
+        hj_server::Req &q = S->reqs[S->running[i]];
+        hj_status st = server_event(S, &q.ev);
+        if (st != HJ_OK) return st;
+        HJ_HIP(hipEventRecord(q.ev, S->stream));
+      }
+    while (act > 0 && remain[small[act - 1]] <= s) --act;
+    for (int st = 0; st < stages && act > 0; ++st)
+      HJ_HIP(hj::launch_multi<T>(di, S->tile_dev[r], act, tile_end[act - 1], (int)(-1 - s), st, S->d.scheme.deriv,
+                                 sg, ball, S->stream));
+    for (int i : big)
+      if (remain[i] > s) {
+        hj_server::Req &q = S->reqs[S->running[i]];
+        hj_status st = server_step_alone<T>(S, q, q.k + s);
+        if (st != HJ_OK) return st;
+      }
+  }
+  HJ_HIP(hipEventRecord(S->ring_ev[r], S->stream));
+  // advance; retire the requests that took their last step
+  std::vector<int64_t> still;
+  for (int i = 0; i < m; ++i) {
+    const int64_t id = S->running[i];
+    hj_server::Req &q = S->reqs[id];
+    q.k += remain[i] < nsteps ? remain[i] : nsteps;
+    if (q.k < q.n) {
+      still.push_back(id);
+      continue;
+    }
+    hj_grid *G = S->slots[q.slot].g;
+    if (q.n & 1) {  // V^n is in w2
+      void *t = G->v;
+      G->v = G->w2;
+      G->w2 = t;
+    }
+    if (!q.ev) {  // finished at the last step of the tick
+      hj_status st = server_event(S, &q.ev);
+      if (st != HJ_OK) return st;
+      HJ_HIP(hipEventRecord(q.ev, S->stream));
+    }
+    q.state = 2;
+  }
+  S->running.swap(still);
+  return HJ_OK;
+}
+
+hj_status check_server(hj_server *S) {
+  if (!S) return fail(HJ_ERR_INVALID_ARG, "null server");
+  return HJ_OK;
+}
+
+void server_counts(hj_server *S) {
+  S->stats.running = (int32_t)S->running.size();
+  S->stats.queued = (int32_t)S->queue.size();
+  int32_t n = 0;
+  for (auto &sl : S->slots)
+    if (sl.g) ++n;
+  S->stats.slots = n;
+  S->stats.slot_bytes = S->slot_bytes;
+}
+
+hj_status server_release_slot(hj_server *S, int64_t id) {
+  auto it = S->reqs.find(id);
+  hj_server::Req &q = it->second;
+  S->slots[q.slot].busy = false;
+  S->slots[q.slot].last_use = S->stats.ticks;
+  if (q.ev) S->ev_free.push_back(q.ev);
+  S->reqs.erase(it);
+  return HJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hj_status hj_server_create(const hj_server_desc *desc, void *hip_stream, hj_server **out) {
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output handle pointer");
+  *out = nullptr;
+  if (!desc) return fail(HJ_ERR_INVALID_ARG, "null server description");
+  if (desc->max_inflight < 1 || desc->max_inflight > hj::kMaxBatch)
+    return fail(HJ_ERR_INVALID_ARG, "max_inflight must be 1..%d", hj::kMaxBatch);
+  if (desc->hbm_budget < 0 || desc->x_planes < 0 || desc->steps_per_tick < 0)
+    return fail(HJ_ERR_INVALID_ARG, "negative budget, tile or steps per tick");
+  const hj_scheme_desc &sc = desc->scheme;
+  if ((sc.deriv != HJ_UPWIND1 && sc.deriv != HJ_ENO2) || (sc.integrator != HJ_EULER && sc.integrator != HJ_TVD_RK2) ||
+      (sc.precision != HJ_F32 && sc.precision != HJ_F64) || (sc.clamp != HJ_CLAMP_NONE && sc.clamp != HJ_CLAMP_MIN_V0) ||
+      !(sc.cfl > 0.0 && sc.cfl <= 1.0))
+    return fail(HJ_ERR_INVALID_ARG, "invalid scheme");
+  hj_server *S = new (std::nothrow) hj_server;
+  if (!S) return fail(HJ_ERR_OUT_OF_MEMORY, "host allocation failed");
+  S->d = *desc;
+  S->stream = static_cast<hipStream_t>(hip_stream);
+  S->elem = sc.precision == HJ_F32 ? 4 : 8;
+  size_t inst_bytes = (size_t)hj::kMaxBatch * (S->elem == 4 ? sizeof(hj::BatchInst<float>) : sizeof(hj::BatchInst<double>));
+  hipError_t e = hipGetDevice(&S->device);
+  for (int i = 0; i < hj_server::kRing && e == hipSuccess; ++i) {
+    e = hipMalloc(&S->inst_dev[i], inst_bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&S->inst_host[i], inst_bytes, 0);
+    if (e == hipSuccess) e = hipMalloc((void **)&S->tile_dev[i], hj::kMaxBatch * sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&S->tile_host[i], hj::kMaxBatch * sizeof(int32_t), 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ring_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(S->ring_ev[i], S->stream);
+  }
+  if (e != hipSuccess) {
+    server_free(S);
+    delete S;
+    return fail(e == hipErrorOutOfMemory ? HJ_ERR_OUT_OF_MEMORY : HJ_ERR_DEVICE, "hj_server_create: %s",
+                hipGetErrorString(e));
+  }
+  *out = S;
+  return HJ_OK;
+}
+
+hj_status hj_server_destroy(hj_server *S) {
+  if (!S) return HJ_OK;
+  (void)hipSetDevice(S->device);
+  (void)hipStreamSynchronize(S->stream);
+  server_free(S);
+  delete S;
+  return HJ_OK;
+}
+
+hj_status hj_server_submit(hj_server *S, const hj_grid_desc *grid, const hj_dynamics_desc *dyn, const double *cx,
+                           const double *cy, const double *r, int32_t m, double horizon, int64_t *id) {
+  hj_status st = check_server(S);
+  if (st != HJ_OK) return st;
+  if (!id) return fail(HJ_ERR_INVALID_ARG, "null id output");
+  if (!isfinite(horizon) || horizon < 0) return fail(HJ_ERR_INVALID_ARG, "horizon must be finite and >= 0");
+  if ((st = validate(grid, dyn, &S->d.scheme)) != HJ_OK) return st;
+  if (!cx || !cy || !r || m < 1) return fail(HJ_ERR_INVALID_ARG, "need at least one obstacle");
+  if (bit(grid->periodic_mask, 0) || bit(grid->periodic_mask, 1))
+    return fail(HJ_ERR_INVALID_ARG, "cylinder targets need open x and y axes");
+  if (!bit(grid->periodic_mask, 3)) return fail(HJ_ERR_UNSUPPORTED, "serving needs a periodic theta axis");
+  for (int o = 0; o < m; ++o)
+    if (!isfinite(cx[o]) || !isfinite(cy[o]) || !isfinite(r[o]) || r[o] < 0)
+      return fail(HJ_ERR_INVALID_ARG, "obstacle %d: need finite centre and radius >= 0", o);
+  if (S->d.hbm_budget > 0 && slot_bytes_of(S, *grid) > S->d.hbm_budget)
+    return fail(HJ_ERR_OUT_OF_MEMORY, "one grid of this size exceeds the server's memory budget");
+  hj_server::Req q;
+  q.g = *grid;
+  q.dyn = *dyn;
+  q.cx.assign(cx, cx + m);
+  q.cy.assign(cy, cy + m);
+  q.r.assign(r, r + m);
+  q.horizon = horizon;
+  int64_t nid = S->next_id++;
+  S->reqs[nid] = q;
+  S->queue.push_back(nid);
+  S->stats.submitted += 1;
+  *id = nid;
+  return HJ_OK;
+}
+
+hj_status hj_server_tick(hj_server *S, int32_t *running) {
+  hj_status st = check_server(S);
+  if (st != HJ_OK) return st;
+  HJ_HIP(hipSetDevice(S->device));
+  if ((st = server_admit(S)) != HJ_OK) return st;
+  st = S->elem == 4 ? server_step<float>(S) : server_step<double>(S);
+  if (st != HJ_OK) return st;
+  S->stats.ticks += 1;
+  if (running) *running = (int32_t)S->running.size();
+  return HJ_OK;
+}
+
+hj_status hj_server_poll(hj_server *S, int64_t *ids, int32_t cap, int32_t *n) {
+  hj_status st = check_server(S);
+  if (st != HJ_OK) return st;
+  if (!n || (cap > 0 && !ids)) return fail(HJ_ERR_INVALID_ARG, "null output");
+  *n = 0;
+  for (auto &kv : S->reqs) {
+    hj_server::Req &q = kv.second;
+    if (q.state == 2) {
+      hipError_t e = hipEventQuery(q.ev);
+      if (e == hipSuccess) {
+        q.state = 3;
+        S->stats.completed += 1;
+      } else if (e != hipErrorNotReady) {
+        return fail(HJ_ERR_DEVICE, "hj_server_poll: %s", hipGetErrorString(e));
+      }
+    }
+    if (q.state == 3 && *n < cap) ids[(*n)++] = kv.first;
+  }
+  return HJ_OK;
+}
+
+hj_status hj_server_take(hj_server *S, int64_t id, void *out, int32_t dtype, int32_t where) {
+  hj_status st = check_server(S);
+  if (st != HJ_OK) return st;
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) return fail(HJ_ERR_INVALID_ARG, "unknown request %lld", (long long)id);
+  if (it->second.state != 3) return fail(HJ_ERR_NOT_READY, "request %lld is not complete", (long long)id);
+  if (out && (st = hj_get_value(S->slots[it->second.slot].g, out, dtype, where)) != HJ_OK) return st;
+  return server_release_slot(S, id);
+}
+
+hj_status hj_server_get_stats(hj_server *S, hj_server_stats *out) {
+  hj_status st = check_server(S);
+  if (st != HJ_OK) return st;
+  if (!out) return fail(HJ_ERR_INVALID_ARG, "null output");
+  server_counts(S);
+  *out = S->stats;
   return HJ_OK;
 }
 

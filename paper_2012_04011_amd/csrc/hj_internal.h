@@ -117,6 +117,7 @@ struct BatchInst {
   int32_t rk2;     // 1: TVD-RK2 (two phases per step), 0: Euler (one)
   int32_t clamp;   // min(V0, .) after the last stage of a step
   int32_t tiles;   // blocks of one phase: a.blocks_per_chunk * a.n_chunks
+  int32_t k;       // the instance's own step, for launches given k < 0
 };
 
 constexpr int kMaxBatch = 256;
@@ -148,7 +149,8 @@ struct PersistArgs {
 };
 
 // One launch of phase (k, stage) over the first ninst instances (their
-// tiles are blocks 0 .. tile_end[ninst-1]-1, XCD-contiguous).
+// tiles are blocks 0 .. tile_end[ninst-1]-1, XCD-contiguous); k < 0: each
+// instance at its own step inst[j].k + (-1 - k).
 template <typename T>
 hipError_t launch_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int k, int stage,
                         int deriv, bool sg, bool ball, hipStream_t s);

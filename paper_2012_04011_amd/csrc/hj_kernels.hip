@@ -1105,7 +1105,7 @@ __global__ __launch_bounds__(kStreamBlock) void stage_multi(const BatchInst<T> *
   const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
   const int j = find_end(tile_end, ninst, lb);
   StreamArgs<T> a = inst[j].a;
-  phase_args(a, inst[j], k, stage);
+  phase_args(a, inst[j], k >= 0 ? k : inst[j].k + (-1 - k), stage);
   tile_any_run<T, DERIV, SG, BALL>(a, lb - (j > 0 ? tile_end[j - 1] : 0));
 }
 
@@ -1146,14 +1146,17 @@ __global__ __launch_bounds__(kStreamBlock) void stage_persistent(PersistArgs<T> 
       }
       if (!ok) __hip_atomic_store(&q->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_abort = !ok;
+      // the acquire above invalidated this CU's L1 and the stale L2 lines
+      // for the whole block; the barrier orders the other waves' loads after it
     }
     __syncthreads();
     if (s_abort) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the previous phase's results
     StreamArgs<T> a = p.inst[j].a;
     phase_args(a, p.inst[j], ph / p.phases_per_step, ph % p.phases_per_step);
     tile_any_run<T, DERIV, SG, BALL>(a, tile);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this tile's stores
+    // every wave's stores complete, then one agent-scope release (L2
+    // write-back) publishes the block's tile with the counter
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_fetch_add(&q->done[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }

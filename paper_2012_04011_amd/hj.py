@@ -42,7 +42,9 @@ EXPORTED = [
     "hj_step", "hj_get_cfl_dt", "hj_get_alpha_max", "hj_get_value", "hj_get_target", "hj_set_value",
     "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_get_launch_info", "hj_autotune",
     "hj_set_autotune", "hj_batch_create", "hj_batch_destroy", "hj_batch_solve", "hj_batch_set_tile",
-    "hj_batch_set_spin_limit", "hj_batch_autotune", "hj_batch_get_info", "hj_last_error", "hj_version",
+    "hj_batch_set_spin_limit", "hj_batch_autotune", "hj_batch_get_info", "hj_server_create", "hj_server_destroy",
+    "hj_server_submit", "hj_server_tick", "hj_server_poll", "hj_server_take", "hj_server_get_stats",
+    "hj_last_error", "hj_version",
 ]
 
 
@@ -85,6 +87,17 @@ class hj_batch_info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("x_planes", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
                 ("graph_nodes", ctypes.c_int32), ("tiles_per_sweep", ctypes.c_int64),
                 ("work_items", ctypes.c_int64), ("points", ctypes.c_int64)]
+
+
+class hj_server_desc(ctypes.Structure):
+    _fields_ = [("scheme", hj_scheme_desc), ("hbm_budget", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("x_planes", ctypes.c_int32), ("steps_per_tick", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class hj_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("running", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("pad", ctypes.c_int32), ("slot_bytes", ctypes.c_int64)]
 
 
 class hj_profile(ctypes.Structure):
@@ -137,6 +150,13 @@ def load_library(path: str = LIB_PATH):
         "hj_batch_set_spin_limit": [vp, i64],
         "hj_batch_autotune": [vp, P(dbl), i32, P(i32)],
         "hj_batch_get_info": [vp, P(hj_batch_info)],
+        "hj_server_create": [P(hj_server_desc), vp, P(vp)],
+        "hj_server_destroy": [vp],
+        "hj_server_submit": [vp, P(hj_grid_desc), P(hj_dynamics_desc), P(dbl), P(dbl), P(dbl), i32, dbl, P(i64)],
+        "hj_server_tick": [vp, P(i32)],
+        "hj_server_poll": [vp, P(i64), i32, P(i32)],
+        "hj_server_take": [vp, i64, vp, i32, i32],
+        "hj_server_get_stats": [vp, P(hj_server_stats)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -373,6 +393,58 @@ def hj_batch_get_info(b: int) -> dict:
     return {f: getattr(i, f) for f, _ in hj_batch_info._fields_}
 
 
+def hj_server_create(scheme: dict, precision: str = "f32", hbm_budget: int = 0, max_inflight: int = 64,
+                     x_planes: int = 0, stream=None, steps_per_tick: int = 0) -> int:
+    d = hj_server_desc()
+    d.scheme = scheme_desc(scheme, precision)
+    d.hbm_budget, d.max_inflight, d.x_planes = int(hbm_budget), int(max_inflight), int(x_planes)
+    d.steps_per_tick = int(steps_per_tick)
+    out = ctypes.c_void_p()
+    _check(_lib.hj_server_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(out)), "hj_server_create")
+    return out.value
+
+
+def hj_server_destroy(s: int) -> None:
+    _check(_lib.hj_server_destroy(s), "hj_server_destroy")
+
+
+def hj_server_submit(s: int, grid: dict, dyn: dict, cx, cy, r, horizon: float) -> int:
+    g, d = grid_desc(grid), dynamics_desc(dyn)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (cx, cy, r)]
+    P = ctypes.POINTER(ctypes.c_double)
+    out = ctypes.c_int64()
+    _check(_lib.hj_server_submit(s, ctypes.byref(g), ctypes.byref(d), *[a.ctypes.data_as(P) for a in arrs],
+                                 len(arrs[0]), float(horizon), ctypes.byref(out)), "hj_server_submit")
+    return out.value
+
+
+def hj_server_tick(s: int) -> int:
+    n = ctypes.c_int32()
+    _check(_lib.hj_server_tick(s, ctypes.byref(n)), "hj_server_tick")
+    return n.value
+
+
+def hj_server_poll(s: int, cap: int = 256) -> list:
+    ids = (ctypes.c_int64 * cap)()
+    n = ctypes.c_int32()
+    _check(_lib.hj_server_poll(s, ids, cap, ctypes.byref(n)), "hj_server_poll")
+    return list(ids[:n.value])
+
+
+def hj_server_take(s: int, rid: int, out=None) -> None:
+    if out is None:
+        _check(_lib.hj_server_take(s, int(rid), None, HJ_F64, HJ_HOST), "hj_server_take")
+        return
+    p, dt, where = _array_arg(out)
+    _check(_lib.hj_server_take(s, int(rid), p, dt, where), "hj_server_take")
+
+
+def hj_server_get_stats(s: int) -> dict:
+    st = hj_server_stats()
+    _check(_lib.hj_server_get_stats(s, ctypes.byref(st)), "hj_server_get_stats")
+    return {f: getattr(st, f) for f, _ in hj_server_stats._fields_ if f != "pad"}
+
+
 def hj_last_error() -> str:
     return load_library().hj_last_error().decode()
 
@@ -502,3 +574,43 @@ class Batch:
 
     def info(self) -> dict:
         return hj_batch_get_info(self.handle)
+
+
+class Server:
+    """Continuous-batching re-solve server (see hj_server_create)."""
+
+    def __init__(self, scheme: dict, precision: str = "f32", hbm_budget: int = 0, max_inflight: int = 64,
+                 x_planes: int = 0, stream=None, steps_per_tick: int = 0):
+        self.handle = hj_server_create(scheme, precision, hbm_budget, max_inflight, x_planes, stream, steps_per_tick)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hj_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, grid: dict, dyn: dict, cylinders, horizon: float) -> int:
+        return hj_server_submit(self.handle, grid, dyn, *cylinders, horizon)
+
+    def tick(self) -> int:
+        return hj_server_tick(self.handle)
+
+    def poll(self) -> list:
+        return hj_server_poll(self.handle)
+
+    def take(self, rid: int, out=None):
+        hj_server_take(self.handle, rid, out)
+
+    def stats(self) -> dict:
+        return hj_server_get_stats(self.handle)

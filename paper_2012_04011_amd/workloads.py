@@ -157,3 +157,53 @@ def batch_instances(count: int = 64, seed0: int = 1000, sizes=((30, 80), (30, 80
 # 64 uneven instances, 30x30x12x18 .. 80x80x24x48, 1-8 cylinders,
 # horizons in [0.5, 2] s, FP32 ENO2 + TVD-RK2 (the batched workload).
 BATCH_64 = dict(count=64, seed0=1000)
+
+
+@dataclass
+class Request:
+    """A re-solve request of a served stream."""
+    arrival: float   # seconds after the stream starts
+    cls: int         # grid class
+    grid: dict
+    dyn: dict
+    cylinders: tuple
+    horizon: float
+
+
+# Served mix: the paper's grid 60x60x20x36 and a finer 100x100x24x48.
+SERVE_GRIDS = (car_grid(60, 60, 20, 36), car_grid(100, 100, 24, 48))
+
+
+def serving_requests(count: int, rate: float = 20.0, seed: int = 7, mix: float = 0.7, horizon: float = 1.5,
+                     grids=SERVE_GRIDS, cap: int = 8) -> list:
+    """Poisson arrivals (exponential gaps at `rate` per second from
+    default_rng(seed)); each request picks grid class 0 with probability
+    `mix` (same stream), then, from default_rng(7000 + i), changes that
+    class's obstacle map (which starts as cylinders(70 + class, 3)) 1-3
+    times: add a cylinder (centre U[-3, 3]^2, radius U[0.4, 1.0]) when fewer
+    than `cap` and a fair coin says so, else move a random one by
+    U[-0.5, 0.5]^2 (clipped to [-3, 3]).  The request carries a copy of the
+    map."""
+    rng = np.random.default_rng(seed)
+    scenes = {}
+    for c in range(len(grids)):
+        cx, cy, r = cylinders(70 + c, 3)
+        scenes[c] = [(float(a), float(b), float(d)) for a, b, d in zip(cx, cy, r)]
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        c = 0 if rng.uniform() < mix else 1
+        r2 = np.random.default_rng(7000 + i)
+        scene = scenes[c]
+        for _ in range(int(r2.integers(1, 4))):
+            if len(scene) < cap and r2.uniform() < 0.5:
+                scene.append((float(r2.uniform(-3, 3)), float(r2.uniform(-3, 3)), float(r2.uniform(0.4, 1.0))))
+            else:
+                j = int(r2.integers(0, len(scene)))
+                x, y, rad = scene[j]
+                scene[j] = (float(np.clip(x + r2.uniform(-0.5, 0.5), -3, 3)),
+                            float(np.clip(y + r2.uniform(-0.5, 0.5), -3, 3)), rad)
+        cyl = tuple(np.array(v, dtype=np.float64) for v in zip(*scene))
+        out.append(Request(t, c, grids[c], car_dynamics(), cyl, horizon))
+    return out

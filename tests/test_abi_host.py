@@ -142,3 +142,33 @@ def test_batch_null_and_range_arguments(lib):
 
 def test_batch_info_layout():
     assert ctypes.sizeof(hj.hj_batch_info) == 40
+
+
+def test_server_null_and_range_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.hj_server_create(None, None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    d = hj.hj_server_desc()
+    d.scheme = hj.scheme_desc(W.scheme("eno2", "rk2"), "f32")
+    d.max_inflight = 0
+    assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    d.max_inflight = 300
+    assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    d.max_inflight = 4
+    d.hbm_budget = -1
+    assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    d.hbm_budget = 0
+    d.scheme.cfl = 0.0
+    assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_server_create(ctypes.byref(d), None, None) == hj.HJ_ERR_INVALID_ARG
+    i64 = ctypes.c_int64()
+    assert lib.hj_server_submit(None, None, None, None, None, None, 1, 1.0, ctypes.byref(i64)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_server_tick(None, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_server_poll(None, None, 0, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_server_take(None, 1, None, 0, 0) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_server_get_stats(None, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_server_destroy(None) == hj.HJ_OK
+
+
+def test_server_struct_layouts():
+    assert ctypes.sizeof(hj.hj_server_desc) == 48
+    assert ctypes.sizeof(hj.hj_server_stats) == 56

@@ -1,0 +1,179 @@
+"""The continuous-batching server (hj_server_*): requests that arrive while
+others are stepping are admitted as slots and memory free up, step together
+in shared launches, and each result equals the same re-solve alone (a fresh
+handle's hj_solve_brt) bit for bit; the memory budget bounds the slots."""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_04011_amd import workloads as W
+
+from helpers import assert_f64_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_04011_amd import hj
+
+    hj.load_library()
+
+
+SMALL_GRIDS = (W.car_grid(20, 18, 8, 12), W.car_grid(16, 17, 6, 9))
+
+
+def small_requests(n=10):
+    return W.serving_requests(n, rate=1000.0, seed=3, mix=0.6, horizon=0.4, grids=SMALL_GRIDS)
+
+
+def alone(hj, req, precision="f32", scheme=None):
+    with hj.Grid(req.grid, req.dyn, scheme or W.scheme("eno2", "rk2"), precision) as g:
+        g.set_target_cylinders(*req.cylinders)
+        info = g.solve_brt(req.horizon)
+        return g.value(np.float64), info
+
+
+def drain(srv, ids, results, shapes, max_ticks=100000):
+    ticks = 0
+    while len(results) < len(ids):
+        srv.tick()
+        ticks += 1
+        assert ticks < max_ticks
+        for rid in srv.poll():
+            out = np.empty(shapes[rid], np.float64)
+            srv.take(rid, out)
+            results[rid] = out
+    return ticks
+
+
+@pytest.mark.parametrize("max_inflight,steps_per_tick", [(3, 1), (5, 3), (64, 0)])
+def test_served_equals_alone(max_inflight, steps_per_tick):
+    """Requests submitted between ticks (others already stepping), a queue
+    when max_inflight is small, slots reused across requests of one shape,
+    requests finishing inside a multi-step tick."""
+    from paper_2012_04011_amd import hj
+
+    reqs = small_requests(10)
+    ref = [alone(hj, r)[0] for r in reqs]
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=max_inflight,
+                   steps_per_tick=steps_per_tick) as srv:
+        ids, shapes, results = [], {}, {}
+        for i, r in enumerate(reqs):
+            rid = srv.submit(r.grid, r.dyn, r.cylinders, r.horizon)
+            ids.append(rid)
+            shapes[rid] = tuple(r.grid["n"])
+            if i % 3 == 2:  # let the running ones step before the next arrivals
+                for _ in range(4):
+                    srv.tick()
+                for rid2 in srv.poll():
+                    out = np.empty(shapes[rid2], np.float64)
+                    srv.take(rid2, out)
+                    results[rid2] = out
+        drain(srv, ids, results, shapes)
+        st = srv.stats()
+        assert st["submitted"] == st["admitted"] == st["completed"] == len(reqs)
+        assert st["running"] == 0 and st["queued"] == 0
+        # finished requests hold their slot until taken, so slots can exceed
+        # max_inflight without a budget; one slot per request at most
+        assert 1 <= st["slots"] <= len(reqs)
+    for rid, r in zip(ids, ref):
+        assert np.array_equal(results[rid], r), rid
+
+
+def test_server_budget_bounds_slots():
+    """A budget of two slots of the larger shape: at most that many bytes are
+    held, idle slots of the other shape are freed to fit, all results right."""
+    from paper_2012_04011_amd import hj
+
+    reqs = small_requests(8)
+    ref = [alone(hj, r)[0] for r in reqs]
+    n_big = max(int(np.prod(g["n"])) for g in SMALL_GRIDS)
+    budget = 2 * (4 * n_big * 4 + 4 * 8 * 20 * 12 + 4 * 20 * 18 + 16 * 8 * 12) + 1
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", hbm_budget=budget, max_inflight=8) as srv:
+        ids, shapes, results = [], {}, {}
+        for r in reqs:
+            rid = srv.submit(r.grid, r.dyn, r.cylinders, r.horizon)
+            ids.append(rid)
+            shapes[rid] = tuple(r.grid["n"])
+        peak = 0
+        while len(results) < len(ids):
+            srv.tick()
+            peak = max(peak, srv.stats()["slot_bytes"])
+            for rid in srv.poll():
+                out = np.empty(shapes[rid], np.float64)
+                srv.take(rid, out)
+                results[rid] = out
+        assert peak <= budget
+    for rid, r in zip(ids, ref):
+        assert np.array_equal(results[rid], r), rid
+
+
+def test_server_zero_horizon_and_errors():
+    from paper_2012_04011_amd import hj
+
+    req = small_requests(1)[0]
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=2) as srv:
+        rid = srv.submit(req.grid, req.dyn, req.cylinders, 0.0)
+        with pytest.raises(hj.HJError):
+            srv.take(rid)  # not complete yet
+        results = {}
+        drain(srv, [rid], results, {rid: tuple(req.grid["n"])})
+        ref, info = alone(hj, dataclasses.replace(req, horizon=0.0))
+        assert info["steps"] == 0 and np.array_equal(results[rid], ref)
+        with pytest.raises(hj.HJError):
+            srv.take(rid)  # already taken
+        with pytest.raises(hj.HJError):
+            srv.submit(req.grid, req.dyn, req.cylinders, -1.0)
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", hbm_budget=1000) as srv:
+        with pytest.raises(hj.HJError) as e:
+            srv.submit(req.grid, req.dyn, req.cylinders, 0.3)
+        assert e.value.status == hj.HJ_ERR_OUT_OF_MEMORY
+
+
+def test_served_fp64_matches_oracle():
+    from paper_2012_04011_amd import hj
+
+    reqs = small_requests(3)
+    with hj.Server(W.scheme("eno2", "rk2"), "f64", max_inflight=4) as srv:
+        ids, shapes, results = [], {}, {}
+        for r in reqs:
+            rid = srv.submit(r.grid, r.dyn, r.cylinders, r.horizon)
+            ids.append(rid)
+            shapes[rid] = tuple(r.grid["n"])
+        drain(srv, ids, results, shapes)
+    for rid, r in zip(ids, reqs):
+        V0 = oracle.target_cylinders(r.grid, *r.cylinders)
+        ref, _ = oracle.solve(r.grid, r.dyn, W.scheme("eno2", "rk2"), V0, r.horizon)
+        assert_f64_close(results[rid], ref)
+
+
+def test_served_mix_of_large_and_small_equals_alone():
+    """A grid above the size that steps alone (64x64x24x48, 4.7M nodes)
+    served together with small batched ones, requests ending inside ticks:
+    every result equals its solve alone."""
+    from paper_2012_04011_amd import hj
+
+    big = W.car_grid(64, 64, 24, 48)
+    reqs = small_requests(5)
+    reqs.insert(1, W.Request(0.0, 2, big, W.car_dynamics(), W.cylinders(77, 4), 0.25))
+    reqs.append(W.Request(0.0, 2, big, W.car_dynamics(), W.cylinders(78, 2), 0.15))
+    ref = [alone(hj, r)[0] for r in reqs]
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=8, steps_per_tick=3) as srv:
+        ids, shapes, results = [], {}, {}
+        for r in reqs:
+            rid = srv.submit(r.grid, r.dyn, r.cylinders, r.horizon)
+            ids.append(rid)
+            shapes[rid] = tuple(r.grid["n"])
+            srv.tick()
+        drain(srv, ids, results, shapes)
+    for rid, r in zip(ids, ref):
+        assert np.array_equal(results[rid], r), rid
