@@ -12,6 +12,8 @@ Problem descriptions are plain dicts (see ``paper_2012_04011_amd.workloads``):
     dyn    = {"kind": "car4d", "a_max": 1.5, "w_max": 1.0, "d_max": (0.0, 0.0)}
              {"kind": "drift_input", "drift": (..4..), "in_speed": s,
               "in_axes": (0, 1), "in_norm": "box"|"ball", "in_role": "max"|"min"}
+             {"kind": "car4d_steer", "a_max": 1.5, "steer_max": pi/18, "wheelbase": 0.3,
+              "d_max": (0.0, 0.0)}
     scheme = {"deriv": "upwind1"|"eno2", "integrator": "euler"|"rk2",
               "clamp": True, "cfl": 0.8}
 
@@ -64,6 +66,8 @@ class _Dyn(ctypes.Structure):
         ("in_axes_mask", ctypes.c_uint32),
         ("in_norm", ctypes.c_int32),
         ("in_role", ctypes.c_int32),
+        ("steer_max", ctypes.c_double),
+        ("wheelbase", ctypes.c_double),
     ]
 
 
@@ -105,6 +109,11 @@ def _load():
         lib.hjo_step.argtypes = [g, dy, sc, dp, dp, ctypes.c_double, dp]
         lib.hjo_solve.argtypes = [g, dy, sc, dp, ctypes.c_double, dp, P(ctypes.c_int64), dp, dp]
         lib.hjo_solve.restype = ctypes.c_int
+        lib.hjo_solve_converge.argtypes = [g, dy, sc, dp, ctypes.c_double, ctypes.c_int64, dp, P(ctypes.c_int64),
+                                           P(ctypes.c_int32), dp, dp]
+        lib.hjo_solve_converge.restype = ctypes.c_int
+        lib.hjo_optimal_control.argtypes = [g, dy, dp, dp, ctypes.c_int64, dp, dp, dp]
+        lib.hjo_optimal_control.restype = ctypes.c_int
         lib.hjo_threads.restype = ctypes.c_int32
         lib.hjo_set_threads.argtypes = [ctypes.c_int32]
         _lib = lib
@@ -113,7 +122,7 @@ def _load():
 
 # ----------------------------------------------------------- marshalling ---
 
-_KIND = {"car4d": 0, "drift_input": 1}
+_KIND = {"car4d": 0, "drift_input": 1, "car4d_steer": 2}
 _DERIV = {"upwind1": 0, "eno2": 1}
 _INTEG = {"euler": 0, "rk2": 1}
 _NORM = {"box": 0, "ball": 1}
@@ -147,6 +156,8 @@ def _dyn(dyn) -> _Dyn:
     s.in_axes_mask = mask
     s.in_norm = _NORM[dyn.get("in_norm", "box")]
     s.in_role = _ROLE[dyn.get("in_role", "max")]
+    s.steer_max = float(dyn.get("steer_max", 0.0))
+    s.wheelbase = float(dyn.get("wheelbase", 1.0))
     return s
 
 
@@ -259,6 +270,40 @@ def solve(grid, dyn, scheme, V0, horizon: float):
     if rc != 0:
         raise MemoryError("oracle solve: out of memory")
     return V, {"steps": n.value, "dt": dt.value, "dt_last": last.value}
+
+
+def solve_converge(grid, dyn, scheme, V0, threshold: float, max_steps: int):
+    """Convergence-mode solve (steps of the CFL dt until the largest change of
+    a step falls below `threshold`, at most max_steps); returns (V, info)
+    with info = {steps, converged, eps_last, dt}."""
+    V0 = _f64(V0, _shape(grid))
+    V = np.empty_like(V0)
+    n = ctypes.c_int64()
+    conv = ctypes.c_int32()
+    eps = ctypes.c_double()
+    dt = ctypes.c_double()
+    rc = _load().hjo_solve_converge(ctypes.byref(_grid(grid)), ctypes.byref(_dyn(dyn)), ctypes.byref(_scheme(scheme)),
+                                    _dptr(V0), float(threshold), int(max_steps), _dptr(V), ctypes.byref(n),
+                                    ctypes.byref(conv), ctypes.byref(eps), ctypes.byref(dt))
+    if rc != 0:
+        raise MemoryError("oracle converge: out of memory")
+    return V, {"steps": n.value, "converged": bool(conv.value), "eps_last": eps.value, "dt": dt.value}
+
+
+def optimal_control(grid, dyn, V, states):
+    """Eq (9) at each state (rows of `states`, shape (m, 4)): returns
+    (controls (m, 2), values (m,), gradients (m, 4))."""
+    V = _f64(V, _shape(grid))
+    z = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(-1, 4))
+    m = z.shape[0]
+    u = np.empty((m, 2))
+    val = np.empty(m)
+    gr = np.empty((m, 4))
+    rc = _load().hjo_optimal_control(ctypes.byref(_grid(grid)), ctypes.byref(_dyn(dyn)), _dptr(V), _dptr(z), m,
+                                     _dptr(u), _dptr(val), _dptr(gr))
+    if rc != 0:
+        raise ValueError("optimal control is defined for the car dynamics only")
+    return u, val, gr
 
 
 def threads() -> int:

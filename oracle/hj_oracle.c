@@ -41,7 +41,7 @@
 #include <omp.h>
 #endif
 
-enum { HJO_CAR4D = 0, HJO_DRIFT_INPUT = 1 };
+enum { HJO_CAR4D = 0, HJO_DRIFT_INPUT = 1, HJO_CAR4D_STEER = 2 };
 enum { HJO_UPWIND1 = 0, HJO_ENO2 = 1 };
 enum { HJO_EULER = 0, HJO_TVD_RK2 = 1 };
 enum { HJO_BOX = 0, HJO_BALL = 1 };
@@ -62,6 +62,10 @@ typedef struct {
  *               z' = drift + u, u nonzero only on the axes in in_axes_mask,
  *               bounded by in_speed in the box (per-axis) or Euclidean-ball
  *               norm; the input either maximises or minimises.
+ *   HJO_CAR4D_STEER (the experiment's car, eq (6)): as HJO_CAR4D but
+ *               theta' = v tan(delta) / L with the steering angle
+ *               |delta| <= steer_max (< pi/2) and wheelbase L; control
+ *               (a, delta) maximises.
  */
 typedef struct {
   int32_t kind;
@@ -69,6 +73,7 @@ typedef struct {
   double drift[4], in_speed;
   uint32_t in_axes_mask;
   int32_t in_norm, in_role;
+  double steer_max, wheelbase;
 } hjo_dyn;
 
 typedef struct {
@@ -150,11 +155,13 @@ static void car_f(double v, double theta, const double u[2], const double dist[2
  * for both the box and the ball).
  */
 static void alpha_at(const hjo_dyn *dy, const double z[4], double alpha[4]) {
-  if (dy->kind == HJO_CAR4D) {
+  if (dy->kind == HJO_CAR4D || dy->kind == HJO_CAR4D_STEER) {
     alpha[0] = fabs(z[2] * cos(z[3])) + dy->d_max[0];
     alpha[1] = fabs(z[2] * sin(z[3])) + dy->d_max[1];
     alpha[2] = dy->a_max;
-    alpha[3] = dy->w_max;
+    /* tan is increasing on (-pi/2, pi/2): |v tan(delta) / L| peaks at the
+     * largest steering angle */
+    alpha[3] = dy->kind == HJO_CAR4D ? dy->w_max : fabs(z[2]) * tan(dy->steer_max) / dy->wheelbase;
   } else {
     for (int d = 0; d < 4; ++d) {
       alpha[d] = fabs(dy->drift[d]);
@@ -176,6 +183,16 @@ static double hamiltonian(const hjo_dyn *dy, const double z[4], const double p[4
     double u[2], dist[2];
     u[0] = p[2] >= 0.0 ? dy->a_max : -dy->a_max;
     u[1] = p[3] >= 0.0 ? dy->w_max : -dy->w_max;
+    dist[0] = p[0] >= 0.0 ? -dy->d_max[0] : dy->d_max[0];
+    dist[1] = p[1] >= 0.0 ? -dy->d_max[1] : dy->d_max[1];
+    car_f(z[2], z[3], u, dist, f);
+  } else if (dy->kind == HJO_CAR4D_STEER) {
+    /* p_theta v tan(delta) / L is largest at delta = +-steer_max with the
+     * sign of p_theta v (ties take +; the term is then zero) */
+    double u[2], dist[2];
+    u[0] = p[2] >= 0.0 ? dy->a_max : -dy->a_max;
+    double delta = p[3] * z[2] >= 0.0 ? dy->steer_max : -dy->steer_max;
+    u[1] = z[2] * tan(delta) / dy->wheelbase;
     dist[0] = p[0] >= 0.0 ? -dy->d_max[0] : dy->d_max[0];
     dist[1] = p[1] >= 0.0 ? -dy->d_max[1] : dy->d_max[1];
     car_f(z[2], z[3], u, dist, f);
@@ -399,6 +416,141 @@ int hjo_solve(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const 
   if (n_steps) *n_steps = n;
   if (dt_out) *dt_out = dt;
   if (dt_last_out) *dt_last_out = dt_last;
+  return 0;
+}
+
+/*
+ * Convergence-mode solve (Algorithms 1 and 2, last lines): V := V0, then
+ * full steps of the CFL step dt while the change of the last step,
+ * eps = max over nodes of |V_{t+1} - V_t|, is at or above `threshold`
+ * (the printed test is inverted; the loop continues until the change falls
+ * below the threshold), at most max_steps steps.  Returns 0, or -1 if memory
+ * runs out; *n_steps = steps taken, *converged = 1 if eps < threshold
+ * stopped it, *eps_last = eps of the last step.
+ */
+int hjo_solve_converge(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0,
+                       double threshold, int64_t max_steps, double *V, int64_t *n_steps, int32_t *converged,
+                       double *eps_last, double *dt_out) {
+  int64_t np = hjo_num_points(g);
+  double dt = hjo_cfl_dt(g, dy, sc->cfl, 1.0);
+  double *work = (double *)malloc((size_t)np * 3 * sizeof(double));
+  if (!work) return -1;
+  double *prev = work + 2 * np;
+  memcpy(V, V0, (size_t)np * sizeof(double));
+  int64_t n = 0;
+  int32_t conv = 0;
+  double eps = 0.0;
+  while (n < max_steps) {
+    memcpy(prev, V, (size_t)np * sizeof(double));
+    hjo_step(g, dy, sc, V0, V, dt, work);
+    n += 1;
+    eps = 0.0;
+    for (int64_t i = 0; i < np; ++i) {
+      double e = fabs(V[i] - prev[i]);
+      if (e > eps || e != e) eps = e;
+    }
+    if (eps < threshold) {
+      conv = 1;
+      break;
+    }
+  }
+  free(work);
+  *n_steps = n;
+  *converged = conv;
+  *eps_last = eps;
+  if (dt_out) *dt_out = dt;
+  return 0;
+}
+
+/* ----------------------------------------------------- optimal control --- */
+
+/* Gradient component d of V at a node: central difference inside, wrapped
+ * on a periodic axis, one-sided at the ends of an open axis. */
+static double node_grad(const hjo_grid *g, const double *V, const int64_t st[4], const int idx[4], int d) {
+  int n = g->n[d], i = idx[d];
+  double h = hjo_spacing(g, d);
+  int64_t p = 0;
+  for (int e = 0; e < 4; ++e) p += (int64_t)idx[e] * st[e];
+  int64_t base = p - (int64_t)i * st[d];
+  if (is_periodic(g, d)) {
+    int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
+    return (V[base + ip * st[d]] - V[base + im * st[d]]) / (2.0 * h);
+  }
+  if (i == 0) return (V[base + st[d]] - V[base]) / h;
+  if (i == n - 1) return (V[base + (n - 1) * st[d]] - V[base + (n - 2) * st[d]]) / h;
+  return (V[base + (i + 1) * st[d]] - V[base + (i - 1) * st[d]]) / (2.0 * h);
+}
+
+/*
+ * Optimal control at arbitrary states (eq (9)): u = argmax_u grad V . f.
+ * grad V and V at the state are multilinear interpolations over the 16
+ * corners of the state's grid cell (of the nodal gradients above and of the
+ * nodal values).  Cell: on an open axis the state is clamped to [lo, hi]
+ * and i0 = min(floor((s - lo) / h), n - 2), weight (s - lo) / h - i0; on a
+ * periodic axis t = (s - lo) / h reduced modulo n, i0 = floor(t),
+ * i1 = (i0 + 1) mod n, weight t - i0.  Corners are visited with the theta
+ * bit fastest; the weight of a corner is the product over x, y, v, theta (in
+ * that order) of w_d or 1 - w_d.  Controls: a = +-a_max by the sign of p_v;
+ * the car's w = +-w_max by the sign of p_theta, the steering car's
+ * delta = +-steer_max by the sign of p_theta v (ties take +).  controls:
+ * 2 per state; values: 1 per state; grads: 4 per state (may be NULL).
+ * Returns -1 for dynamics without a control (the drift+input test model).
+ */
+int hjo_optimal_control(const hjo_grid *g, const hjo_dyn *dy, const double *V, const double *states, int64_t m,
+                        double *controls, double *values, double *grads) {
+  if (dy->kind != HJO_CAR4D && dy->kind != HJO_CAR4D_STEER) return -1;
+  int64_t st[4];
+  strides_of(g, st);
+  for (int64_t q = 0; q < m; ++q) {
+    const double *z = states + 4 * q;
+    int i0[4], i1[4];
+    double w[4];
+    for (int d = 0; d < 4; ++d) {
+      int n = g->n[d];
+      double h = hjo_spacing(g, d);
+      if (is_periodic(g, d)) {
+        double t = (z[d] - g->lo[d]) / h;
+        t = fmod(t, (double)n);
+        if (t < 0.0) t += (double)n;
+        int a = (int)floor(t);
+        if (a >= n) a = n - 1;
+        i0[d] = a;
+        i1[d] = a + 1 == n ? 0 : a + 1;
+        w[d] = t - (double)a;
+      } else {
+        double s = z[d] < g->lo[d] ? g->lo[d] : (z[d] > g->hi[d] ? g->hi[d] : z[d]);
+        double t = (s - g->lo[d]) / h;
+        int a = (int)floor(t);
+        if (a > n - 2) a = n - 2;
+        if (a < 0) a = 0;
+        i0[d] = a;
+        i1[d] = a + 1;
+        w[d] = t - (double)a;
+      }
+    }
+    double val = 0.0, p[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 16; ++c) {
+      int idx[4];
+      double wt = 1.0;
+      for (int d = 0; d < 4; ++d) {
+        int bitd = (c >> (3 - d)) & 1;
+        idx[d] = bitd ? i1[d] : i0[d];
+        wt = wt * (bitd ? w[d] : 1.0 - w[d]);
+      }
+      int64_t off = 0;
+      for (int d = 0; d < 4; ++d) off += (int64_t)idx[d] * st[d];
+      val = val + wt * V[off];
+      for (int d = 0; d < 4; ++d) p[d] = p[d] + wt * node_grad(g, V, st, idx, d);
+    }
+    controls[2 * q] = p[2] >= 0.0 ? dy->a_max : -dy->a_max;
+    if (dy->kind == HJO_CAR4D)
+      controls[2 * q + 1] = p[3] >= 0.0 ? dy->w_max : -dy->w_max;
+    else
+      controls[2 * q + 1] = p[3] * z[2] >= 0.0 ? dy->steer_max : -dy->steer_max;
+    if (values) values[q] = val;
+    if (grads)
+      for (int d = 0; d < 4; ++d) grads[4 * q + d] = p[d];
+  }
   return 0;
 }
 

@@ -39,6 +39,17 @@ def car_dynamics(a_max: float = 1.5, w_max: float = 1.0, d_max: float = 0.0) -> 
     return {"kind": "car4d", "a_max": a_max, "w_max": w_max, "d_max": (d_max, d_max)}
 
 
+def steer_dynamics(a_max: float = 1.5, steer_max: float = math.pi / 18, wheelbase: float = 0.3,
+                   d_max: float = 0.0) -> dict:
+    """The experiment's car (section "Experiment setup", eq (6)):
+    x' = v cos(theta) + d_x, y' = v sin(theta) + d_y, v' = a,
+    theta' = v tan(delta) / L; |a| <= a_max, |delta| <= steer_max (control,
+    maximises); the paper's values a in [-1.5, 1.5], delta in
+    [-pi/18, pi/18], L = 0.3 m."""
+    return {"kind": "car4d_steer", "a_max": a_max, "steer_max": steer_max, "wheelbase": wheelbase,
+            "d_max": (d_max, d_max)}
+
+
 def scheme(deriv: str, integrator: str, cfl: float = 0.8, clamp: bool = True) -> dict:
     return {"deriv": deriv, "integrator": integrator, "clamp": clamp, "cfl": cfl}
 

@@ -460,3 +460,182 @@ def test_target_is_signed_distance(oracle_lib):
     d1 = np.hypot(x - 0.5, y - 1.0) - 0.75
     d2 = np.hypot(x + 2.0, y - 0.0) - 0.4
     np.testing.assert_allclose(V0, np.broadcast_to(np.minimum(d1, d2), g["n"]), atol=1e-14)
+
+
+# ------------------------------------------------- steering car, eq (6) ---
+
+
+def _steer_f(z, A, D, DX, DY, L):
+    v, th = z[2], z[3]
+    return np.stack([v * np.cos(th) + DX, v * np.sin(th) + DY, A, v * np.tan(D) / L], axis=-1)
+
+
+def test_steer_hamiltonian_and_alpha_brute_force(oracle_lib):
+    """The steering car's H (max over (a, delta), min over the disturbance)
+    and alpha (max |f_d| over all inputs) by exhaustive search over grids of
+    the input boxes that include their vertices; v of both signs."""
+    rng = np.random.default_rng(21)
+    dyn = W.steer_dynamics(d_max=0.1)
+    dm, L = dyn["steer_max"], dyn["wheelbase"]
+    s = np.linspace(-1, 1, 11)
+    A, D, DX, DY = np.meshgrid(1.5 * s, dm * s, 0.1 * s, 0.1 * s, indexing="ij")
+    for _ in range(40):
+        z = np.array([rng.uniform(-5, 5), rng.uniform(-5, 5), rng.uniform(-2, 2), rng.uniform(-math.pi, math.pi)])
+        p = rng.normal(size=4)
+        if rng.random() < 0.2:
+            p[rng.integers(4)] = 0.0
+        f = _steer_f(z, A, D, DX, DY, L)
+        bf = (f @ p).min(axis=(2, 3)).max()
+        assert oracle_lib.hamiltonian(dyn, z, p) == pytest.approx(bf, abs=1e-12)
+        np.testing.assert_allclose(oracle_lib.alpha(dyn, z), np.abs(f).reshape(-1, 4).max(axis=0), atol=1e-13)
+
+
+def test_steer_is_car_with_speed_scaled_turn_rate(oracle_lib):
+    """At speed v the steering car turns at most |v| tan(delta_max) / L, so
+    its H and alpha equal the unicycle car's with that turn-rate bound."""
+    rng = np.random.default_rng(22)
+    st = W.steer_dynamics(d_max=0.05)
+    for _ in range(30):
+        z = np.array([0.3, -1.0, rng.uniform(0, 2), rng.uniform(-math.pi, math.pi)])
+        p = rng.normal(size=4)
+        car = W.car_dynamics(a_max=1.5, w_max=abs(z[2]) * math.tan(math.pi / 18) / 0.3, d_max=0.05)
+        assert oracle_lib.hamiltonian(st, z, p) == pytest.approx(oracle_lib.hamiltonian(car, z, p), rel=1e-14,
+                                                                  abs=1e-15)
+        np.testing.assert_allclose(oracle_lib.alpha(st, z), oracle_lib.alpha(car, z), rtol=1e-14)
+
+
+def test_steer_paper_turn_rate_bound(oracle_lib):
+    """The paper's steering limits (delta in [-pi/18, pi/18], L = 0.3 m) at
+    the grid's top speed of 2 m/s: the largest turn rate is
+    2 tan(10 deg) / 0.3 = 1.17551 rad/s, which bounds alpha_theta."""
+    a = oracle_lib.alpha(W.steer_dynamics(), np.array([0.0, 0.0, 2.0, 0.0]))
+    assert a[3] == pytest.approx(1.1755132047, abs=1e-9)
+
+
+def test_steer_mirror_symmetry(oracle_lib):
+    """The steering car is invariant under the mirror (x, y, theta) ->
+    (x, -y, -theta) too (delta -> -delta is admissible)."""
+    g = W.car_grid(18, 18, 6, 12)
+    dyn = W.steer_dynamics()
+    cx, cy, r = W.cylinders(9, 3)
+    V, _ = oracle_lib.solve(g, dyn, UP_EU, oracle_lib.target_cylinders(g, cx, cy, r), 0.5)
+    Vm, _ = oracle_lib.solve(g, dyn, UP_EU, oracle_lib.target_cylinders(g, cx, -cy, r), 0.5)
+    lidx = (-np.arange(12)) % 12
+    assert np.abs(Vm - V[:, ::-1, :, :][:, :, :, lidx]).max() < 1e-11
+
+
+# ------------------------------------------------------ convergence mode ---
+
+
+@pytest.mark.parametrize("dyn", [W.car_dynamics(), W.steer_dynamics()], ids=["car", "steer"])
+def test_converge_stops_at_first_small_change(oracle_lib, dyn):
+    """The loop stops after the first step whose largest change is below the
+    threshold: the result is that many plain steps, the change of the last
+    step (recomputed here) is below it and the one before is not."""
+    g = W.car_grid(16, 15, 6, 12)
+    V0 = oracle_lib.target_cylinders(g, *W.cylinders(4, 3))
+    thr = 2e-3
+    V, info = oracle_lib.solve_converge(g, dyn, UP_EU, V0, thr, 500)
+    assert info["converged"] and 2 <= info["steps"] < 500
+    dt = oracle_lib.cfl_dt(g, dyn, 0.8, 1.0)
+    assert info["dt"] == dt
+    U, prev, eps = V0.copy(), None, []
+    for _ in range(info["steps"]):
+        prev = U
+        U = oracle_lib.step(g, dyn, UP_EU, V0, U, dt)
+        eps.append(np.abs(U - prev).max())
+    assert np.array_equal(U, V)
+    assert eps[-1] < thr <= eps[-2] and info["eps_last"] == eps[-1]
+
+
+def test_converge_zero_dynamics_and_cap(oracle_lib):
+    """Nothing moves: the first step changes nothing and stops the loop.  A
+    zero threshold is never met: the loop runs exactly max_steps."""
+    g = W.car_grid(10, 9, 5, 8)
+    V0 = oracle_lib.target_cylinders(g, *W.cylinders(2, 2))
+    V, info = oracle_lib.solve_converge(g, drift_dyn(), UP_EU, V0, 1e-12, 50)
+    assert info["steps"] == 1 and info["converged"] and info["eps_last"] == 0.0 and np.array_equal(V, V0)
+    V, info = oracle_lib.solve_converge(g, W.car_dynamics(), ENO_RK, V0, 0.0, 7)
+    assert info["steps"] == 7 and not info["converged"]
+    dt = oracle_lib.cfl_dt(g, W.car_dynamics(), 0.8, 1.0)
+    U = V0.copy()
+    for _ in range(7):
+        U = oracle_lib.step(g, W.car_dynamics(), ENO_RK, V0, U, dt)
+    assert np.array_equal(U, V)
+
+
+# -------------------------------------------- optimal control, eq (9) ---
+
+
+def _states(rng, m, g):
+    lo, hi = np.array(g["lo"]), np.array(g["hi"])
+    return lo + (hi - lo) * rng.uniform(size=(m, 4))
+
+
+def test_control_on_linear_value(oracle_lib):
+    """V = 0.7 x - 0.3 y - 1.2 v (constant in theta): every difference
+    formula and the multilinear interpolation are exact, so the gradient is
+    (0.7, -0.3, -1.2, 0) and V is reproduced at any state; the acceleration
+    takes -a_max and the turn rate the tie value +w_max."""
+    g = W.car_grid(9, 8, 6, 10)
+    x, y, v = (oracle_lib.nodes(g, d) for d in range(3))
+    V = 0.7 * x[:, None, None, None] - 0.3 * y[None, :, None, None] - 1.2 * v[None, None, :, None] \
+        + np.zeros(g["n"])
+    z = _states(np.random.default_rng(5), 200, g)
+    u, val, gr = oracle_lib.optimal_control(g, W.car_dynamics(), V, z)
+    np.testing.assert_allclose(gr, np.tile([0.7, -0.3, -1.2, 0.0], (200, 1)), atol=1e-13)
+    np.testing.assert_allclose(val, 0.7 * z[:, 0] - 0.3 * z[:, 1] - 1.2 * z[:, 2], atol=1e-12)
+    assert (u[:, 0] == -1.5).all() and (u[:, 1] == 1.0).all()
+
+
+def test_control_turns_with_cos_theta(oracle_lib):
+    """V = sin(theta) on the periodic axis: the nodal central difference is
+    cos(theta) sin(h)/h, so the turn control follows the sign of cos(theta)
+    away from its zeros, and the interpolated V is within h^2/8 of sin; a
+    state one period away gives the same answer."""
+    g = W.car_grid(5, 5, 4, 36)
+    th = oracle_lib.nodes(g, 3)
+    V = np.broadcast_to(np.sin(th), g["n"]).copy()
+    rng = np.random.default_rng(6)
+    z = _states(rng, 300, g)
+    u, val, gr = oracle_lib.optimal_control(g, W.car_dynamics(), V, z)
+    h = 2 * math.pi / 36
+    clear = np.abs(np.cos(z[:, 3])) > 0.2
+    assert (u[clear, 1] == np.where(np.cos(z[clear, 3]) > 0, 1.0, -1.0)).all()
+    assert np.abs(val - np.sin(z[:, 3])).max() <= h * h / 8 + 1e-12
+    z2 = z.copy()
+    z2[:, 3] += 2 * math.pi
+    u2, val2, _ = oracle_lib.optimal_control(g, W.car_dynamics(), V, z2)
+    assert np.array_equal(u, u2) and np.allclose(val, val2, atol=1e-12)
+
+
+@pytest.mark.parametrize("dyn", [W.car_dynamics(), W.steer_dynamics()], ids=["car", "steer"])
+def test_control_is_argmax_over_inputs(oracle_lib, dyn):
+    """With the interpolated gradient p the query returns, its control
+    maximises p . f(z, u) over a grid of the control box (vertices
+    included); for the steering car the turn follows the sign of p_theta v
+    (v of both signs on this grid)."""
+    g = W.car_grid(8, 7, 6, 9, v=(-1.0, 2.0))
+    V = np.random.default_rng(7).normal(size=g["n"])
+    z = _states(np.random.default_rng(8), 200, g)
+    u, _, p = oracle_lib.optimal_control(g, dyn, V, z)
+    s = np.linspace(-1, 1, 21)
+    for q in range(len(z)):
+        v, th = z[q, 2], z[q, 3]
+        if dyn["kind"] == "car4d":
+            A, Wr = np.meshgrid(1.5 * s, 1.0 * s, indexing="ij")
+            turn = Wr
+            chosen_turn = u[q, 1]
+        else:
+            A, Dl = np.meshgrid(1.5 * s, dyn["steer_max"] * s, indexing="ij")
+            turn = v * np.tan(Dl) / dyn["wheelbase"]
+            chosen_turn = v * math.tan(u[q, 1]) / dyn["wheelbase"]
+        best = (p[q, 2] * A + p[q, 3] * turn).max()
+        got = p[q, 2] * u[q, 0] + p[q, 3] * chosen_turn
+        assert got == pytest.approx(best, abs=1e-12)
+
+
+def test_control_undefined_for_test_dynamics(oracle_lib):
+    g = W.car_grid(5, 5, 4, 8)
+    with pytest.raises(ValueError):
+        oracle_lib.optimal_control(g, drift_dyn(), np.zeros(g["n"]), np.zeros((1, 4)))
