@@ -52,7 +52,7 @@ typedef enum {
 /* enum values used in the descriptors */
 enum { HJ_F32 = 0, HJ_F64 = 1 };                      /* dtype / precision */
 enum { HJ_HOST = 0, HJ_DEVICE = 1 };                  /* where an array lives */
-enum { HJ_DYN_CAR4D = 0, HJ_DYN_DRIFT_INPUT = 1 };    /* dynamics kind */
+enum { HJ_DYN_CAR4D = 0, HJ_DYN_DRIFT_INPUT = 1, HJ_DYN_CAR4D_STEER = 2 }; /* dynamics kind */
 enum { HJ_UPWIND1 = 0, HJ_ENO2 = 1 };                 /* derivative scheme */
 enum { HJ_EULER = 0, HJ_TVD_RK2 = 1 };                /* integrator */
 enum { HJ_CLAMP_NONE = 0, HJ_CLAMP_MIN_V0 = 1 };      /* target clamp */
@@ -82,6 +82,10 @@ typedef struct {
  *   disturbance |d_x| <= d_max[0], |d_y| <= d_max[1] minimises it (eq (3),
  *   eq (4); the paper's car, eq (6), with the steering term replaced by a
  *   bounded turn rate).  Axis 2 must be v and axis 3 theta.
+ * HJ_DYN_CAR4D_STEER: the paper's car exactly (eq (6)): as HJ_DYN_CAR4D but
+ *   theta' = v tan(delta) / L with the steering angle |delta| <= steer_max
+ *   (radians, < pi/2) and wheelbase L = wheelbase > 0 (the experiment:
+ *   a_max 1.5, steer_max pi/18, L 0.3 m); w_max is unused.
  * HJ_DYN_DRIFT_INPUT (closed-form checks): z' = drift + u, u nonzero only on
  *   the axes in in_axes_mask, |u| <= in_speed in the box (per axis) or
  *   Euclidean-ball norm (in_norm); the input maximises or minimises
@@ -94,6 +98,7 @@ typedef struct {
   double drift[4], in_speed;
   uint32_t in_axes_mask;
   int32_t in_norm, in_role;
+  double steer_max, wheelbase;
 } hj_dynamics_desc;
 
 /*
@@ -199,6 +204,38 @@ hj_status hj_set_profiling(hj_grid *g, int32_t enable);
 
 /* Read the step-loop timing (synchronises the stream). */
 hj_status hj_get_profile(hj_grid *g, hj_profile *out);
+
+/* Convergence mode (Algorithms 1 and 2: "compute the HJ PDE until it
+ * converges").  V := V0, then steps of the CFL step while the largest change
+ * of a step, eps = max over nodes |V_{t+1} - V_t|, is at or above threshold
+ * (the printed test is inverted; read as: stop once eps < threshold), at
+ * most max_steps steps (>= 1).  The stop test runs on the device after every
+ * step; the host looks at it every 32 steps, and steps enqueued past the
+ * stop do nothing.  Synchronises.  A grid on which nothing moves takes
+ * steps of one time unit. */
+typedef struct {
+  int64_t steps;     /* steps taken */
+  int32_t converged; /* 1: eps < threshold stopped it, 0: max_steps did */
+  int32_t reserved;
+  double dt;         /* the step */
+  double eps_last;   /* eps of the last step taken */
+} hj_converge_info;
+
+hj_status hj_solve_converge(hj_grid *g, double threshold, int64_t max_steps, hj_converge_info *info);
+
+/* Optimal control at m arbitrary states (eq (9), applied by the paper's
+ * safety controller when eq (8) V < 0.15 holds): grad V and V at each state
+ * from multilinear interpolation over its grid cell of the nodal
+ * central-difference gradient (one-sided at the ends of open axes, wrapped
+ * on theta) and of V; states outside an open axis are clamped to it.
+ * states: m x 4 (x, y, v, theta) FP64; controls: m x 2, (a, w) for
+ * HJ_DYN_CAR4D or (a, delta) for HJ_DYN_CAR4D_STEER, bang-bang with ties
+ * (zero gradient) to the + bound; values: m (may be NULL).  All three on the
+ * host (synchronises) or all on the device (stream-ordered), per `where`.
+ * Computed in FP64 from the current V.  HJ_ERR_UNSUPPORTED for the test
+ * dynamics. */
+hj_status hj_optimal_control(hj_grid *g, const double *states, int64_t m, int32_t where, double *controls,
+                             double *values);
 
 /* How the time step runs on this handle.  kernel: 2 = LDS plane kernel, 1 =
  * streaming kernel, 0 = one-thread-per-node kernel (chosen by grid shape,

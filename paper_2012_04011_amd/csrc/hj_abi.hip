@@ -41,6 +41,9 @@ hj_status fail(hj_status st, const char *fmt, ...) {
 
 bool bit(uint32_t mask, int d) { return ((mask >> d) & 1u) != 0; }
 
+// Steps the convergence mode enqueues between two looks at the stop flag.
+constexpr int kConvergeChunk = 32;
+
 }  // namespace
 
 struct hj_grid {
@@ -59,6 +62,7 @@ struct hj_grid {
   void *w2 = nullptr;   // next value (swapped with v after a step)
   void *lut = nullptr;  // bx | by | ax | ay in the scheme's precision
   void *coef = nullptr;  // kp_x | km_x | kp_y | km_y (streaming kernel)
+  void *th = nullptr;    // per v: alpha_th | sig_th | kp_th | km_th | sg_th (theta axis)
   // stage kernel: 2 = plane (LDS), 1 = streaming, 0 = generic
   int kernel = 0;
   int x_chunks = 1;
@@ -77,6 +81,18 @@ struct hj_grid {
   double bv = 0, bth = 0, av = 0, ath = 0, sig[4] = {0, 0, 0, 0}, sig_ball = 0;
   uint32_t ball_mask = 0;
   double h[4];
+  std::vector<double> th_a, th_s;  // per v: alpha and input bound of the theta axis
+
+  // convergence mode: the stop flag the stage kernels test (null otherwise)
+  const int32_t *skip = nullptr;
+  unsigned long long *conv_acc = nullptr;  // device: max |dV| of the step (bits)
+  int32_t *conv_state = nullptr;           // device: stopped, step count
+  double *conv_eps = nullptr;              // device: eps of the last steps
+  int32_t *conv_host = nullptr;            // pinned: state
+  double *conv_eps_host = nullptr;         // pinned: eps log
+  // control queries: device copies of host states and results
+  double *ctl_dev = nullptr;
+  int64_t ctl_cap = 0;  // states
 
   bool has_target = false;
   bool dt_cached = false;
@@ -116,8 +132,12 @@ hj_status validate(const hj_grid_desc *g, const hj_dynamics_desc *dy, const hj_s
     if (np > INT32_MAX) return fail(HJ_ERR_INVALID_ARG, "grid has more than 2^31-1 nodes");
   }
   if (g->periodic_mask & ~0xFu) return fail(HJ_ERR_INVALID_ARG, "periodic_mask has bits above axis 3");
-  if (dy->kind != HJ_DYN_CAR4D && dy->kind != HJ_DYN_DRIFT_INPUT)
+  if (dy->kind != HJ_DYN_CAR4D && dy->kind != HJ_DYN_DRIFT_INPUT && dy->kind != HJ_DYN_CAR4D_STEER)
     return fail(HJ_ERR_INVALID_ARG, "unknown dynamics kind %d", dy->kind);
+  if (dy->kind == HJ_DYN_CAR4D_STEER &&
+      (!isfinite(dy->steer_max) || dy->steer_max < 0 || dy->steer_max >= 1.5707963267948966 ||
+       !isfinite(dy->wheelbase) || !(dy->wheelbase > 0)))
+    return fail(HJ_ERR_INVALID_ARG, "steering car: need 0 <= steer_max < pi/2 and wheelbase > 0");
   double vals[] = {dy->a_max, dy->w_max, dy->d_max[0], dy->d_max[1], dy->in_speed};
   for (double x : vals)
     if (!isfinite(x) || x < 0) return fail(HJ_ERR_INVALID_ARG, "input bounds must be finite and >= 0");
@@ -154,7 +174,9 @@ void build_table(hj_grid *G, std::vector<double> &tab) {
   int64_t m = (int64_t)n2 * n3;
   tab.assign(4 * m, 0.0);
   for (int d = 0; d < 4; ++d) G->h[d] = spacing(g, d);
-  if (dy.kind == HJ_DYN_CAR4D) {
+  G->th_a.assign(n2, 0.0);
+  G->th_s.assign(n2, 0.0);
+  if (dy.kind == HJ_DYN_CAR4D || dy.kind == HJ_DYN_CAR4D_STEER) {
     for (int k = 0; k < n2; ++k) {
       double v = node(g, 2, k);
       for (int l = 0; l < n3; ++l) {
@@ -170,11 +192,16 @@ void build_table(hj_grid *G, std::vector<double> &tab) {
     G->bv = 0;
     G->bth = 0;
     G->av = dy.a_max;
-    G->ath = dy.w_max;
     G->sig[0] = -dy.d_max[0];
     G->sig[1] = -dy.d_max[1];
     G->sig[2] = dy.a_max;
-    G->sig[3] = dy.w_max;
+    // theta' = w (|w| <= w_max), or v tan(delta) / L for the steering car:
+    // a maximising input bounded by |v| tan(steer_max) / L at speed v
+    for (int k = 0; k < n2; ++k) {
+      double b = dy.kind == HJ_DYN_CAR4D ? dy.w_max : fabs(node(g, 2, k)) * tan(dy.steer_max) / dy.wheelbase;
+      G->th_a[k] = b;
+      G->th_s[k] = b;
+    }
     G->sig_ball = 0;
     G->ball_mask = 0;
   } else {
@@ -191,11 +218,32 @@ void build_table(hj_grid *G, std::vector<double> &tab) {
     G->bv = dy.drift[2];
     G->bth = dy.drift[3];
     G->av = alpha[2];
-    G->ath = alpha[3];
     for (int d = 0; d < 4; ++d)
       G->sig[d] = (dy.in_norm == HJ_NORM_BOX && bit(dy.in_axes_mask, d)) ? sgn * s : 0.0;
+    for (int k = 0; k < n2; ++k) {
+      G->th_a[k] = alpha[3];
+      G->th_s[k] = G->sig[3];
+    }
     G->sig_ball = dy.in_norm == HJ_NORM_BALL ? sgn * s : 0.0;
     G->ball_mask = dy.in_norm == HJ_NORM_BALL ? dy.in_axes_mask : 0u;
+  }
+  G->sig[3] = 0.0;  // the theta axis uses th_s (per v)
+  G->ath = 0.0;     // alpha_theta^max over the grid's v nodes (CFL)
+  for (int k = 0; k < n2; ++k)
+    if (G->th_a[k] > G->ath) G->ath = G->th_a[k];
+}
+
+// Theta-axis table per v in FP64: alpha | sig | kp = (b + alpha) / (2h) |
+// km = (b - alpha) / (2h) | sg = sig / (2h).
+void build_theta(const hj_grid *G, std::vector<double> &th) {
+  int n2 = G->g.n[2];
+  th.assign(5 * (size_t)n2, 0.0);
+  for (int k = 0; k < n2; ++k) {
+    th[k] = G->th_a[k];
+    th[n2 + k] = G->th_s[k];
+    th[2 * n2 + k] = (G->bth + G->th_a[k]) / (2.0 * G->h[3]);
+    th[3 * n2 + k] = (G->bth - G->th_a[k]) / (2.0 * G->h[3]);
+    th[4 * n2 + k] = G->th_s[k] / (2.0 * G->h[3]);
   }
 }
 
@@ -244,9 +292,13 @@ T *buf(void *p) {
 }
 
 void free_all(hj_grid *G) {
-  void *ptrs[] = {G->v0, G->v, G->w1, G->w2, G->lut, G->coef, G->v0xy, G->lut64, G->amax_dev, G->flag_dev};
+  void *ptrs[] = {G->v0,       G->v,           G->w1,       G->w2,       G->lut,      G->coef,
+                  G->th,       G->v0xy,        G->lut64,    G->amax_dev, G->flag_dev, G->conv_acc,
+                  G->conv_state, G->conv_eps, G->ctl_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  if (G->conv_host) (void)hipHostFree(G->conv_host);
+  if (G->conv_eps_host) (void)hipHostFree(G->conv_eps_host);
   if (G->amax_host) (void)hipHostFree(G->amax_host);
   if (G->flag_host) (void)hipHostFree(G->flag_host);
   for (hipEvent_t e : G->ev_pool) (void)hipEventDestroy(e);
@@ -441,6 +493,8 @@ hj::StageArgs<T> stage_args(hj_grid *G) {
     a.sig[d] = (T)G->sig[d];
   }
   a.lut = buf<const T>(G->lut);
+  a.th = buf<const T>(G->th);
+  a.skip = G->skip;
   a.bv = (T)G->bv;
   a.bth = (T)G->bth;
   a.av = (T)G->av;
@@ -473,8 +527,8 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   // uniform v and theta coefficients: b = bv / bth, alpha = av / ath
   a.kp_v = (T)((G->bv + G->av) / (2.0 * G->h[2]));
   a.km_v = (T)((G->bv - G->av) / (2.0 * G->h[2]));
-  a.kp_th = (T)((G->bth + G->ath) / (2.0 * G->h[3]));
-  a.km_th = (T)((G->bth - G->ath) / (2.0 * G->h[3]));
+  a.coef_th = buf<const T>(G->th) + 2 * g.n[2];
+  a.skip = G->skip;
   for (int d = 0; d < 4; ++d) {
     a.sg[d] = (T)(G->sig[d] / (2.0 * G->h[d]));
     a.half_inv_h[d] = (T)(1.0 / (2.0 * G->h[d]));
@@ -635,9 +689,10 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   G->stream = static_cast<hipStream_t>(hip_stream);
   G->npts = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * grid->n[3];
   G->elem = scheme->precision == HJ_F32 ? 4 : 8;
-  std::vector<double> tab, coef;
+  std::vector<double> tab, coef, th;
   build_table(G, tab);
   build_coef(G, tab, coef);
+  build_theta(G, th);
   int64_t m = (int64_t)grid->n[2] * grid->n[3];
   {
     int run = hj::run_length(G->elem, grid->n[3]);
@@ -669,6 +724,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   if (e == hipSuccess && rk2) e = hipMalloc(&G->w1, bytes);
   if (e == hipSuccess) e = hipMalloc(&G->lut, 4 * m * G->elem);
   if (e == hipSuccess) e = hipMalloc(&G->coef, 4 * m * G->elem);
+  if (e == hipSuccess) e = hipMalloc(&G->th, th.size() * G->elem);
   if (e == hipSuccess) e = hipMalloc(&G->v0xy, (size_t)grid->n[0] * grid->n[1] * G->elem);
   if (e == hipSuccess) e = hipMalloc(&G->lut64, 2 * m * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&G->amax_dev, 4 * sizeof(double));
@@ -682,15 +738,18 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
       if (G->elem == 8) {
         e = hipMemcpyAsync(G->lut, tab.data(), 4 * m * 8, hipMemcpyHostToDevice, G->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(G->coef, coef.data(), 4 * m * 8, hipMemcpyHostToDevice, G->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(G->th, th.data(), th.size() * 8, hipMemcpyHostToDevice, G->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
       } else {
-        std::vector<float> t32(4 * m), c32(4 * m);
+        std::vector<float> t32(4 * m), c32(4 * m), h32(th.size());
         for (int64_t i = 0; i < 4 * m; ++i) {
           t32[i] = (float)tab[i];
           c32[i] = (float)coef[i];
         }
+        for (size_t i = 0; i < th.size(); ++i) h32[i] = (float)th[i];
         e = hipMemcpyAsync(G->lut, t32.data(), 4 * m * 4, hipMemcpyHostToDevice, G->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(G->coef, c32.data(), 4 * m * 4, hipMemcpyHostToDevice, G->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(G->th, h32.data(), th.size() * 4, hipMemcpyHostToDevice, G->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
       }
     }
@@ -866,6 +925,157 @@ hj_status hj_step(hj_grid *G, double dt, double *dt_taken) {
   return HJ_OK;
 }
 
+hj_status hj_solve_converge(hj_grid *G, double threshold, int64_t max_steps, hj_converge_info *info) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (isnan(threshold) || threshold < 0) return fail(HJ_ERR_INVALID_ARG, "threshold must be >= 0");
+  if (max_steps < 1) return fail(HJ_ERR_INVALID_ARG, "max_steps must be >= 1");
+  if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if ((st = set_device(G)) != HJ_OK) return st;
+  if ((st = ensure_dt(G)) != HJ_OK) return st;
+  const int K = kConvergeChunk;
+  if (!G->conv_acc) {
+    HJ_HIP(hipMalloc((void **)&G->conv_acc, sizeof(unsigned long long)));
+    HJ_HIP(hipMalloc((void **)&G->conv_state, 2 * sizeof(int32_t)));
+    HJ_HIP(hipMalloc((void **)&G->conv_eps, K * sizeof(double)));
+    HJ_HIP(hipHostMalloc((void **)&G->conv_host, 2 * sizeof(int32_t), 0));
+    HJ_HIP(hipHostMalloc((void **)&G->conv_eps_host, K * sizeof(double), 0));
+  }
+  // a grid on which nothing moves takes steps of one time unit
+  const double dt = isinf(G->dt_cfl) ? 1.0 : G->dt_cfl;
+  if ((st = reset_value(G)) != HJ_OK) return st;
+  if (G->autotune_on && !G->autotuned && !G->launch_fixed)
+    if ((st = autotune(G)) != HJ_OK) return st;
+  HJ_HIP(hj::launch_converge_reset(G->conv_acc, G->conv_state, S(G)));
+  G->skip = G->conv_state;
+  int64_t k = 0, steps = max_steps;
+  bool stopped = false;
+  double eps_last = 0.0;
+  while (k < max_steps && st == HJ_OK) {
+    const int64_t chunk = max_steps - k < K ? max_steps - k : K;
+    int64_t launches = 0;
+    for (int64_t j = 0; j < chunk && st == HJ_OK; ++j) {
+      st = step_once(G, dt, &launches);  // reads v, writes w2, swaps: v new, w2 old
+      if (st != HJ_OK) break;
+      hipError_t e = G->elem == 4 ? hj::launch_delta_max<float>(buf<const float>(G->v), buf<const float>(G->w2),
+                                                                G->npts, G->conv_acc, G->skip, S(G))
+                                  : hj::launch_delta_max<double>(buf<const double>(G->v), buf<const double>(G->w2),
+                                                                 G->npts, G->conv_acc, G->skip, S(G));
+      if (e == hipSuccess) e = hj::launch_converge_check(G->conv_acc, threshold, G->conv_state, G->conv_eps, (int)j, k + j, S(G));
+      if (e != hipSuccess) st = fail(HJ_ERR_DEVICE, "hj_solve_converge: %s", hipGetErrorString(e));
+    }
+    if (st != HJ_OK) break;
+    hipError_t e = hipMemcpyAsync(G->conv_host, G->conv_state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, S(G));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(G->conv_eps_host, G->conv_eps, chunk * sizeof(double), hipMemcpyDeviceToHost, S(G));
+    if (e == hipSuccess) e = hipStreamSynchronize(S(G));
+    if (e != hipSuccess) {
+      st = fail(HJ_ERR_DEVICE, "hj_solve_converge: %s", hipGetErrorString(e));
+      break;
+    }
+    if (G->conv_host[0]) {
+      steps = G->conv_host[1];
+      stopped = true;
+      eps_last = G->conv_eps_host[steps - 1 - k];
+      // the steps after the stop did nothing, but v and w2 were swapped for
+      // each of them
+      if (((k + chunk - steps) & 1) != 0) {
+        void *t = G->v;
+        G->v = G->w2;
+        G->w2 = t;
+      }
+      break;
+    }
+    eps_last = G->conv_eps_host[chunk - 1];
+    k += chunk;
+  }
+  G->skip = nullptr;
+  if (st != HJ_OK) return st;
+  if (info) {
+    info->steps = steps;
+    info->converged = stopped ? 1 : 0;
+    info->reserved = 0;
+    info->dt = dt;
+    info->eps_last = eps_last;
+  }
+  return HJ_OK;
+}
+
+hj_status hj_optimal_control(hj_grid *G, const double *states, int64_t m, int32_t where, double *controls,
+                             double *values) {
+  hj_status st = check_handle(G);
+  if (st != HJ_OK) return st;
+  if (m < 0 || (m > 0 && (!states || !controls))) return fail(HJ_ERR_INVALID_ARG, "null states or controls");
+  if (where != HJ_HOST && where != HJ_DEVICE) return fail(HJ_ERR_INVALID_ARG, "unknown location %d", where);
+  if (G->dyn.kind != HJ_DYN_CAR4D && G->dyn.kind != HJ_DYN_CAR4D_STEER)
+    return fail(HJ_ERR_UNSUPPORTED, "the optimal control is defined for the car dynamics");
+  if (m == 0) return HJ_OK;
+  if ((st = set_device(G)) != HJ_OK) return st;
+  const double *z = states;
+  double *u = controls, *val = values;
+  if (where == HJ_HOST) {
+    for (int64_t i = 0; i < 4 * m; ++i)
+      if (!isfinite(states[i])) return fail(HJ_ERR_INVALID_ARG, "state %lld is not finite", (long long)(i / 4));
+    if (m > G->ctl_cap) {
+      if (G->ctl_dev) HJ_HIP(hipFree(G->ctl_dev));
+      G->ctl_dev = nullptr;
+      G->ctl_cap = 0;
+      HJ_HIP(hipMalloc((void **)&G->ctl_dev, (size_t)m * 7 * sizeof(double)));
+      G->ctl_cap = m;
+    }
+    double *zd = G->ctl_dev;
+    HJ_HIP(hipMemcpyAsync(zd, states, m * 4 * sizeof(double), hipMemcpyHostToDevice, S(G)));
+    z = zd;
+    u = zd + 4 * m;
+    val = values ? zd + 6 * m : nullptr;
+  }
+  if (G->elem == 4) {
+    hj::ControlArgs<float> a;
+    memset(&a, 0, sizeof a);
+    a.v = buf<const float>(G->v);
+    for (int d = 0; d < 4; ++d) {
+      a.n[d] = G->g.n[d];
+      a.lo[d] = G->g.lo[d];
+      a.hi[d] = G->g.hi[d];
+      a.h[d] = G->h[d];
+    }
+    a.periodic_mask = G->g.periodic_mask;
+    a.states = z;
+    a.m = m;
+    a.controls = u;
+    a.values = val;
+    a.steer = G->dyn.kind == HJ_DYN_CAR4D_STEER;
+    a.a_max = G->dyn.a_max;
+    a.turn_max = a.steer ? G->dyn.steer_max : G->dyn.w_max;
+    HJ_HIP(hj::launch_control(a, S(G)));
+  } else {
+    hj::ControlArgs<double> a;
+    memset(&a, 0, sizeof a);
+    a.v = buf<const double>(G->v);
+    for (int d = 0; d < 4; ++d) {
+      a.n[d] = G->g.n[d];
+      a.lo[d] = G->g.lo[d];
+      a.hi[d] = G->g.hi[d];
+      a.h[d] = G->h[d];
+    }
+    a.periodic_mask = G->g.periodic_mask;
+    a.states = z;
+    a.m = m;
+    a.controls = u;
+    a.values = val;
+    a.steer = G->dyn.kind == HJ_DYN_CAR4D_STEER;
+    a.a_max = G->dyn.a_max;
+    a.turn_max = a.steer ? G->dyn.steer_max : G->dyn.w_max;
+    HJ_HIP(hj::launch_control(a, S(G)));
+  }
+  if (where == HJ_HOST) {
+    HJ_HIP(hipMemcpyAsync(controls, u, m * 2 * sizeof(double), hipMemcpyDeviceToHost, S(G)));
+    if (values) HJ_HIP(hipMemcpyAsync(values, val, m * sizeof(double), hipMemcpyDeviceToHost, S(G)));
+    HJ_HIP(hipStreamSynchronize(S(G)));
+  }
+  return HJ_OK;
+}
+
 hj_status hj_get_value(hj_grid *G, void *out, int32_t dtype, int32_t where) {
   hj_status st = check_handle(G);
   if (st == HJ_OK) st = check_array(out, dtype, where);
@@ -1027,6 +1237,7 @@ int batch_chunks(const hj_batch *b, const hj_grid *G) {
 template <typename T>
 hj::StreamArgs<T> batch_stream_args(hj_grid *G, int n_chunks) {
   hj::StreamArgs<T> a = stream_args<T>(G);
+  a.skip = nullptr;
   a.blocks_per_chunk = (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
   int nx = G->g.n[0];
   if (n_chunks > nx) n_chunks = nx;

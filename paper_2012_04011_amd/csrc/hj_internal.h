@@ -28,6 +28,7 @@ struct StageArgs {
   const T *v0;   // target, for the clamp (unused without clamp)
   T *out;
   const T *lut;  // bx | by | ax | ay, each n[2] * n[3] values
+  const T *th;   // alpha_theta | sig_theta, each n[2] values (theta axis per v)
   int32_t n[4];
   int64_t st[4];  // C-order strides of the external layout
   uint32_t periodic_mask;
@@ -40,6 +41,7 @@ struct StageArgs {
   int32_t mode;
   int32_t clamp;
   int64_t npts;
+  const int32_t *skip;  // when non-null and *skip != 0 the launch does nothing
 };
 
 // The streaming stage kernel (see hj_kernels.hip).  Each thread owns a run
@@ -49,7 +51,9 @@ struct StageArgs {
 // with unscaled one-sided differences p' = h p:
 //   kp = (b + alpha) / (2h), km = (b - alpha) / (2h), sg = sig / (2h).
 // kp, km of x and y vary with (v, theta) (table `coef`: kp_x | km_x | kp_y |
-// km_y, each n[2] * n[3]); those of v and theta are uniform.
+// km_y, each n[2] * n[3]); those of theta vary with v (the steering car
+// turns at most |v| tan(delta_max) / L; table `coef_th`), those of v are
+// uniform.
 template <typename T>
 struct StreamArgs {
   const T *vs;
@@ -68,7 +72,8 @@ struct StreamArgs {
   int32_t blocks_per_chunk;
   int32_t chunk_len;       // x planes per block
   int32_t n_chunks;
-  T kp_v, km_v, kp_th, km_th;
+  const T *coef_th;  // kp_theta | km_theta | sg_theta, each n[2] values (per v)
+  T kp_v, km_v;
   T sg[4];
   T half_inv_h[4];  // 1 / (2 h_d), for the ball term
   T sig_ball;
@@ -76,6 +81,7 @@ struct StreamArgs {
   T dt;
   int32_t mode;
   int32_t clamp;
+  const int32_t *skip;  // when non-null and *skip != 0 the launch does nothing
 };
 
 constexpr int kStreamBlock = 256;
@@ -166,6 +172,40 @@ int persistent_blocks_per_cu(int deriv, bool sg, bool ball);
 // queue->next = queue->error = 0, done[0..m) = 0 (a kernel, so that the
 // sequence can be captured in a graph).
 hipError_t launch_batch_reset(BatchQueue *queue, int m, hipStream_t s);
+
+// ---- convergence mode ----------------------------------------------------
+// acc = max over i < n of |a[i] - b[i]| as the bit pattern of a non-negative
+// double (NaN counts as +inf); nothing when *skip.
+template <typename T>
+hipError_t launch_delta_max(const T *a, const T *b, int64_t n, unsigned long long *acc, const int32_t *skip,
+                            hipStream_t s);
+
+// state[0] = stopped, state[1] = step count at the stop.  Unless stopped:
+// eps_log[slot] = eps = acc, acc = 0, and eps < threshold stops after step k.
+hipError_t launch_converge_check(unsigned long long *acc, double threshold, int32_t *state, double *eps_log, int slot,
+                                 int64_t k, hipStream_t s);
+
+// state[0] = state[1] = 0, acc = 0 (a kernel, graph-safe).
+hipError_t launch_converge_reset(unsigned long long *acc, int32_t *state, hipStream_t s);
+
+// ---- optimal control at arbitrary states (eq (9)) -------------------------
+template <typename T>
+struct ControlArgs {
+  const T *v;
+  int32_t n[4];
+  uint32_t periodic_mask;
+  double lo[4], hi[4], h[4];
+  const double *states;  // m x 4
+  int64_t m;
+  double *controls;  // m x 2
+  double *values;    // m, may be null
+  double *grads;     // m x 4, may be null
+  int32_t steer;     // 0: (a, w) car, 1: (a, delta) steering car
+  double a_max, turn_max;
+};
+
+template <typename T>
+hipError_t launch_control(const ControlArgs<T> &a, hipStream_t s);
 
 constexpr int kMaxCylindersPerLaunch = 32;
 

@@ -95,7 +95,7 @@ __device__ inline void one_sided(const T (&w)[5], T inv_h, T &pm, T &pp) {
 //   - a ball-bounded input contributes +-s |p_S|_2.
 // The dissipation adds alpha_d (p+ - p-) / 2 with alpha_d the bound on |f_d|.
 template <typename T, bool BALL>
-__device__ inline T lf_rhs(const T (&pm)[4], const T (&pp)[4], T bx, T by, T ax, T ay,
+__device__ inline T lf_rhs(const T (&pm)[4], const T (&pp)[4], T bx, T by, T ax, T ay, T ath, T sgt,
                            const StageArgs<T> &a) {
   T pb[4], hd[4];
 #pragma unroll
@@ -105,8 +105,8 @@ __device__ inline T lf_rhs(const T (&pm)[4], const T (&pp)[4], T bx, T by, T ax,
   }
   T L = bx * pb[0] + by * pb[1] + a.bv * pb[2] + a.bth * pb[3];
 #pragma unroll
-  for (int d = 0; d < 4; ++d) L += a.sig[d] * tabs(pb[d]);
-  L += ax * hd[0] + ay * hd[1] + a.av * hd[2] + a.ath * hd[3];
+  for (int d = 0; d < 4; ++d) L += (d == 3 ? sgt : a.sig[d]) * tabs(pb[d]);
+  L += ax * hd[0] + ay * hd[1] + a.av * hd[2] + ath * hd[3];
   if (BALL) {
     T s2 = T(0);
 #pragma unroll
@@ -132,6 +132,7 @@ __device__ inline T finish(const StageArgs<T> &a, int64_t p, T vs, T L) {
 // serve the reuse).  Works for every grid shape.
 template <typename T, int DERIV, bool BALL>
 __global__ __launch_bounds__(256) void stage_generic(StageArgs<T> a) {
+  if (a.skip && *a.skip) return;
   int64_t blk = xcd_logical_block(blockIdx.x, gridDim.x);
   int64_t p = blk * 256 + threadIdx.x;
   if (p >= a.npts) return;
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) void stage_generic(StageArgs<T> a) {
   int64_t c = (int64_t)idx[2] * a.n[3] + idx[3];
   int64_t m = (int64_t)a.n[2] * a.n[3];
   T bx = a.lut[c], by = a.lut[m + c], ax = a.lut[2 * m + c], ay = a.lut[3 * m + c];
-  T L = lf_rhs<T, BALL>(pm, pp, bx, by, ax, ay, a);
+  T L = lf_rhs<T, BALL>(pm, pp, bx, by, ax, ay, a.th[idx[2]], a.th[a.n[2] + idx[2]], a);
   a.out[p] = finish(a, p, v[p], L);
 }
 
@@ -445,6 +446,8 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
   }
   const bool vedge = !perv && (v < 2 || v >= nv - 2);
   const bool yedge = !pery && (y < 2 || y >= ny - 2);
+  // theta-axis coefficients of this thread's v (see StreamArgs::coef_th)
+  const T kpt = a.coef_th[v], kmt = a.coef_th[nv + v], sgt = a.coef_th[2 * nv + v];
   T kpx[R], kmx[R], kpy[R], kmy[R];
   {
     const int c = v * nth + th0, m = nv * nth;
@@ -586,7 +589,7 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
           pp = dnext;
         }
         dprev = dnext;
-        accumulate<T, true, BALL>(L[j], b2[j], a.kp_th, a.km_th, a.sg[3], pp, pm, ball_t, a.half_inv_h[3]);
+        accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
       }
     }
     // ---- v
@@ -630,6 +633,7 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
 
 template <typename T, int R, int DERIV, bool SG, bool BALL>
 __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
+  if (a.skip && *a.skip) return;
   stream_tile<T, R, DERIV, SG, BALL>(a, (int)xcd_logical_block(blockIdx.x, gridDim.x));
 }
 
@@ -660,6 +664,7 @@ __device__ inline void lds_pair(const T *p, T &a, T &b) {
 
 template <typename T, int R, int DERIV, bool SG, bool BALL>
 __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
+  if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   constexpr uint32_t E = sizeof(T);
@@ -692,6 +697,8 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   theta_halo_offsets<R>(v * nth, th0, nth, lh);
   const bool vedge = !perv && (v < 2 || v >= nv - 2);
   const bool yedge = !pery && (y < 2 || y >= ny - 2);
+  // theta-axis coefficients of this thread's v (see StreamArgs::coef_th)
+  const T kpt = a.coef_th[v], kmt = a.coef_th[nv + v], sgt = a.coef_th[2 * nv + v];
   T kpx[R], kmx[R], kpy[R], kmy[R];
   {
     const int m = nv * nth;
@@ -841,7 +848,7 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
           pp = dnext;
         }
         dprev = dnext;
-        accumulate<T, true, BALL>(L[j], b2[j], a.kp_th, a.km_th, a.sg[3], pp, pm, ball_t, a.half_inv_h[3]);
+        accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
       }
     }
     // ---- v: neighbours from LDS
@@ -1170,6 +1177,149 @@ __global__ void batch_reset_kernel(BatchQueue *q, int m) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Convergence mode: the largest change of a step, and the stop test.
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_max_d(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void delta_max_kernel(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
+                                                        unsigned long long *acc, const int32_t *skip) {
+  if (skip && *skip) return;
+  __shared__ double part[4];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double d = fabs((double)a[i] - (double)b[i]);
+    if (d != d) d = INFINITY;
+    m = d > m ? d : m;
+  }
+  m = wave_max_d(m);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = part[w] > m ? part[w] : m;
+    atomicMax(acc, (unsigned long long)__double_as_longlong(m));  // non-negative: bit order = value order
+  }
+}
+
+__global__ void converge_check_kernel(unsigned long long *acc, double threshold, int32_t *state, double *eps_log,
+                                      int slot, int64_t k) {
+  if (state[0]) return;
+  double eps = __longlong_as_double((long long)*acc);
+  eps_log[slot] = eps;
+  *acc = 0ull;
+  if (eps < threshold) {
+    state[0] = 1;
+    state[1] = (int32_t)(k + 1);
+  }
+}
+
+__global__ void converge_reset_kernel(unsigned long long *acc, int32_t *state) {
+  *acc = 0ull;
+  state[0] = 0;
+  state[1] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Optimal control at arbitrary states (eq (9)): grad V and V at the state by
+// multilinear interpolation over the 16 corners of its cell, of the nodal
+// central-difference gradient (one-sided at the ends of an open axis, wrapped
+// on a periodic one) and of V; then the bang-bang control.  FP64 whatever the
+// grid's precision; no fused multiply-add, in a fixed order (corners with the
+// theta bit fastest, weights multiplied x, y, v, theta), so that the result
+// is reproducible from the same V.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline double node_value(const ControlArgs<T> &a, const int (&idx)[4]) {
+  int64_t off = (((int64_t)idx[0] * a.n[1] + idx[1]) * a.n[2] + idx[2]) * a.n[3] + idx[3];
+  return (double)a.v[off];
+}
+
+template <typename T>
+__device__ inline double node_gradient(const ControlArgs<T> &a, const int (&idx)[4], int d) {
+#pragma clang fp contract(off)
+  const int n = a.n[d], i = idx[d];
+  int lo_i[4] = {idx[0], idx[1], idx[2], idx[3]}, hi_i[4] = {idx[0], idx[1], idx[2], idx[3]};
+  double den;
+  if ((a.periodic_mask >> d) & 1u) {
+    lo_i[d] = i == 0 ? n - 1 : i - 1;
+    hi_i[d] = i == n - 1 ? 0 : i + 1;
+    den = 2.0 * a.h[d];
+  } else if (i == 0) {
+    hi_i[d] = 1;
+    den = a.h[d];
+  } else if (i == n - 1) {
+    lo_i[d] = n - 2;
+    den = a.h[d];
+  } else {
+    lo_i[d] = i - 1;
+    hi_i[d] = i + 1;
+    den = 2.0 * a.h[d];
+  }
+  return (node_value(a, hi_i) - node_value(a, lo_i)) / den;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void control_kernel(ControlArgs<T> a) {
+#pragma clang fp contract(off)
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.m) return;
+  const double *z = a.states + 4 * q;
+  int i0[4], i1[4];
+  double w[4];
+  for (int d = 0; d < 4; ++d) {
+    const int n = a.n[d];
+    if ((a.periodic_mask >> d) & 1u) {
+      double t = (z[d] - a.lo[d]) / a.h[d];
+      t = fmod(t, (double)n);
+      if (t < 0.0) t += (double)n;
+      int c = (int)floor(t);
+      if (c >= n) c = n - 1;
+      i0[d] = c;
+      i1[d] = c + 1 == n ? 0 : c + 1;
+      w[d] = t - (double)c;
+    } else {
+      double s = z[d] < a.lo[d] ? a.lo[d] : (z[d] > a.hi[d] ? a.hi[d] : z[d]);
+      double t = (s - a.lo[d]) / a.h[d];
+      int c = (int)floor(t);
+      if (c > n - 2) c = n - 2;
+      if (c < 0) c = 0;
+      i0[d] = c;
+      i1[d] = c + 1;
+      w[d] = t - (double)c;
+    }
+  }
+  double val = 0.0, p[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < 16; ++c) {
+    int idx[4];
+    double wt = 1.0;
+    for (int d = 0; d < 4; ++d) {
+      const int bitd = (c >> (3 - d)) & 1;
+      idx[d] = bitd ? i1[d] : i0[d];
+      wt = wt * (bitd ? w[d] : 1.0 - w[d]);
+    }
+    val = val + wt * node_value(a, idx);
+    for (int d = 0; d < 4; ++d) p[d] = p[d] + wt * node_gradient(a, idx, d);
+  }
+  a.controls[2 * q] = p[2] >= 0.0 ? a.a_max : -a.a_max;
+  // the car turns at +-w_max by the sign of p_theta; the steering car steers
+  // +-steer_max by the sign of p_theta v
+  const double s3 = a.steer ? p[3] * z[2] : p[3];
+  a.controls[2 * q + 1] = s3 >= 0.0 ? a.turn_max : -a.turn_max;
+  if (a.values) a.values[q] = val;
+  if (a.grads)
+    for (int d = 0; d < 4; ++d) a.grads[4 * q + d] = p[d];
+}
+
 }  // namespace
 
 template <typename T>
@@ -1317,6 +1467,40 @@ template hipError_t launch_persistent<float>(const PersistArgs<float> &, int, in
 template hipError_t launch_persistent<double>(const PersistArgs<double> &, int, int, bool, bool, hipStream_t);
 template int persistent_blocks_per_cu<float>(int, bool, bool);
 template int persistent_blocks_per_cu<double>(int, bool, bool);
+template <typename T>
+hipError_t launch_delta_max(const T *a, const T *b, int64_t n, unsigned long long *acc, const int32_t *skip,
+                            hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(delta_max_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n, acc, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_converge_check(unsigned long long *acc, double threshold, int32_t *state, double *eps_log, int slot,
+                                 int64_t k, hipStream_t s) {
+  hipLaunchKernelGGL(converge_check_kernel, dim3(1), dim3(1), 0, s, acc, threshold, state, eps_log, slot, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_converge_reset(unsigned long long *acc, int32_t *state, hipStream_t s) {
+  hipLaunchKernelGGL(converge_reset_kernel, dim3(1), dim3(1), 0, s, acc, state);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_control(const ControlArgs<T> &a, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(control_kernel<T>, dim3((unsigned)((a.m + 63) / 64)), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_delta_max<float>(const float *, const float *, int64_t, unsigned long long *,
+                                            const int32_t *, hipStream_t);
+template hipError_t launch_delta_max<double>(const double *, const double *, int64_t, unsigned long long *,
+                                             const int32_t *, hipStream_t);
+template hipError_t launch_control<float>(const ControlArgs<float> &, hipStream_t);
+template hipError_t launch_control<double>(const ControlArgs<double> &, hipStream_t);
 template hipError_t launch_stream<float>(const StreamArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_plane<float>(const StreamArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_plane<double>(const StreamArgs<double> &, int, bool, hipStream_t);

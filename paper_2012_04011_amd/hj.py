@@ -25,7 +25,7 @@ HJ_OK, HJ_ERR_INVALID_ARG, HJ_ERR_OUT_OF_MEMORY, HJ_ERR_DEVICE, HJ_ERR_NOT_READY
     HJ_ERR_UNSUPPORTED = range(7)
 HJ_F32, HJ_F64 = 0, 1
 HJ_HOST, HJ_DEVICE = 0, 1
-HJ_DYN_CAR4D, HJ_DYN_DRIFT_INPUT = 0, 1
+HJ_DYN_CAR4D, HJ_DYN_DRIFT_INPUT, HJ_DYN_CAR4D_STEER = 0, 1, 2
 HJ_UPWIND1, HJ_ENO2 = 0, 1
 HJ_EULER, HJ_TVD_RK2 = 0, 1
 HJ_CLAMP_NONE, HJ_CLAMP_MIN_V0 = 0, 1
@@ -41,7 +41,7 @@ EXPORTED = [
     "hj_grid_create", "hj_grid_destroy", "hj_set_target", "hj_set_target_cylinders", "hj_solve_brt",
     "hj_step", "hj_get_cfl_dt", "hj_get_alpha_max", "hj_get_value", "hj_get_target", "hj_set_value",
     "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_get_launch_info", "hj_autotune",
-    "hj_set_autotune", "hj_batch_create", "hj_batch_destroy", "hj_batch_solve", "hj_batch_set_tile",
+    "hj_set_autotune", "hj_solve_converge", "hj_optimal_control", "hj_batch_create", "hj_batch_destroy", "hj_batch_solve", "hj_batch_set_tile",
     "hj_batch_set_spin_limit", "hj_batch_autotune", "hj_batch_get_info", "hj_server_create", "hj_server_destroy",
     "hj_server_submit", "hj_server_tick", "hj_server_poll", "hj_server_take", "hj_server_get_stats",
     "hj_last_error", "hj_version",
@@ -62,7 +62,8 @@ class hj_grid_desc(ctypes.Structure):
 class hj_dynamics_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("a_max", ctypes.c_double), ("w_max", ctypes.c_double),
                 ("d_max", ctypes.c_double * 2), ("drift", ctypes.c_double * 4), ("in_speed", ctypes.c_double),
-                ("in_axes_mask", ctypes.c_uint32), ("in_norm", ctypes.c_int32), ("in_role", ctypes.c_int32)]
+                ("in_axes_mask", ctypes.c_uint32), ("in_norm", ctypes.c_int32), ("in_role", ctypes.c_int32),
+                ("steer_max", ctypes.c_double), ("wheelbase", ctypes.c_double)]
 
 
 class hj_scheme_desc(ctypes.Structure):
@@ -81,6 +82,11 @@ class hj_launch_info(ctypes.Structure):
 
 
 KERNEL_NAMES = {0: "generic", 1: "stream", 2: "plane"}
+
+
+class hj_converge_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("eps_last", ctypes.c_double)]
 
 
 class hj_batch_info(ctypes.Structure):
@@ -143,6 +149,8 @@ def load_library(path: str = LIB_PATH):
         "hj_get_launch_info": [vp, P(hj_launch_info)],
         "hj_autotune": [vp],
         "hj_set_autotune": [vp, i32],
+        "hj_solve_converge": [vp, dbl, i64, P(hj_converge_info)],
+        "hj_optimal_control": [vp, vp, i64, i32, vp, vp],
         "hj_batch_create": [P(vp), i32, P(vp)],
         "hj_batch_destroy": [vp],
         "hj_batch_solve": [vp, P(dbl), i32, P(hj_solve_info)],
@@ -177,7 +185,7 @@ def _check(status: int, func: str):
 
 # ----------------------------------------------------------- marshalling ---
 
-_KIND = {"car4d": HJ_DYN_CAR4D, "drift_input": HJ_DYN_DRIFT_INPUT}
+_KIND = {"car4d": HJ_DYN_CAR4D, "drift_input": HJ_DYN_DRIFT_INPUT, "car4d_steer": HJ_DYN_CAR4D_STEER}
 _DERIV = {"upwind1": HJ_UPWIND1, "eno2": HJ_ENO2}
 _INTEG = {"euler": HJ_EULER, "rk2": HJ_TVD_RK2}
 _NORM = {"box": HJ_NORM_BOX, "ball": HJ_NORM_BALL}
@@ -205,6 +213,8 @@ def dynamics_desc(dyn: dict) -> hj_dynamics_desc:
     s.in_axes_mask = sum(1 << int(a) for a in dyn.get("in_axes", ()))
     s.in_norm = _NORM[dyn.get("in_norm", "box")]
     s.in_role = _ROLE[dyn.get("in_role", "max")]
+    s.steer_max = float(dyn.get("steer_max", 0.0))
+    s.wheelbase = float(dyn.get("wheelbase", 0.0))
     return s
 
 
@@ -347,6 +357,36 @@ def hj_autotune(h: int) -> None:
 
 def hj_set_autotune(h: int, enable: bool) -> None:
     _check(load_library().hj_set_autotune(h, 1 if enable else 0), "hj_set_autotune")
+
+
+def hj_solve_converge(h: int, threshold: float, max_steps: int) -> dict:
+    i = hj_converge_info()
+    _check(_lib.hj_solve_converge(h, float(threshold), int(max_steps), ctypes.byref(i)), "hj_solve_converge")
+    return {"steps": i.steps, "converged": bool(i.converged), "dt": i.dt, "eps_last": i.eps_last}
+
+
+def hj_optimal_control(h: int, states, controls=None, values=None):
+    """states: (m, 4) float64 numpy array (host) or torch tensor (device).
+    Returns (controls (m, 2), values (m,)) of the same kind."""
+    if isinstance(states, np.ndarray) or not hasattr(states, "data_ptr"):
+        z = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(-1, 4))
+        m = z.shape[0]
+        u = np.empty((m, 2)) if controls is None else controls
+        val = np.empty(m) if values is None else values
+        _check(_lib.hj_optimal_control(h, z.ctypes.data, m, HJ_HOST, u.ctypes.data, val.ctypes.data),
+               "hj_optimal_control")
+        return u, val
+    import torch
+
+    z = states.contiguous()
+    if z.dtype != torch.float64:
+        raise TypeError("states must be float64")
+    m = z.shape[0]
+    u = torch.empty((m, 2), dtype=torch.float64, device=z.device) if controls is None else controls
+    val = torch.empty(m, dtype=torch.float64, device=z.device) if values is None else values
+    _check(_lib.hj_optimal_control(h, z.data_ptr(), m, HJ_DEVICE, u.data_ptr(), val.data_ptr()),
+           "hj_optimal_control")
+    return u, val
 
 
 def hj_batch_create(handles) -> int:
@@ -528,6 +568,12 @@ class Grid:
 
     def launch_info(self) -> dict:
         return hj_get_launch_info(self.handle)
+
+    def solve_converge(self, threshold: float, max_steps: int) -> dict:
+        return hj_solve_converge(self.handle, threshold, max_steps)
+
+    def optimal_control(self, states):
+        return hj_optimal_control(self.handle, states)
 
     def autotune(self):
         hj_autotune(self.handle)

@@ -47,7 +47,7 @@ def test_struct_sizes_match_the_header_layout():
     assert ctypes.sizeof(hj.hj_grid_desc) == 88
     assert ctypes.sizeof(hj.hj_scheme_desc) == 24
     assert ctypes.sizeof(hj.hj_solve_info) == 32
-    assert ctypes.sizeof(hj.hj_dynamics_desc) == 96
+    assert ctypes.sizeof(hj.hj_dynamics_desc) == 112
 
 
 def _create(grid=None, dyn=None, sch=None, precision="f32"):
