@@ -15,7 +15,7 @@ Problem descriptions are plain dicts (see ``paper_2012_04011_amd.workloads``):
              {"kind": "car4d_steer", "a_max": 1.5, "steer_max": pi/18, "wheelbase": 0.3,
               "d_max": (0.0, 0.0)}
     scheme = {"deriv": "upwind1"|"eno2", "integrator": "euler"|"rk2",
-              "clamp": True, "cfl": 0.8}
+              "clamp": True, "cfl": 0.8, "alpha": "state"|"deriv_range"}
 
 Arrays are float64 numpy arrays of shape ``n`` in C order [x][y][v][theta].
 """
@@ -76,6 +76,7 @@ class _Scheme(ctypes.Structure):
         ("deriv", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
         ("clamp", ctypes.c_int32),
+        ("alpha_mode", ctypes.c_int32),
         ("cfl", ctypes.c_double),
     ]
 
@@ -113,6 +114,8 @@ def _load():
                                            P(ctypes.c_int32), dp, dp]
         lib.hjo_solve_converge.restype = ctypes.c_int
         lib.hjo_optimal_control.argtypes = [g, dy, dp, dp, ctypes.c_int64, dp, dp, dp]
+        lib.hjo_deriv_range.argtypes = [g, sc, dp, dp, dp]
+        lib.hjo_alpha_box.argtypes = [dy, dp, dp, dp, dp]
         lib.hjo_optimal_control.restype = ctypes.c_int
         lib.hjo_threads.restype = ctypes.c_int32
         lib.hjo_set_threads.argtypes = [ctypes.c_int32]
@@ -127,6 +130,7 @@ _DERIV = {"upwind1": 0, "eno2": 1}
 _INTEG = {"euler": 0, "rk2": 1}
 _NORM = {"box": 0, "ball": 1}
 _ROLE = {"max": 0, "min": 1}
+_ALPHA = {"state": 0, "deriv_range": 1}
 
 
 def _grid(grid) -> _Grid:
@@ -166,6 +170,7 @@ def _scheme(scheme) -> _Scheme:
     s.deriv = _DERIV[scheme["deriv"]]
     s.integrator = _INTEG[scheme["integrator"]]
     s.clamp = 1 if scheme.get("clamp", True) else 0
+    s.alpha_mode = _ALPHA[scheme.get("alpha", "state")]
     s.cfl = float(scheme.get("cfl", 0.8))
     return s
 
@@ -285,6 +290,8 @@ def solve_converge(grid, dyn, scheme, V0, threshold: float, max_steps: int):
     rc = _load().hjo_solve_converge(ctypes.byref(_grid(grid)), ctypes.byref(_dyn(dyn)), ctypes.byref(_scheme(scheme)),
                                     _dptr(V0), float(threshold), int(max_steps), _dptr(V), ctypes.byref(n),
                                     ctypes.byref(conv), ctypes.byref(eps), ctypes.byref(dt))
+    if rc == -2:
+        raise ValueError("convergence mode needs the state-bound alpha")
     if rc != 0:
         raise MemoryError("oracle converge: out of memory")
     return V, {"steps": n.value, "converged": bool(conv.value), "eps_last": eps.value, "dt": dt.value}
@@ -304,6 +311,22 @@ def optimal_control(grid, dyn, V, states):
     if rc != 0:
         raise ValueError("optimal control is defined for the car dynamics only")
     return u, val, gr
+
+
+def deriv_range(grid, scheme, V):
+    """(pmin, pmax): smallest and largest one-sided derivative per axis."""
+    V = _f64(V, _shape(grid))
+    lo, hi = np.empty(4), np.empty(4)
+    _load().hjo_deriv_range(ctypes.byref(_grid(grid)), ctypes.byref(_scheme(scheme)), _dptr(V), _dptr(lo), _dptr(hi))
+    return lo, hi
+
+
+def alpha_box(dyn, z, pmin, pmax) -> np.ndarray:
+    """Algorithm 1's alpha at state z for the gradient box [pmin, pmax]."""
+    z, lo, hi = _f64(z), _f64(pmin), _f64(pmax)
+    out = np.empty(4)
+    _load().hjo_alpha_box(ctypes.byref(_dyn(dyn)), _dptr(z), _dptr(lo), _dptr(hi), _dptr(out))
+    return out
 
 
 def threads() -> int:

@@ -76,8 +76,15 @@ typedef struct {
   double steer_max, wheelbase;
 } hjo_dyn;
 
+/* alpha_mode: HJO_ALPHA_STATE = alpha_d(z) bounds |f_d| over every input
+ * (state-local, the default); HJO_ALPHA_DERIV_RANGE = Algorithm 1's global
+ * Lax-Friedrichs: alpha_d(z) = max |dH/dp_d (z, p)| over the box of
+ * gradients spanned, axis by axis, by the smallest and largest one-sided
+ * derivative on the grid, recomputed every step together with dt. */
+enum { HJO_ALPHA_STATE = 0, HJO_ALPHA_DERIV_RANGE = 1 };
+
 typedef struct {
-  int32_t deriv, integrator, clamp;
+  int32_t deriv, integrator, clamp, alpha_mode;
   double cfl;
 } hjo_scheme;
 
@@ -335,8 +342,109 @@ void hjo_derivs(const hjo_grid *g, const hjo_scheme *sc, const double *V, int32_
 /* ------------------------------------------------------------ L(V) --- */
 
 /* L(V)(z) = H(z, (p+ + p-)/2) + sum_d alpha_d(z) (p+_d - p-_d) / 2. */
+/* ---------------------------------- Algorithm 1: derivative-range alpha --- */
+
+/* Smallest and largest one-sided derivative (p- and p+ together) per axis
+ * over every node of V. */
+void hjo_deriv_range(const hjo_grid *g, const hjo_scheme *sc, const double *V, double pmin[4], double pmax[4]) {
+  int64_t st[4];
+  strides_of(g, st);
+  int64_t np = hjo_num_points(g);
+  for (int d = 0; d < 4; ++d) {
+    pmin[d] = INFINITY;
+    pmax[d] = -INFINITY;
+  }
+  for (int64_t p = 0; p < np; ++p) {
+    int idx[4];
+    unravel(g, p, idx);
+    for (int d = 0; d < 4; ++d) {
+      double a, b;
+      one_sided(g, sc->deriv, V, st, p, idx, d, &a, &b);
+      double lo = a < b ? a : b, hi = a < b ? b : a;
+      if (lo < pmin[d]) pmin[d] = lo;
+      if (hi > pmax[d]) pmax[d] = hi;
+    }
+  }
+}
+
+/* Largest |b + u| over the values u that a box-bounded input takes when its
+ * gradient component runs over [lo, hi]: the input is +bound where p >= 0
+ * and -bound where p < 0 (dir = +1; dir = -1 flips both), so the range
+ * decides which of the two vertices occur. */
+static double box_input_alpha(double b, double bound, int dir, double lo, double hi) {
+  double up = dir * bound, dn = -dir * bound;  /* input at p >= 0, at p < 0 */
+  double a = 0.0;
+  if (hi >= 0.0) a = fabs(b + up);
+  if (lo < 0.0 && fabs(b + dn) > a) a = fabs(b + dn);
+  return a;
+}
+
+/* Range of p_d / |p_S| over the box (S = the ball's axes, d in S): it grows
+ * with p_d; for p_d > 0 it falls as the other components grow, for p_d < 0
+ * it rises.  A zero gradient counts as 0 (the input is then 0). */
+static void ball_ratio_range(const double pmin[4], const double pmax[4], uint32_t mask, int d, double *gmin,
+                             double *gmax) {
+  double rmin2 = 0.0, rmax2 = 0.0;
+  for (int e = 0; e < 4; ++e) {
+    if (e == d || !((mask >> e) & 1u)) continue;
+    double a = pmin[e] * pmin[e], b = pmax[e] * pmax[e];
+    rmax2 += a > b ? a : b;
+    if (!(pmin[e] <= 0.0 && pmax[e] >= 0.0)) rmin2 += a < b ? a : b;
+  }
+  double M = pmax[d], m = pmin[d];
+  *gmax = M > 0.0 ? M / sqrt(M * M + rmin2) : (M < 0.0 ? M / sqrt(M * M + rmax2) : 0.0);
+  *gmin = m < 0.0 ? m / sqrt(m * m + rmin2) : (m > 0.0 ? m / sqrt(m * m + rmax2) : 0.0);
+}
+
+/* alpha_d(z) = max over the gradient box of |dH/dp_d (z, p)| (Algorithm 1):
+ * dH/dp_d = f_d(z, u*(p), d*(p)) for the input-affine dynamics here. */
+void hjo_alpha_box(const hjo_dyn *dy, const double z[4], const double pmin[4], const double pmax[4],
+                   double alpha[4]) {
+  if (dy->kind == HJO_CAR4D || dy->kind == HJO_CAR4D_STEER) {
+    /* the disturbance minimises: -d_max where p >= 0 */
+    alpha[0] = box_input_alpha(z[2] * cos(z[3]), dy->d_max[0], -1, pmin[0], pmax[0]);
+    alpha[1] = box_input_alpha(z[2] * sin(z[3]), dy->d_max[1], -1, pmin[1], pmax[1]);
+    alpha[2] = box_input_alpha(0.0, dy->a_max, +1, pmin[2], pmax[2]);
+    if (dy->kind == HJO_CAR4D)
+      alpha[3] = box_input_alpha(0.0, dy->w_max, +1, pmin[3], pmax[3]);
+    else
+      alpha[3] = box_input_alpha(0.0, fabs(z[2]) * tan(dy->steer_max) / dy->wheelbase, +1, pmin[3], pmax[3]);
+    return;
+  }
+  int dir = dy->in_role == HJO_INPUT_MAXIMIZES ? 1 : -1;
+  for (int d = 0; d < 4; ++d) {
+    double b = dy->drift[d];
+    if (!((dy->in_axes_mask >> d) & 1u)) {
+      alpha[d] = fabs(b);
+    } else if (dy->in_norm == HJO_BOX) {
+      alpha[d] = box_input_alpha(b, dy->in_speed, dir, pmin[d], pmax[d]);
+    } else {
+      double gmin, gmax;
+      ball_ratio_range(pmin, pmax, dy->in_axes_mask, d, &gmin, &gmax);
+      double a = fabs(b + dir * dy->in_speed * gmax), c = fabs(b + dir * dy->in_speed * gmin);
+      alpha[d] = a > c ? a : c;
+    }
+  }
+}
+
+/* max over the grid's nodes of hjo_alpha_box. */
+void hjo_alpha_max_box(const hjo_grid *g, const hjo_dyn *dy, const double pmin[4], const double pmax[4],
+                       double amax[4]) {
+  for (int d = 0; d < 4; ++d) amax[d] = 0.0;
+  int64_t np = hjo_num_points(g);
+  for (int64_t p = 0; p < np; ++p) {
+    int idx[4];
+    double z[4], a[4];
+    unravel(g, p, idx);
+    for (int d = 0; d < 4; ++d) z[d] = hjo_node(g, d, idx[d]);
+    hjo_alpha_box(dy, z, pmin, pmax, a);
+    for (int d = 0; d < 4; ++d)
+      if (a[d] > amax[d]) amax[d] = a[d];
+  }
+}
+
 static double rhs_at(const hjo_grid *g, const hjo_dyn *dy, int deriv, const double *V,
-                     const int64_t st[4], int64_t p) {
+                     const int64_t st[4], int64_t p, const double *box) {
   int idx[4];
   double z[4], pm[4], pp[4], pbar[4], alpha[4];
   unravel(g, p, idx);
@@ -345,7 +453,10 @@ static double rhs_at(const hjo_grid *g, const hjo_dyn *dy, int deriv, const doub
     one_sided(g, deriv, V, st, p, idx, d, &pm[d], &pp[d]);
     pbar[d] = (pp[d] + pm[d]) / 2.0;
   }
-  alpha_at(dy, z, alpha);
+  if (box)
+    hjo_alpha_box(dy, z, box, box + 4, alpha);
+  else
+    alpha_at(dy, z, alpha);
   double diss = 0.0;
   for (int d = 0; d < 4; ++d) diss += alpha[d] * (pp[d] - pm[d]) / 2.0;
   return hamiltonian(dy, z, pbar) + diss;
@@ -353,8 +464,8 @@ static double rhs_at(const hjo_grid *g, const hjo_dyn *dy, int deriv, const doub
 
 /* L(V) at every node (outermost axis split across OpenMP threads; every
  * node is independent, so the result does not depend on the thread count). */
-void hjo_rhs(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V,
-             double *L) {
+static void rhs_all(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V,
+                    const double *box, double *L) {
   int64_t st[4];
   strides_of(g, st);
   int n0 = g->n[0];
@@ -362,8 +473,16 @@ void hjo_rhs(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const d
   for (int i = 0; i < n0; ++i)
     for (int64_t q = 0; q < st[0]; ++q) {
       int64_t p = (int64_t)i * st[0] + q;
-      L[p] = rhs_at(g, dy, sc->deriv, V, st, p);
+      L[p] = rhs_at(g, dy, sc->deriv, V, st, p, box);
     }
+}
+
+/* L(V); in the derivative-range mode alpha comes from V's own range. */
+void hjo_rhs(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V,
+             double *L) {
+  double box[8];
+  if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE) hjo_deriv_range(g, sc, V, box, box + 4);
+  rhs_all(g, dy, sc, V, sc->alpha_mode == HJO_ALPHA_DERIV_RANGE ? box : NULL, L);
 }
 
 /* ------------------------------------------------------------- steps --- */
@@ -376,16 +495,18 @@ void hjo_rhs(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const d
  *                          V <- (V + V2) / 2.
  * Then, if the clamp is on, V <- min(V0, V) (once per full step).
  */
-void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0, double *V,
-              double dt, double *work) {
+/* One step with alpha from `box` (the derivative range of V at the start of
+ * the step; both TVD-RK2 stages use it) or the state bound (box NULL). */
+static void step_with(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0, double *V,
+                      double dt, const double *box, double *work) {
   int64_t np = hjo_num_points(g);
   double *L = work, *V1 = work + np;
-  hjo_rhs(g, dy, sc, V, L);
+  rhs_all(g, dy, sc, V, box, L);
   if (sc->integrator == HJO_EULER) {
     for (int64_t p = 0; p < np; ++p) V[p] = V[p] + dt * L[p];
   } else {
     for (int64_t p = 0; p < np; ++p) V1[p] = V[p] + dt * L[p];
-    hjo_rhs(g, dy, sc, V1, L);
+    rhs_all(g, dy, sc, V1, box, L);
     for (int64_t p = 0; p < np; ++p) {
       double v2 = V1[p] + dt * L[p];
       V[p] = (V[p] + v2) / 2.0;
@@ -396,6 +517,13 @@ void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const 
       if (V0[p] < V[p]) V[p] = V0[p];
 }
 
+void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0, double *V,
+              double dt, double *work) {
+  double box[8];
+  if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE) hjo_deriv_range(g, sc, V, box, box + 4);
+  step_with(g, dy, sc, V0, V, dt, sc->alpha_mode == HJO_ALPHA_DERIV_RANGE ? box : NULL, work);
+}
+
 /*
  * Whole fixed-horizon solve: V := V0, then n = ceil(T / dt) steps with the
  * CFL step dt and a shortened last step.  Returns 0 on success, -1 if memory
@@ -404,6 +532,35 @@ void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const 
 int hjo_solve(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0,
               double horizon, double *V, int64_t *n_steps, double *dt_out, double *dt_last_out) {
   int64_t np = hjo_num_points(g);
+  if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE) {
+    /* Algorithm 1: every step finds the derivative range, alpha and
+     * dt = cfl / sum_d(alpha_d^max / dx_d); the step that would reach or pass
+     * the horizon is shortened to end on it */
+    double *work = (double *)malloc((size_t)np * 2 * sizeof(double));
+    if (!work) return -1;
+    memcpy(V, V0, (size_t)np * sizeof(double));
+    double t = 0.0, first = 0.0, dtk = 0.0;
+    int64_t n = 0;
+    while (horizon > 0.0 && t < horizon) {
+      double box[8], amax[4], S = 0.0;
+      hjo_deriv_range(g, sc, V, box, box + 4);
+      hjo_alpha_max_box(g, dy, box, box + 4, amax);
+      for (int d = 0; d < 4; ++d) S += amax[d] / hjo_spacing(g, d);
+      dtk = S == 0.0 ? horizon - t : sc->cfl / S;
+      int last = t + dtk >= horizon;
+      if (last) dtk = horizon - t;
+      step_with(g, dy, sc, V0, V, dtk, box, work);
+      if (n == 0) first = dtk;
+      n += 1;
+      if (last) break;
+      t += dtk;
+    }
+    free(work);
+    if (n_steps) *n_steps = n;
+    if (dt_out) *dt_out = first;
+    if (dt_last_out) *dt_last_out = n > 0 ? dtk : 0.0;
+    return 0;
+  }
   double dt = hjo_cfl_dt(g, dy, sc->cfl, horizon);
   int64_t n;
   double dt_last;
@@ -432,6 +589,7 @@ int hjo_solve_converge(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *s
                        double threshold, int64_t max_steps, double *V, int64_t *n_steps, int32_t *converged,
                        double *eps_last, double *dt_out) {
   int64_t np = hjo_num_points(g);
+  if (sc->alpha_mode != HJO_ALPHA_STATE) return -2;  /* a fixed step needs the state bound */
   double dt = hjo_cfl_dt(g, dy, sc->cfl, 1.0);
   double *work = (double *)malloc((size_t)np * 3 * sizeof(double));
   if (!work) return -1;

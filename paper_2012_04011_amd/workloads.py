@@ -50,8 +50,10 @@ def steer_dynamics(a_max: float = 1.5, steer_max: float = math.pi / 18, wheelbas
             "d_max": (d_max, d_max)}
 
 
-def scheme(deriv: str, integrator: str, cfl: float = 0.8, clamp: bool = True) -> dict:
-    return {"deriv": deriv, "integrator": integrator, "clamp": clamp, "cfl": cfl}
+def scheme(deriv: str, integrator: str, cfl: float = 0.8, clamp: bool = True, alpha: str = "state") -> dict:
+    """alpha: "state" (the bound on |f_d| over all inputs) or "deriv_range"
+    (Algorithm 1's global Lax-Friedrichs over the grid's derivative range)."""
+    return {"deriv": deriv, "integrator": integrator, "clamp": clamp, "cfl": cfl, "alpha": alpha}
 
 
 def cylinders(seed: int, m: int):

@@ -639,3 +639,127 @@ def test_control_undefined_for_test_dynamics(oracle_lib):
     g = W.car_grid(5, 5, 4, 8)
     with pytest.raises(ValueError):
         oracle_lib.optimal_control(g, drift_dyn(), np.zeros(g["n"]), np.zeros((1, 4)))
+
+
+# ------------------------------ Algorithm 1: derivative-range alpha (f4) ---
+
+
+def _dH_dp(dyn, z, p):
+    """dH/dp at p (envelope: f at the optimal inputs), by the definitions."""
+    k = dyn["kind"]
+    if k in ("car4d", "car4d_steer"):
+        dm = dyn.get("d_max", (0.0, 0.0))
+        dx = -dm[0] if p[0] >= 0 else dm[0]
+        dy = -dm[1] if p[1] >= 0 else dm[1]
+        a = dyn["a_max"] if p[2] >= 0 else -dyn["a_max"]
+        if k == "car4d":
+            w = dyn["w_max"] if p[3] >= 0 else -dyn["w_max"]
+        else:
+            delta = dyn["steer_max"] if p[3] * z[2] >= 0 else -dyn["steer_max"]
+            w = z[2] * math.tan(delta) / dyn["wheelbase"]
+        return np.array([z[2] * math.cos(z[3]) + dx, z[2] * math.sin(z[3]) + dy, a, w])
+    sgn = 1.0 if dyn["in_role"] == "max" else -1.0
+    out = np.array(dyn["drift"], dtype=float)
+    axes = dyn["in_axes"]
+    if dyn["in_norm"] == "box":
+        for d in axes:
+            out[d] += sgn * (dyn["in_speed"] if p[d] >= 0 else -dyn["in_speed"])
+    else:
+        nrm = math.sqrt(sum(p[d] ** 2 for d in axes))
+        if nrm > 0:
+            for d in axes:
+                out[d] += sgn * dyn["in_speed"] * p[d] / nrm
+    return out
+
+
+def _box_samples(lo, hi, k=7):
+    s = set(np.linspace(lo, hi, k).tolist())
+    if lo <= 0.0 <= hi:
+        s.add(0.0)
+    return sorted(s)
+
+
+@pytest.mark.parametrize("dyn", [
+    W.car_dynamics(d_max=0.1), W.steer_dynamics(d_max=0.05),
+    drift_dyn((0.4, -0.3, 0.2, 0.0), (0, 1), 0.7, "box", "max"),
+    drift_dyn((0.4, -0.3, 0.2, 0.0), (0, 1), 0.7, "box", "min"),
+    drift_dyn((0.4, -0.3, 0.0, 0.1), (0, 1, 3), 0.7, "ball", "max"),
+    drift_dyn((0.4, -0.3, 0.0, 0.1), (0, 1, 3), 0.7, "ball", "min"),
+], ids=["car", "steer", "box-max", "box-min", "ball-max", "ball-min"])
+def test_alpha_box_brute_force(oracle_lib, dyn):
+    """Algorithm 1's alpha_d = max over the gradient box of |dH/dp_d|, by
+    exhaustive search over a grid of the box that contains its corners and
+    (where inside) zero: boxes of both signs, one-signed and degenerate."""
+    rng = np.random.default_rng(31)
+    for trial in range(25):
+        lo, hi = np.empty(4), np.empty(4)
+        for d in range(4):
+            kind = rng.integers(4)
+            a, b = sorted(rng.normal(size=2))
+            if kind == 1:
+                a, b = abs(a), abs(a) + abs(b)  # positive
+            elif kind == 2:
+                a, b = -abs(a) - abs(b), -abs(a)  # negative
+            elif kind == 3:
+                a = b = 0.0 if rng.random() < 0.5 else abs(a)
+            lo[d], hi[d] = a, b
+        z = np.array([0.1, -0.2, rng.uniform(-2, 2), rng.uniform(-math.pi, math.pi)])
+        best = np.zeros(4)
+        for p0 in _box_samples(lo[0], hi[0]):
+            for p1 in _box_samples(lo[1], hi[1]):
+                for p2 in _box_samples(lo[2], hi[2], 3):
+                    for p3 in _box_samples(lo[3], hi[3]):
+                        best = np.maximum(best, np.abs(_dH_dp(dyn, z, (p0, p1, p2, p3))))
+        np.testing.assert_allclose(oracle_lib.alpha_box(dyn, z, lo, hi), best, rtol=0, atol=1e-12,
+                                   err_msg=f"trial {trial}: box {lo} {hi}")
+
+
+def test_deriv_range_exact_on_linear(oracle_lib):
+    """V = 0.7 x - 0.3 y + 1.2 v: every one-sided difference (ends included,
+    both schemes) is exact, so the ranges are the coefficients, and 0 on
+    theta."""
+    g = W.car_grid(9, 8, 6, 10)
+    x, y, v = (oracle_lib.nodes(g, d) for d in range(3))
+    V = 0.7 * x[:, None, None, None] - 0.3 * y[None, :, None, None] + 1.2 * v[None, None, :, None] \
+        + np.zeros(g["n"])
+    for sch in (UP_EU, ENO_RK):
+        lo, hi = oracle_lib.deriv_range(g, sch, V)
+        np.testing.assert_allclose(lo, [0.7, -0.3, 1.2, 0.0], atol=1e-12)
+        np.testing.assert_allclose(hi, [0.7, -0.3, 1.2, 0.0], atol=1e-12)
+
+
+def test_deriv_range_alpha_half_plane_closed_form(oracle_lib):
+    """z' = 0.5 + u on x, |u| <= 1, u minimising, target V0 = x: the
+    gradient is (1, 0, 0, 0) everywhere, the input is -1, so Algorithm 1's
+    alpha_x = |0.5 - 1| = 0.5 (the state bound is 1.5): dt = 0.8 dx / 0.5,
+    n = ceil(T / dt), and V_T = x - 0.5 T exactly (linear data, exact
+    differences, no dissipation)."""
+    g = W.car_grid(21, 6, 5, 8)
+    dyn = drift_dyn((0.5, 0, 0, 0), (0,), 1.0, "box", "min")
+    x = oracle_lib.nodes(g, 0)
+    V0 = np.broadcast_to(x[:, None, None, None], g["n"]).copy()
+    T = 2.1
+    sch = W.scheme("upwind1", "euler", alpha="deriv_range")
+    V, info = oracle_lib.solve(g, dyn, sch, V0, T)
+    dx = 10.0 / 20
+    dt = 0.8 * dx / 0.5
+    assert info["dt"] == pytest.approx(dt, rel=1e-15)
+    assert info["steps"] == math.ceil(T / dt)
+    np.testing.assert_allclose(V, V0 - 0.5 * T, atol=1e-13)
+    _, info_state = oracle_lib.solve(g, dyn, W.scheme("upwind1", "euler"), V0, T)
+    assert info_state["dt"] == pytest.approx(0.8 * dx / 1.5, rel=1e-15)
+
+
+@pytest.mark.parametrize("sch", [UP_EU, ENO_RK], ids=["upwind", "eno2"])
+def test_deriv_range_equals_state_bound_when_gradients_span_zero(oracle_lib, sch):
+    """Cylinder targets have gradients of every sign on x and y, so
+    Algorithm 1's alpha reaches the state bound: the same steps and the same
+    V (to the last bits of the accumulated time)."""
+    g = W.car_grid(16, 15, 6, 12)
+    dyn = W.car_dynamics(d_max=0.1)
+    V0 = oracle_lib.target_cylinders(g, *W.cylinders(6, 3))
+    a = dict(sch, alpha="deriv_range")
+    V1, i1 = oracle_lib.solve(g, dyn, a, V0, 0.6)
+    V2, i2 = oracle_lib.solve(g, dyn, sch, V0, 0.6)
+    assert i1["steps"] == i2["steps"] and i1["dt"] == i2["dt"]
+    assert np.abs(V1 - V2).max() < 1e-12
