@@ -106,9 +106,22 @@ typedef struct {
  * (Algorithm 2) or HJ_TVD_RK2; precision: HJ_F32 or HJ_F64 storage and
  * arithmetic of the time step (the CFL reduction is always FP64); clamp:
  * HJ_CLAMP_MIN_V0 applies V = min(V0, V) once per full step; cfl in (0, 1].
+ * alpha_mode: HJ_ALPHA_STATE (default): the dissipation coefficient
+ * alpha_d(z) bounds |f_d| over every input, fixed per grid, one CFL step
+ * for the whole solve.  HJ_ALPHA_DERIV_RANGE (Algorithm 1, the general
+ * Lax-Friedrichs scheme): every step first finds the smallest and largest
+ * one-sided derivative per axis on the grid, takes alpha_d(z) = max |dH/dp_d|
+ * over that box of gradients and dt = cfl / sum_d(alpha_d^max / dx_d), the
+ * last step shortened to the horizon; both TVD-RK2 stages use the step's
+ * alpha.  It needs a host round trip per step; batches, servers and the
+ * convergence mode reject it.
  */
+enum { HJ_ALPHA_STATE = 0, HJ_ALPHA_DERIV_RANGE = 1 };
+
 typedef struct {
   int32_t deriv, integrator, precision, clamp;
+  int32_t alpha_mode;
+  int32_t reserved; /* 0 */
   double cfl;
 } hj_scheme_desc;
 

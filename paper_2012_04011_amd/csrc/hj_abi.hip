@@ -90,6 +90,13 @@ struct hj_grid {
   double *conv_eps = nullptr;              // device: eps of the last steps
   int32_t *conv_host = nullptr;            // pinned: state
   double *conv_eps_host = nullptr;         // pinned: eps log
+  // derivative-range alpha (Algorithm 1): the state table (bx, by, ax, ay)
+  // in FP64, device keys of the range, and the host copies of the tables
+  std::vector<double> tab64;
+  unsigned long long *range_keys = nullptr;
+  unsigned long long *range_host = nullptr;  // pinned
+  std::vector<double> up_lut, up_coef, up_th;
+  std::vector<float> up32;
   // control queries: device copies of host states and results
   double *ctl_dev = nullptr;
   int64_t ctl_cap = 0;  // states
@@ -158,6 +165,8 @@ hj_status validate(const hj_grid_desc *g, const hj_dynamics_desc *dy, const hj_s
   if (s->clamp != HJ_CLAMP_NONE && s->clamp != HJ_CLAMP_MIN_V0)
     return fail(HJ_ERR_INVALID_ARG, "unknown clamp %d", s->clamp);
   if (!(s->cfl > 0.0 && s->cfl <= 1.0)) return fail(HJ_ERR_INVALID_ARG, "cfl must lie in (0, 1]");
+  if (s->alpha_mode != HJ_ALPHA_STATE && s->alpha_mode != HJ_ALPHA_DERIV_RANGE)
+    return fail(HJ_ERR_INVALID_ARG, "unknown alpha_mode %d", s->alpha_mode);
   return HJ_OK;
 }
 
@@ -294,10 +303,11 @@ T *buf(void *p) {
 void free_all(hj_grid *G) {
   void *ptrs[] = {G->v0,       G->v,           G->w1,       G->w2,       G->lut,      G->coef,
                   G->th,       G->v0xy,        G->lut64,    G->amax_dev, G->flag_dev, G->conv_acc,
-                  G->conv_state, G->conv_eps, G->ctl_dev};
+                  G->conv_state, G->conv_eps, G->ctl_dev, G->range_keys};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (G->conv_host) (void)hipHostFree(G->conv_host);
+  if (G->range_host) (void)hipHostFree(G->range_host);
   if (G->conv_eps_host) (void)hipHostFree(G->conv_eps_host);
   if (G->amax_host) (void)hipHostFree(G->amax_host);
   if (G->flag_host) (void)hipHostFree(G->flag_host);
@@ -596,6 +606,145 @@ hj_status step_once(hj_grid *G, double dt, int64_t *launches) {
   return enqueue_step<double>(G, dt, launches);
 }
 
+// ---- Algorithm 1's derivative-range alpha ----------------------------------
+
+double key_to_double(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  double x;
+  memcpy(&x, &b, sizeof x);
+  return x;
+}
+
+// A box-bounded input that is +dir*bound where its gradient component is
+// >= 0 and -dir*bound where it is < 0: the largest |b + input| over the
+// gradient range [lo, hi].
+double range_box_alpha(double b, double bound, int dir, double lo, double hi) {
+  double best = 0.0;
+  if (hi >= 0.0) best = fabs(b + dir * bound);
+  if (lo < 0.0) {
+    double c = fabs(b - dir * bound);
+    if (c > best) best = c;
+  }
+  return best;
+}
+
+// Extremes of p_d / |p_S| over the gradient box (0 where p_S = 0).
+void range_ball_ratio(const double lo[4], const double hi[4], uint32_t mask, int d, double *gmin, double *gmax) {
+  double near2 = 0.0, far2 = 0.0;
+  for (int e = 0; e < 4; ++e) {
+    if (e == d || !bit(mask, e)) continue;
+    double a = lo[e] * lo[e], b = hi[e] * hi[e];
+    far2 += a > b ? a : b;
+    if (lo[e] > 0.0 || hi[e] < 0.0) near2 += a < b ? a : b;
+  }
+  double M = hi[d], m = lo[d];
+  *gmax = M > 0.0 ? M / sqrt(M * M + near2) : (M < 0.0 ? M / sqrt(M * M + far2) : 0.0);
+  *gmin = m < 0.0 ? m / sqrt(m * m + near2) : (m > 0.0 ? m / sqrt(m * m + far2) : 0.0);
+}
+
+template <typename T>
+hj_status upload_tables(hj_grid *G, void *dst, const std::vector<double> &src) {
+  if (G->elem == 8) {
+    HJ_HIP(hipMemcpyAsync(dst, src.data(), src.size() * 8, hipMemcpyHostToDevice, S(G)));
+  } else {
+    // the float staging copy of each table lives until the next range update
+    // (which synchronises first)
+    size_t off = G->up32.size();
+    G->up32.resize(off + src.size());
+    for (size_t i = 0; i < src.size(); ++i) G->up32[off + i] = (float)src[i];
+    HJ_HIP(hipMemcpyAsync(dst, G->up32.data() + off, src.size() * 4, hipMemcpyHostToDevice, S(G)));
+  }
+  return HJ_OK;
+}
+
+// Derivative range of the current V on the device, Algorithm 1's alpha on
+// the host, the stage tables rewritten with it; *dt_allowed = cfl / sum_d
+// alpha_d^max / dx_d (+inf when nothing moves).  Synchronises.
+hj_status range_alpha_update(hj_grid *G, double *dt_allowed) {
+  hj_status st0 = ensure_dt(G);  // caches the state-bound step before av is rewritten below
+  if (st0 != HJ_OK) return st0;
+  if (!G->range_keys) {
+    HJ_HIP(hipMalloc((void **)&G->range_keys, 8 * sizeof(unsigned long long)));
+    HJ_HIP(hipHostMalloc((void **)&G->range_host, 8 * sizeof(unsigned long long), 0));
+  }
+  if (G->elem == 4) {
+    hj::StageArgs<float> a = stage_args<float>(G);
+    a.vs = buf<const float>(G->v);
+    HJ_HIP(hj::launch_deriv_range(a, G->sch.deriv, G->range_keys, S(G)));
+  } else {
+    hj::StageArgs<double> a = stage_args<double>(G);
+    a.vs = buf<const double>(G->v);
+    HJ_HIP(hj::launch_deriv_range(a, G->sch.deriv, G->range_keys, S(G)));
+  }
+  HJ_HIP(hipMemcpyAsync(G->range_host, G->range_keys, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, S(G)));
+  HJ_HIP(hipStreamSynchronize(S(G)));  // also retires the previous update's uploads
+  double lo[4], hi[4];
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = key_to_double(G->range_host[d]);
+    hi[d] = key_to_double(G->range_host[4 + d]);
+  }
+  const hj_dynamics_desc &dy = G->dyn;
+  const int n2 = G->g.n[2], n3 = G->g.n[3];
+  const int64_t m = (int64_t)n2 * n3;
+  const std::vector<double> &tab = G->tab64;
+  G->up_lut.assign(tab.begin(), tab.end());
+  double amax[4] = {0, 0, 0, 0};
+  std::vector<double> ath(n2);
+  if (dy.kind == HJ_DYN_CAR4D || dy.kind == HJ_DYN_CAR4D_STEER) {
+    for (int64_t c = 0; c < m; ++c) {  // the disturbance is -d_max where p >= 0
+      G->up_lut[2 * m + c] = range_box_alpha(tab[c], dy.d_max[0], -1, lo[0], hi[0]);
+      G->up_lut[3 * m + c] = range_box_alpha(tab[m + c], dy.d_max[1], -1, lo[1], hi[1]);
+    }
+    G->av = range_box_alpha(0.0, dy.a_max, +1, lo[2], hi[2]);
+    for (int k = 0; k < n2; ++k) ath[k] = range_box_alpha(0.0, G->th_s[k], +1, lo[3], hi[3]);
+  } else {
+    const int dir = dy.in_role == HJ_INPUT_MAXIMIZES ? 1 : -1;
+    double al[4];
+    for (int d = 0; d < 4; ++d) {
+      if (!bit(dy.in_axes_mask, d)) {
+        al[d] = fabs(dy.drift[d]);
+      } else if (dy.in_norm == HJ_NORM_BOX) {
+        al[d] = range_box_alpha(dy.drift[d], dy.in_speed, dir, lo[d], hi[d]);
+      } else {
+        double gmin, gmax;
+        range_ball_ratio(lo, hi, dy.in_axes_mask, d, &gmin, &gmax);
+        double a1 = fabs(dy.drift[d] + dir * dy.in_speed * gmax), a2 = fabs(dy.drift[d] + dir * dy.in_speed * gmin);
+        al[d] = a1 > a2 ? a1 : a2;
+      }
+    }
+    for (int64_t c = 0; c < m; ++c) {
+      G->up_lut[2 * m + c] = al[0];
+      G->up_lut[3 * m + c] = al[1];
+    }
+    G->av = al[2];
+    for (int k = 0; k < n2; ++k) ath[k] = al[3];
+  }
+  for (int64_t c = 0; c < m; ++c) {
+    if (G->up_lut[2 * m + c] > amax[0]) amax[0] = G->up_lut[2 * m + c];
+    if (G->up_lut[3 * m + c] > amax[1]) amax[1] = G->up_lut[3 * m + c];
+  }
+  amax[2] = G->av;
+  for (int k = 0; k < n2; ++k)
+    if (ath[k] > amax[3]) amax[3] = ath[k];
+  // the stage tables with this alpha (the Hamiltonian's own terms unchanged)
+  build_coef(G, G->up_lut, G->up_coef);
+  std::vector<double> keep_a = G->th_a;
+  G->th_a = ath;
+  build_theta(G, G->up_th);
+  G->th_a = keep_a;
+  G->up32.clear();
+  G->up32.reserve(G->up_lut.size() + G->up_coef.size() + G->up_th.size());
+  hj_status st;
+  if ((st = upload_tables<double>(G, G->lut, G->up_lut)) != HJ_OK) return st;
+  if ((st = upload_tables<double>(G, G->coef, G->up_coef)) != HJ_OK) return st;
+  if ((st = upload_tables<double>(G, G->th, G->up_th)) != HJ_OK) return st;
+  double sum = 0.0;
+  for (int d = 0; d < 4; ++d) sum += amax[d] / G->h[d];
+  *dt_allowed = sum == 0.0 ? INFINITY : G->sch.cfl / sum;
+  (void)n3;
+  return HJ_OK;
+}
+
 hj_status reset_value(hj_grid *G) {
   HJ_HIP(hipMemcpyAsync(G->v, G->v0, G->npts * G->elem, hipMemcpyDeviceToDevice, S(G)));
   return HJ_OK;
@@ -693,6 +842,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   build_table(G, tab);
   build_coef(G, tab, coef);
   build_theta(G, th);
+  if (scheme->alpha_mode == HJ_ALPHA_DERIV_RANGE) G->tab64 = tab;
   int64_t m = (int64_t)grid->n[2] * grid->n[3];
   {
     int run = hj::run_length(G->elem, grid->n[3]);
@@ -879,6 +1029,32 @@ hj_status hj_solve_brt(hj_grid *G, double horizon, hj_solve_info *info) {
   if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
   if ((st = set_device(G)) != HJ_OK) return st;
   if ((st = ensure_dt(G)) != HJ_OK) return st;
+  if (G->sch.alpha_mode == HJ_ALPHA_DERIV_RANGE) {
+    // Algorithm 1: alpha and dt from each step's derivative range; the step
+    // that would reach or pass the horizon is shortened to end on it
+    if ((st = reset_value(G)) != HJ_OK) return st;
+    double t = 0.0, first = 0.0, dtk = 0.0;
+    int64_t n = 0, launches = 0;
+    while (horizon > 0.0 && t < horizon) {
+      double allowed;
+      if ((st = range_alpha_update(G, &allowed)) != HJ_OK) return st;
+      dtk = isinf(allowed) ? horizon - t : allowed;
+      const bool last = t + dtk >= horizon;
+      if (last) dtk = horizon - t;
+      if ((st = step_once(G, dtk, &launches)) != HJ_OK) return st;
+      if (n == 0) first = dtk;
+      n += 1;
+      if (last) break;
+      t += dtk;
+    }
+    if (info) {
+      info->steps = n;
+      info->dt = first;
+      info->dt_last = n > 0 ? dtk : 0.0;
+      info->t_final = horizon;
+    }
+    return HJ_OK;
+  }
   double dt, dt_last;
   int64_t n;
   schedule(G, horizon, &n, &dt, &dt_last);
@@ -914,7 +1090,14 @@ hj_status hj_step(hj_grid *G, double dt, double *dt_taken) {
   if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
   if (isnan(dt) || isinf(dt)) return fail(HJ_ERR_INVALID_ARG, "dt must be finite");
   if ((st = set_device(G)) != HJ_OK) return st;
-  if (dt <= 0) {
+  if (G->sch.alpha_mode == HJ_ALPHA_DERIV_RANGE) {
+    double allowed;
+    if ((st = range_alpha_update(G, &allowed)) != HJ_OK) return st;
+    if (dt <= 0) {
+      if (isinf(allowed)) return fail(HJ_ERR_INVALID_ARG, "nothing moves: the CFL step is unbounded, pass dt > 0");
+      dt = allowed;
+    }
+  } else if (dt <= 0) {
     if ((st = ensure_dt(G)) != HJ_OK) return st;
     if (isinf(G->dt_cfl)) return fail(HJ_ERR_INVALID_ARG, "nothing moves: the CFL step is unbounded, pass dt > 0");
     dt = G->dt_cfl;
@@ -931,6 +1114,8 @@ hj_status hj_solve_converge(hj_grid *G, double threshold, int64_t max_steps, hj_
   if (isnan(threshold) || threshold < 0) return fail(HJ_ERR_INVALID_ARG, "threshold must be >= 0");
   if (max_steps < 1) return fail(HJ_ERR_INVALID_ARG, "max_steps must be >= 1");
   if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
+  if (G->sch.alpha_mode != HJ_ALPHA_STATE)
+    return fail(HJ_ERR_UNSUPPORTED, "the convergence mode steps with the state-bound CFL step");
   if ((st = set_device(G)) != HJ_OK) return st;
   if ((st = ensure_dt(G)) != HJ_OK) return st;
   const int K = kConvergeChunk;
@@ -1486,6 +1671,8 @@ hj_status hj_batch_create(hj_grid *const *grids, int32_t m, hj_batch **out) {
       return fail(HJ_ERR_UNSUPPORTED, "grid %d: a batch needs one device and one stream", j);
     if (!G->stream_ok)
       return fail(HJ_ERR_UNSUPPORTED, "grid %d: batched solves need a periodic theta axis and < 4 GiB arrays", j);
+    if (G->sch.alpha_mode != HJ_ALPHA_STATE)
+      return fail(HJ_ERR_UNSUPPORTED, "grid %d: batched solves need the state-bound alpha", j);
   }
   hj_batch *b = new (std::nothrow) hj_batch;
   if (!b) return fail(HJ_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -1955,6 +2142,7 @@ hj_status hj_server_create(const hj_server_desc *desc, void *hip_stream, hj_serv
       (sc.precision != HJ_F32 && sc.precision != HJ_F64) || (sc.clamp != HJ_CLAMP_NONE && sc.clamp != HJ_CLAMP_MIN_V0) ||
       !(sc.cfl > 0.0 && sc.cfl <= 1.0))
     return fail(HJ_ERR_INVALID_ARG, "invalid scheme");
+  if (sc.alpha_mode != HJ_ALPHA_STATE) return fail(HJ_ERR_UNSUPPORTED, "servers need the state-bound alpha");
   hj_server *S = new (std::nothrow) hj_server;
   if (!S) return fail(HJ_ERR_OUT_OF_MEMORY, "host allocation failed");
   S->d = *desc;

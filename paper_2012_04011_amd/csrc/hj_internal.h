@@ -173,6 +173,12 @@ int persistent_blocks_per_cu(int deriv, bool sg, bool ball);
 // sequence can be captured in a graph).
 hipError_t launch_batch_reset(BatchQueue *queue, int m, hipStream_t s);
 
+// ---- Algorithm 1's derivative range -----------------------------------------
+// keys[d] / keys[4 + d] = order-preserving keys of the smallest / largest
+// one-sided derivative (p- or p+) on axis d over every node of a.vs.
+template <typename T>
+hipError_t launch_deriv_range(const StageArgs<T> &a, int deriv, unsigned long long *keys, hipStream_t s);
+
 // ---- convergence mode ----------------------------------------------------
 // acc = max over i < n of |a[i] - b[i]| as the bit pattern of a non-negative
 // double (NaN counts as +inf); nothing when *skip.

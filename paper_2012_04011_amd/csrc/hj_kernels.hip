@@ -1178,6 +1178,87 @@ __global__ void batch_reset_kernel(BatchQueue *q, int m) {
 }
 
 // ---------------------------------------------------------------------------
+// Algorithm 1's derivative range: the smallest and largest one-sided
+// derivative per axis over the grid.  Doubles are compared through an
+// order-preserving 64-bit key (sign bit flipped for non-negative values,
+// all bits flipped for negative ones), so unsigned atomics give min and max.
+// ---------------------------------------------------------------------------
+
+__device__ inline unsigned long long order_key(double x) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+template <typename T, int DERIV>
+__global__ __launch_bounds__(256) void deriv_range_kernel(StageArgs<T> a, unsigned long long *keys) {
+  __shared__ unsigned long long part[8][4];
+  double lo[4], hi[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    lo[d] = INFINITY;
+    hi[d] = -INFINITY;
+  }
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npts; p += (int64_t)gridDim.x * blockDim.x) {
+    int idx[4];
+    int64_t q = p;
+    idx[3] = (int)(q % a.n[3]);
+    q /= a.n[3];
+    idx[2] = (int)(q % a.n[2]);
+    q /= a.n[2];
+    idx[1] = (int)(q % a.n[1]);
+    idx[0] = (int)(q / a.n[1]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      T w[5], pm, pp;
+      const bool per = (a.periodic_mask >> d) & 1u;
+      const int R = DERIV == kUpwind1 ? 1 : 2;
+#pragma unroll
+      for (int o = -2; o <= 2; ++o)
+        w[o + 2] = (o < -R || o > R) ? T(0) : axis_value(a.vs, p, idx[d], o, a.n[d], a.st[d], per);
+      one_sided<T, DERIV>(w, a.inv_h[d], pm, pp);
+      double x = (double)pm, y = (double)pp;
+      double mn = x < y ? x : y, mx = x < y ? y : x;
+      lo[d] = mn < lo[d] ? mn : lo[d];
+      hi[d] = mx > hi[d] ? mx : hi[d];
+    }
+  }
+  // block reduction in key space: min of the lows, max of the highs
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    unsigned long long kl = order_key(lo[d]), kh = order_key(hi[d]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      unsigned long long ol = __shfl_xor(kl, o, 64), oh = __shfl_xor(kh, o, 64);
+      kl = ol < kl ? ol : kl;
+      kh = oh > kh ? oh : kh;
+    }
+    if (lane == 0) {
+      part[d][wave] = kl;
+      part[4 + d][wave] = kh;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int d = threadIdx.x;
+    unsigned long long kl = part[d][0], kh = part[4 + d][0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      kl = part[d][w] < kl ? part[d][w] : kl;
+      kh = part[4 + d][w] > kh ? part[4 + d][w] : kh;
+    }
+    atomicMin(&keys[d], kl);
+    atomicMax(&keys[4 + d], kh);
+  }
+}
+
+__global__ void range_reset_kernel(unsigned long long *keys) {
+  if (threadIdx.x < 4) {
+    keys[threadIdx.x] = ~0ull;
+    keys[4 + threadIdx.x] = 0ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Convergence mode: the largest change of a step, and the stop test.
 // ---------------------------------------------------------------------------
 
@@ -1501,6 +1582,20 @@ template hipError_t launch_delta_max<double>(const double *, const double *, int
                                              const int32_t *, hipStream_t);
 template hipError_t launch_control<float>(const ControlArgs<float> &, hipStream_t);
 template hipError_t launch_control<double>(const ControlArgs<double> &, hipStream_t);
+template <typename T>
+hipError_t launch_deriv_range(const StageArgs<T> &a, int deriv, unsigned long long *keys, hipStream_t s) {
+  hipLaunchKernelGGL(range_reset_kernel, dim3(1), dim3(64), 0, s, keys);
+  int64_t blocks = (a.npts + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (deriv == kUpwind1)
+    hipLaunchKernelGGL((deriv_range_kernel<T, kUpwind1>), dim3((unsigned)blocks), dim3(256), 0, s, a, keys);
+  else
+    hipLaunchKernelGGL((deriv_range_kernel<T, kEno2>), dim3((unsigned)blocks), dim3(256), 0, s, a, keys);
+  return hipGetLastError();
+}
+
+template hipError_t launch_deriv_range<float>(const StageArgs<float> &, int, unsigned long long *, hipStream_t);
+template hipError_t launch_deriv_range<double>(const StageArgs<double> &, int, unsigned long long *, hipStream_t);
 template hipError_t launch_stream<float>(const StreamArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_plane<float>(const StreamArgs<float> &, int, bool, hipStream_t);
 template hipError_t launch_plane<double>(const StreamArgs<double> &, int, bool, hipStream_t);

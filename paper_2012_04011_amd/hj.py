@@ -32,6 +32,7 @@ HJ_CLAMP_NONE, HJ_CLAMP_MIN_V0 = 0, 1
 HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
 HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
 HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT = 0, 1, 2
+HJ_ALPHA_STATE, HJ_ALPHA_DERIV_RANGE = 0, 1
 BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT}
 
 STATUS_NAMES = {0: "HJ_OK", 1: "HJ_ERR_INVALID_ARG", 2: "HJ_ERR_OUT_OF_MEMORY", 3: "HJ_ERR_DEVICE",
@@ -68,7 +69,8 @@ class hj_dynamics_desc(ctypes.Structure):
 
 class hj_scheme_desc(ctypes.Structure):
     _fields_ = [("deriv", ctypes.c_int32), ("integrator", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("clamp", ctypes.c_int32), ("cfl", ctypes.c_double)]
+                ("clamp", ctypes.c_int32), ("alpha_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("cfl", ctypes.c_double)]
 
 
 class hj_solve_info(ctypes.Structure):
@@ -224,6 +226,7 @@ def scheme_desc(scheme: dict, precision: str) -> hj_scheme_desc:
     s.integrator = _INTEG[scheme["integrator"]]
     s.precision = _PREC[precision]
     s.clamp = HJ_CLAMP_MIN_V0 if scheme.get("clamp", True) else HJ_CLAMP_NONE
+    s.alpha_mode = {"state": HJ_ALPHA_STATE, "deriv_range": HJ_ALPHA_DERIV_RANGE}[scheme.get("alpha", "state")]
     s.cfl = float(scheme.get("cfl", 0.8))
     return s
 

@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_sizes_match_the_header_layout():
     # int32[4] + pad to 8 + double[4] * 2 + uint32 (+ pad) = 88
     assert ctypes.sizeof(hj.hj_grid_desc) == 88
-    assert ctypes.sizeof(hj.hj_scheme_desc) == 24
+    assert ctypes.sizeof(hj.hj_scheme_desc) == 32
     assert ctypes.sizeof(hj.hj_solve_info) == 32
     assert ctypes.sizeof(hj.hj_dynamics_desc) == 112
 
@@ -170,5 +170,5 @@ def test_server_null_and_range_arguments(lib):
 
 
 def test_server_struct_layouts():
-    assert ctypes.sizeof(hj.hj_server_desc) == 48
+    assert ctypes.sizeof(hj.hj_server_desc) == 56
     assert ctypes.sizeof(hj.hj_server_stats) == 56
