@@ -101,7 +101,7 @@ hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream
 // The plane kernel: one block per (y row, x chunk) holds the whole
 // (v, theta) plane of the current x in LDS; it needs n[2] * n[3] / R <= 1024
 // runs and 2 n[2] n[3] values of LDS.  Uses blocks_per_chunk = n[1].
-constexpr int kPlaneMaxThreads = 1024;
+constexpr int kPlaneMaxThreads = 768;
 constexpr int kPlaneMaxLdsBytes = 64 * 1024;
 
 template <typename T>

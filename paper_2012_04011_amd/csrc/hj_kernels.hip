@@ -720,30 +720,39 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   constexpr int FR = DERIV == kEno2 ? 2 : 1;
   const int psz = nv * nth;  // values per LDS buffer
 
-  T vx0[R], vx1[R], dxm[R], qx0[R], mxm[R], pre[R];
+  // x ring: slot S[(P + k) & 3] holds V(X + k) at phase P = (X - x0) & 3
+  // (k = 0 .. FR, and the front of the next plane loading into the last);
+  // the rotating slots and the two-plane difference pairs need no register
+  // moves once the loop is unrolled by four.  D[i], Q[i], M[i]: the first
+  // difference V(X) - V(X-1), the second difference at X and the ENO choice
+  // between X-1 and X, for the current (i = P & 1) and next plane.
+  T S[4][R], D[2][R], Q[2][R], M[2][R];
   if (DERIV == kEno2) {
     T wm2[R], wm1[R];
     x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
     x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
-    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, vx0);
-    x_plane_b<T, R>(rs, x0 + 1, nx, perx, pb, oc, vx1);
+    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, S[0]);
+    x_plane_b<T, R>(rs, x0 + 1, nx, perx, pb, oc, S[1]);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      dxm[j] = vx0[j] - wm1[j];
-      T qm = second_diff(wm2[j], wm1[j], vx0[j]);
-      qx0[j] = second_diff(wm1[j], vx0[j], vx1[j]);
-      mxm[j] = choose(qm, qx0[j]);
+      D[0][j] = S[0][j] - wm1[j];
+      T qm = second_diff(wm2[j], wm1[j], S[0][j]);
+      Q[0][j] = second_diff(wm1[j], S[0][j], S[1][j]);
+      M[0][j] = choose(qm, Q[0][j]);
     }
   } else {
     T wm1[R];
     x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
-    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, vx0);
+    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, S[0]);
 #pragma unroll
-    for (int j = 0; j < R; ++j) dxm[j] = vx0[j] - wm1[j];
+    for (int j = 0; j < R; ++j) D[0][j] = S[0][j] - wm1[j];
   }
-  x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, pre);
+  x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, S[FR]);
 
-  for (int X = x0; X < x1; ++X) {
+  auto plane = [&](auto phase, const int X) {
+    constexpr int P = decltype(phase)::value;
+    constexpr int I0 = P & 3, I1 = (P + 1) & 3, IF = (P + FR) & 3, IL = (P + FR + 1) & 3;
+    constexpr int DC = P & 1, DN = (P + 1) & 1;
     const uint32_t sX = (uint32_t)X * pb;
     T *buf = lds + ((X - x0) & 1) * psz;
     // ---- global loads: y neighbours of this plane, then the next front
@@ -765,20 +774,15 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
         bload<T, R, kCacheStream>(rv0, oc, sX, t0);
       }
     }
-    T front[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) front[j] = pre[j];
     if (X + 1 < x1) {
       const int xf = X + 1 + FR;
       if (xf < nx)
-        bload<T, R>(rs, oc, (uint32_t)xf * pb, pre);
+        bload<T, R>(rs, oc, (uint32_t)xf * pb, S[IL]);
       else
-        x_plane_b<T, R>(rs, xf, nx, perx, pb, oc, pre);
+        x_plane_b<T, R>(rs, xf, nx, perx, pb, oc, S[IL]);
     }
     // ---- publish the centre run; c = V_X
-    T c[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) c[j] = vx0[j];
+    const T(&c)[R] = S[I0];
     if (active) {
       typedef typename VecT<T, R>::type V;
       V cv;
@@ -792,27 +796,20 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       L[j] = T(0);
       b2[j] = T(0);
     }
-    // ---- x: advance the ring (registers only, overlaps the barrier wait)
+    // ---- x from the ring (registers only, overlaps the barrier wait)
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       T pm, pp;
       if (DERIV == kEno2) {
-        T dxp = vx1[j] - vx0[j];
-        T qx1 = second_diff(vx0[j], vx1[j], front[j]);
-        T mxp = choose(qx0[j], qx1);
-        pm = dxm[j] + T(0.5) * mxm[j];
-        pp = dxp - T(0.5) * mxp;
-        dxm[j] = dxp;
-        qx0[j] = qx1;
-        mxm[j] = mxp;
-        vx0[j] = vx1[j];
-        vx1[j] = front[j];
+        D[DN][j] = S[I1][j] - S[I0][j];
+        Q[DN][j] = second_diff(S[I0][j], S[I1][j], S[IF][j]);
+        M[DN][j] = choose(Q[DC][j], Q[DN][j]);
+        pm = D[DC][j] + T(0.5) * M[DC][j];
+        pp = D[DN][j] - T(0.5) * M[DN][j];
       } else {
-        T dxp = front[j] - vx0[j];
-        pm = dxm[j];
-        pp = dxp;
-        dxm[j] = dxp;
-        vx0[j] = front[j];
+        D[DN][j] = S[IF][j] - S[I0][j];
+        pm = D[DC][j];
+        pp = D[DN][j];
       }
       accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
     }
@@ -891,6 +888,19 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
     }
     if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
+  };
+
+  // four planes per trip: every slot index above is a compile-time constant
+  int X = x0;
+  for (;;) {
+    if (X >= x1) break;
+    plane(std::integral_constant<int, 0>(), X++);
+    if (X >= x1) break;
+    plane(std::integral_constant<int, 1>(), X++);
+    if (X >= x1) break;
+    plane(std::integral_constant<int, 2>(), X++);
+    if (X >= x1) break;
+    plane(std::integral_constant<int, 3>(), X++);
   }
 }
 
