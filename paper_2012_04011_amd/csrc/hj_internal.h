@@ -99,7 +99,7 @@ template <typename T>
 hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s);
 
 // The plane kernel: one block per (y row, x chunk) holds the whole
-// (v, theta) plane of the current x in LDS; it needs n[2] * n[3] / R <= 1024
+// (v, theta) plane of the current x in LDS; it needs n[2] * n[3] / R <= 768
 // runs and 2 n[2] n[3] values of LDS.  Uses blocks_per_chunk = n[1].
 constexpr int kPlaneMaxThreads = 768;
 constexpr int kPlaneMaxLdsBytes = 64 * 1024;
