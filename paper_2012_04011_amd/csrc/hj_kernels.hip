@@ -61,6 +61,15 @@ __device__ inline T axis_value(const T *__restrict__ v, int64_t p, int i, int o,
 // Second difference Q_j = V_{j+1} - 2 V_j + V_{j-1}, evaluated as
 // (V_{j+1} - 2 V_j) + V_{j-1}: the doubling is exact, so fused or not this is
 // two roundings, and equal inputs give equal Q (and equal ENO choices).
+// A block-uniform element of a table that no thread writes during the
+// launch, read through the scalar data cache: its latency is then counted
+// apart from the vector loads in flight.
+template <typename T>
+__device__ inline T uniform_load(const T *p, int i) {
+  typedef const T __attribute__((address_space(4))) CT;
+  return ((CT *)p)[i];
+}
+
 template <typename T>
 __device__ inline T second_diff(T vm, T v0, T vp) {
   return (vp - T(2) * v0) + vm;
@@ -515,16 +524,15 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
     bload<T, R>(rs, oy[2], sX, yp1);
     if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
     // pointwise streams of this plane (V^n, V0): issued now, used at the end
-    T vn[R], t0[R];
+    // (the x-y table's value stays one register until the clamp: copying it
+    // into t0 here would make the wave wait for every load issued above)
+    T vn[R], t0[R], tv = T(0);
     if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
     if (a.clamp) {
-      if (a.v0xy) {
-        T tv = a.v0xy[X * ny + y];
-#pragma unroll
-        for (int j = 0; j < R; ++j) t0[j] = tv;
-      } else {
+      if (a.v0xy)
+        tv = a.v0xy[X * ny + y];
+      else
         bload<T, R, kCacheStream>(rv0, oc, sX, t0);
-      }
     }
     T front[R];
 #pragma unroll
@@ -621,8 +629,13 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
       for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
     }
     if (a.clamp) {
+      if (a.v0xy) {
 #pragma unroll
-      for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+        for (int j = 0; j < R; ++j) res[j] = tv < res[j] ? tv : res[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+      }
     }
     // a global (not buffer) store: with a register soffset the compiler puts
     // no wait state between a 128-bit buffer store and the next write of its
@@ -762,17 +775,13 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     bload<T, R>(rs, oy[2], sX, yp1);
     if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
     // pointwise streams of this plane (V^n, V0): issued now, used at the end
-    T vn[R], t0[R];
+    T vn[R], t0[R], tv = T(0);
     if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
     if (a.clamp) {
-      if (a.v0xy) {
-        // every run of the block shares (x, y): one scalar load per plane
-        T tv = a.v0xy[X * ny + y];
-#pragma unroll
-        for (int j = 0; j < R; ++j) t0[j] = tv;
-      } else {
+      if (a.v0xy)
+        tv = uniform_load(a.v0xy, X * ny + y);  // every run of the block shares (x, y)
+      else
         bload<T, R, kCacheStream>(rv0, oc, sX, t0);
-      }
     }
     if (X + 1 < x1) {
       const int xf = X + 1 + FR;
@@ -884,8 +893,13 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
     }
     if (a.clamp) {
+      if (a.v0xy) {
 #pragma unroll
-      for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+        for (int j = 0; j < R; ++j) res[j] = tv < res[j] ? tv : res[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+      }
     }
     if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
   };
