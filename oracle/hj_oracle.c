@@ -298,7 +298,8 @@ static double value_at(const hjo_grid *g, const double *V, const int64_t st[4], 
 /*
  * One-sided derivatives along axis d at one node.
  *   UPWIND1 (eq 5):  p- = (V_i - V_{i-1}) / h,  p+ = (V_{i+1} - V_i) / h.
- *   ENO2 (textbook): with Q_j = V_{j+1} - 2 V_j + V_{j-1},
+ *   ENO2 (textbook): with the undivided second difference in its
+ *   divided-difference form, Q_j = (V_{j+1} - V_j) - (V_j - V_{j-1}),
  *     p- = (V_i - V_{i-1}) / h + c- / (2h),  c- = the smaller-magnitude of
  *          Q_{i-1}, Q_i (ties pick Q_{i-1});
  *     p+ = (V_{i+1} - V_i) / h - c+ / (2h),  c+ = the smaller-magnitude of
@@ -317,13 +318,14 @@ static void one_sided(const hjo_grid *g, int deriv, const double *V, const int64
   }
   double w[5];
   for (int k = -2; k <= 2; ++k) w[k + 2] = value_at(g, V, st, p, idx, d, k);
-  double q_left = w[2] - 2.0 * w[1] + w[0];  /* Q_{i-1} */
-  double q_mid = w[3] - 2.0 * w[2] + w[1];   /* Q_i     */
-  double q_right = w[4] - 2.0 * w[3] + w[2]; /* Q_{i+1} */
+  double d0 = w[1] - w[0], d1 = w[2] - w[1], d2 = w[3] - w[2], d3 = w[4] - w[3];
+  double q_left = d1 - d0;  /* Q_{i-1} */
+  double q_mid = d2 - d1;   /* Q_i     */
+  double q_right = d3 - d2; /* Q_{i+1} */
   double c_minus = fabs(q_left) <= fabs(q_mid) ? q_left : q_mid;
   double c_plus = fabs(q_mid) <= fabs(q_right) ? q_mid : q_right;
-  *pm = (w[2] - w[1]) / h + c_minus / (2.0 * h);
-  *pp = (w[3] - w[2]) / h - c_plus / (2.0 * h);
+  *pm = d1 / h + c_minus / (2.0 * h);
+  *pp = d2 / h - c_plus / (2.0 * h);
 }
 
 /* Exported for tests: p- and p+ along axis d at every node. */

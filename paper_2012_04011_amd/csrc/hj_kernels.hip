@@ -70,10 +70,10 @@ __device__ inline T uniform_load(const T *p, int i) {
   return ((CT *)p)[i];
 }
 
-template <typename T>
-__device__ inline T second_diff(T vm, T v0, T vp) {
-  return (vp - T(2) * v0) + vm;
-}
+// ENO2 works with the undivided second difference at node i in its
+// divided-difference form: the first difference on the right minus the one
+// on the left, Q_i = (V_{i+1} - V_i) - (V_i - V_{i-1}).  Sweeps that already
+// hold the first differences pay one subtraction per Q.
 
 // One-sided derivatives from the window w[0..4] = V_{i-2..i+2} (upwind uses
 // w[1..3]).  ENO2: the second-order correction takes the smaller-magnitude
@@ -84,13 +84,12 @@ __device__ inline void one_sided(const T (&w)[5], T inv_h, T &pm, T &pp) {
     pm = (w[2] - w[1]) * inv_h;
     pp = (w[3] - w[2]) * inv_h;
   } else {
-    T ql = second_diff(w[0], w[1], w[2]);
-    T qm = second_diff(w[1], w[2], w[3]);
-    T qr = second_diff(w[2], w[3], w[4]);
+    T d0 = w[1] - w[0], d1 = w[2] - w[1], d2 = w[3] - w[2], d3 = w[4] - w[3];
+    T ql = d1 - d0, qm = d2 - d1, qr = d3 - d2;
     T cm = tabs(ql) <= tabs(qm) ? ql : qm;
     T cp = tabs(qm) <= tabs(qr) ? qm : qr;
-    pm = ((w[2] - w[1]) + T(0.5) * cm) * inv_h;
-    pp = ((w[3] - w[2]) - T(0.5) * cp) * inv_h;
+    pm = (d1 + T(0.5) * cm) * inv_h;
+    pp = (d2 - T(0.5) * cp) * inv_h;
   }
 }
 
@@ -249,11 +248,10 @@ __device__ inline void window_diffs(T w0, T w1, T w2, T w3, T w4, T &pm, T &pp) 
     pm = w2 - w1;
     pp = w3 - w2;
   } else {
-    T ql = second_diff(w0, w1, w2);
-    T qm = second_diff(w1, w2, w3);
-    T qr = second_diff(w2, w3, w4);
-    pm = (w2 - w1) + T(0.5) * choose(ql, qm);
-    pp = (w3 - w2) - T(0.5) * choose(qm, qr);
+    T d0 = w1 - w0, d1 = w2 - w1, d2 = w3 - w2, d3 = w4 - w3;
+    T ql = d1 - d0, qm = d2 - d1, qr = d3 - d2;
+    pm = d1 + T(0.5) * choose(ql, qm);
+    pp = d2 - T(0.5) * choose(qm, qr);
   }
 }
 
@@ -478,7 +476,7 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
   constexpr int FR = DERIV == kEno2 ? 2 : 1;  // the x front is plane X + FR
 
   // x ring (see the description above) and the prefetched front
-  T vx0[R], vx1[R], dxm[R], qx0[R], mxm[R], pre[R];
+  T vx0[R], vx1[R], dxm[R], dxp[R], qx0[R], mxm[R], pre[R];
   if (DERIV == kEno2) {
     T wm2[R], wm1[R];
     x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
@@ -488,8 +486,9 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       dxm[j] = vx0[j] - wm1[j];
-      T qm = second_diff(wm2[j], wm1[j], vx0[j]);
-      qx0[j] = second_diff(wm1[j], vx0[j], vx1[j]);
+      dxp[j] = vx1[j] - vx0[j];
+      T qm = dxm[j] - (wm1[j] - wm2[j]);
+      qx0[j] = dxp[j] - dxm[j];
       mxm[j] = choose(qm, qx0[j]);
     }
   } else {
@@ -557,21 +556,22 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
       T pm, pp;
       c[j] = vx0[j];
       if (DERIV == kEno2) {
-        T dxp = vx1[j] - vx0[j];
-        T qx1 = second_diff(vx0[j], vx1[j], front[j]);
+        T dnn = front[j] - vx1[j];
+        T qx1 = dnn - dxp[j];
         T mxp = choose(qx0[j], qx1);
         pm = dxm[j] + T(0.5) * mxm[j];
-        pp = dxp - T(0.5) * mxp;
-        dxm[j] = dxp;
+        pp = dxp[j] - T(0.5) * mxp;
+        dxm[j] = dxp[j];
+        dxp[j] = dnn;
         qx0[j] = qx1;
         mxm[j] = mxp;
         vx0[j] = vx1[j];
         vx1[j] = front[j];
       } else {
-        T dxp = front[j] - vx0[j];
+        T dn = front[j] - vx0[j];
         pm = dxm[j];
-        pp = dxp;
-        dxm[j] = dxp;
+        pp = dn;
+        dxm[j] = dn;
         vx0[j] = front[j];
       }
       accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
@@ -580,23 +580,25 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
 #pragma unroll
     for (int j = 0; j < R; ++j) u[j + 2] = c[j];
     {
-      T dprev = u[2] - u[1];
+      // e[k] = u[k+1] - u[k]; the second difference at u[k] is e[k] - e[k-1]
+      T e[R + 3];
+#pragma unroll
+      for (int k = 0; k < R + 3; ++k)
+        if (DERIV == kEno2 || (k >= 1 && k <= R + 1)) e[k] = u[k + 1] - u[k];  // upwind: no outer halo
       T mprev = T(0);
-      if (DERIV == kEno2) mprev = choose(second_diff(u[0], u[1], u[2]), second_diff(u[1], u[2], u[3]));
+      if (DERIV == kEno2) mprev = choose(e[1] - e[0], e[2] - e[1]);
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        T dnext = u[j + 3] - u[j + 2];
         T pm, pp;
         if (DERIV == kEno2) {
-          T mnext = choose(second_diff(u[j + 1], u[j + 2], u[j + 3]), second_diff(u[j + 2], u[j + 3], u[j + 4]));
-          pm = dprev + T(0.5) * mprev;
-          pp = dnext - T(0.5) * mnext;
+          T mnext = choose(e[j + 2] - e[j + 1], e[j + 3] - e[j + 2]);
+          pm = e[j + 1] + T(0.5) * mprev;
+          pp = e[j + 2] - T(0.5) * mnext;
           mprev = mnext;
         } else {
-          pm = dprev;
-          pp = dnext;
+          pm = e[j + 1];
+          pp = e[j + 2];
         }
-        dprev = dnext;
         accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
       }
     }
@@ -735,11 +737,12 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
 
   // x ring: slot S[(P + k) & 3] holds V(X + k) at phase P = (X - x0) & 3
   // (k = 0 .. FR, and the front of the next plane loading into the last);
-  // the rotating slots and the two-plane difference pairs need no register
-  // moves once the loop is unrolled by four.  D[i], Q[i], M[i]: the first
-  // difference V(X) - V(X-1), the second difference at X and the ENO choice
-  // between X-1 and X, for the current (i = P & 1) and next plane.
-  T S[4][R], D[2][R], Q[2][R], M[2][R];
+  // the rotating slots and the difference pairs need no register moves once
+  // the loop is unrolled by four.  D[(P + k) & 3] = V(X + k) - V(X + k - 1)
+  // for k = 0, 1 (and 2 once computed); Q[i], M[i]: the second difference at
+  // X and the ENO choice between X-1 and X, for the current (i = P & 1) and
+  // next plane.
+  T S[4][R], D[4][R], Q[2][R], M[2][R];
   if (DERIV == kEno2) {
     T wm2[R], wm1[R];
     x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
@@ -749,8 +752,9 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       D[0][j] = S[0][j] - wm1[j];
-      T qm = second_diff(wm2[j], wm1[j], S[0][j]);
-      Q[0][j] = second_diff(wm1[j], S[0][j], S[1][j]);
+      D[1][j] = S[1][j] - S[0][j];
+      T qm = D[0][j] - (wm1[j] - wm2[j]);
+      Q[0][j] = D[1][j] - D[0][j];
       M[0][j] = choose(qm, Q[0][j]);
     }
   } else {
@@ -810,15 +814,15 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     for (int j = 0; j < R; ++j) {
       T pm, pp;
       if (DERIV == kEno2) {
-        D[DN][j] = S[I1][j] - S[I0][j];
-        Q[DN][j] = second_diff(S[I0][j], S[I1][j], S[IF][j]);
+        D[(P + 2) & 3][j] = S[IF][j] - S[I1][j];
+        Q[DN][j] = D[(P + 2) & 3][j] - D[(P + 1) & 3][j];
         M[DN][j] = choose(Q[DC][j], Q[DN][j]);
-        pm = D[DC][j] + T(0.5) * M[DC][j];
-        pp = D[DN][j] - T(0.5) * M[DN][j];
+        pm = D[P & 3][j] + T(0.5) * M[DC][j];
+        pp = D[(P + 1) & 3][j] - T(0.5) * M[DN][j];
       } else {
-        D[DN][j] = S[IF][j] - S[I0][j];
-        pm = D[DC][j];
-        pp = D[DN][j];
+        D[(P + 1) & 3][j] = S[IF][j] - S[I0][j];
+        pm = D[P & 3][j];
+        pp = D[(P + 1) & 3][j];
       }
       accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
     }
@@ -837,23 +841,25 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       }
 #pragma unroll
       for (int j = 0; j < R; ++j) u[j + 2] = c[j];
-      T dprev = u[2] - u[1];
+      // e[k] = u[k+1] - u[k]; the second difference at u[k] is e[k] - e[k-1]
+      T e[R + 3];
+#pragma unroll
+      for (int k = 0; k < R + 3; ++k)
+        if (DERIV == kEno2 || (k >= 1 && k <= R + 1)) e[k] = u[k + 1] - u[k];  // upwind: no outer halo
       T mprev = T(0);
-      if (DERIV == kEno2) mprev = choose(second_diff(u[0], u[1], u[2]), second_diff(u[1], u[2], u[3]));
+      if (DERIV == kEno2) mprev = choose(e[1] - e[0], e[2] - e[1]);
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        T dnext = u[j + 3] - u[j + 2];
         T pm, pp;
         if (DERIV == kEno2) {
-          T mnext = choose(second_diff(u[j + 1], u[j + 2], u[j + 3]), second_diff(u[j + 2], u[j + 3], u[j + 4]));
-          pm = dprev + T(0.5) * mprev;
-          pp = dnext - T(0.5) * mnext;
+          T mnext = choose(e[j + 2] - e[j + 1], e[j + 3] - e[j + 2]);
+          pm = e[j + 1] + T(0.5) * mprev;
+          pp = e[j + 2] - T(0.5) * mnext;
           mprev = mnext;
         } else {
-          pm = dprev;
-          pp = dnext;
+          pm = e[j + 1];
+          pp = e[j + 2];
         }
-        dprev = dnext;
         accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
       }
     }
