@@ -270,33 +270,6 @@ __device__ inline void accumulate(T &L, T &b2, T kp, T km, T sg, T pp, T pm, boo
   }
 }
 
-// Ghost values of a non-periodic axis from the loaded window (neighbour runs
-// at -2, -1, +1, +2 were loaded with clamped indices): linear extrapolation
-// from the two end nodes, ghost k layers out = V_end + k (V_end - V_next).
-template <typename T, int DERIV>
-__device__ inline void fix_ghosts(int i, int n, T c, T &m2, T &m1, T &p1, T &p2) {
-  if (i < 2) {
-    if (i == 0) {
-      T d = c - p1;
-      m1 = c + d;
-      if (DERIV == kEno2) m2 = c + T(2) * d;
-    } else if (DERIV == kEno2) {
-      T d = m1 - c;
-      m2 = m1 + d;
-    }
-  }
-  if (i >= n - 2) {
-    if (i == n - 1) {
-      T d = c - m1;
-      p1 = c + d;
-      if (DERIV == kEno2) p2 = c + T(2) * d;
-    } else if (DERIV == kEno2) {
-      T d = p1 - c;
-      p2 = p1 + d;
-    }
-  }
-}
-
 __device__ inline int wrap_or_clamp(int i, int n, bool periodic) {
   if (periodic) return i < 0 ? i + n : (i >= n ? i - n : i);
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
@@ -411,11 +384,24 @@ __device__ inline void x_plane_b(__amdgpu_buffer_rsrc_t rs, int xi, int nx, bool
   }
 }
 
-// Ghost fix-up of one open axis for a whole run (see fix_ghosts).
-template <typename T, int R, int DERIV>
-__device__ inline void fix_run(int i, int n, const T (&c)[R], T (&m2)[R], T (&m1)[R], T (&p1)[R], T (&p2)[R]) {
-#pragma unroll
-  for (int j = 0; j < R; ++j) fix_ghosts<T, DERIV>(i, n, c[j], m2[j], m1[j], p1[j], p2[j]);
+// One-sided differences at the nodes next to the ends of an open axis,
+// straight from the interior values.  With ghosts extrapolated linearly
+// (ghost k layers out = V_end + k (V_end - V_next)), every first difference
+// beyond an end equals the last one inside it and the second differences
+// there vanish, so the ENO correction on the ghost side is zero and (ENO2
+// and upwind alike)
+//   i = 0:      h p- = h p+ = V_1 - V_0
+//   i = 1:      h p-        = V_1 - V_0
+//   i = n - 2:        h p+  = V_{n-1} - V_{n-2}
+//   i = n - 1:  h p- = h p+ = V_{n-1} - V_{n-2}.
+// This equals the ghost-layer evaluation up to its rounding (a few units in
+// the last place of V); the windows of these nodes were loaded with clamped
+// indices, and pm, pp computed from them are replaced here.
+template <typename T>
+__device__ inline void edge_diffs(int i, int n, T m1, T c, T p1, T &pm, T &pp) {
+  const T dl = c - m1, dr = p1 - c;
+  pm = i == 0 ? dr : ((i == 1 || i == n - 1) ? dl : pm);
+  pp = i == n - 1 ? dl : ((i == 0 || i == n - 2) ? dr : pp);
 }
 
 // One tile of the streaming kernel: logical block lb of the launch that `a`
@@ -603,19 +589,19 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
       }
     }
     // ---- v
-    if (vedge) fix_run<T, R, DERIV>(v, nv, c, vn2, vn1, vp1, vp2);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       T pm, pp;
       window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pm, pp);
+      if (vedge) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pm, pp);
       accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
     }
     // ---- y
-    if (yedge) fix_run<T, R, DERIV>(y, ny, c, yn2, yn1, yp1, yp2);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       T pm, pp;
       window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pm, pp);
+      if (yedge) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pm, pp);
       accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
     }
     // ---- update
@@ -870,20 +856,20 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       lds_run<T, R>(buf + lv[1], vn1);
       lds_run<T, R>(buf + lv[2], vp1);
       if (DERIV == kEno2) lds_run<T, R>(buf + lv[3], vp2);
-      if (vedge) fix_run<T, R, DERIV>(v, nv, c, vn2, vn1, vp1, vp2);
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         T pm, pp;
         window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pm, pp);
+        if (vedge) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pm, pp);
         accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
       }
     }
     // ---- y: neighbours from global memory
-    if (yedge) fix_run<T, R, DERIV>(y, ny, c, yn2, yn1, yp1, yp2);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       T pm, pp;
       window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pm, pp);
+      if (yedge) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pm, pp);
       accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
     }
     // ---- update
