@@ -394,6 +394,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--workload", choices=["large120", "batch64", "serve"], default="large120")
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32",
+                    help="large120: arithmetic of the solve (the headline is FP32)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
     ap.add_argument("--hbm-budget", type=int, default=8 << 30, help="serve: slot memory budget in bytes")
     ap.add_argument("--summarize-traffic", metavar="DIR")
@@ -423,8 +425,9 @@ def main() -> int:
     hj.load_library()
     torch.cuda.set_device(0)
     wl = W.LARGE_120
+    prec = args.precision
     stream = torch.cuda.current_stream()
-    g = hj.Grid(wl.grid, wl.dyn, wl.scheme, wl.precision, stream)
+    g = hj.Grid(wl.grid, wl.dyn, wl.scheme, prec, stream)
     npts = g.num_points
     obstacle_sets = [W.cylinders(s, wl.obstacles) for s in range(args.warmup + args.steps)]
 
@@ -455,7 +458,7 @@ def main() -> int:
     bpl = algorithmic_bytes_per_launch(npts, launch, wl.scheme["integrator"])
     avg_launch_s = prof["loop_ms"] / 1e3 / prof["step_launches"]
     achieved = bpl / avg_launch_s / 1e9
-    traffic = measured_traffic(npts)
+    traffic = measured_traffic(npts) if prec == "f32" else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -467,10 +470,10 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": prec,
         "data": "synthetic (seeded cylinder obstacles)",
         "config": {
-            "workload": "car4d 120x120x40x72 (41.5M points) ENO2+TVD-RK2 FP32, horizon 2 s, 8 cylinders",
+            "workload": f"car4d 120x120x40x72 (41.5M points) ENO2+TVD-RK2 {prec.upper()}, horizon 2 s, 8 cylinders",
             "grid": list(wl.grid["n"]),
             "points": npts,
             "scheme": "eno2+rk2",

@@ -255,11 +255,14 @@ hj_status hj_optimal_control(hj_grid *g, const double *states, int64_t m, int32_
  * then by hj_autotune).  x_chunks: how many pieces each x sweep is split
  * into.  target_xy: 1 if the target is constant over (v, theta) (set by
  * hj_set_target_cylinders) and the clamp reads an Nx*Ny table instead of
- * the 4D V0.  bytes_per_point_step: algorithmic HBM bytes one full step moves
- * per grid node in this mode (each array read once and written once per
- * stage). */
+ * the 4D V0.  plane_segments: with the plane kernel, how many blocks share
+ * one (v, theta) plane (split along v when it has more than 768 runs of
+ * theta nodes); 0 with the other kernels.  bytes_per_point_step: algorithmic
+ * HBM bytes one full step moves per grid node in this mode (each array read
+ * once and written once per stage). */
 typedef struct {
   int32_t kernel, x_chunks, target_xy, autotuned;
+  int32_t plane_segments, reserved;
   double bytes_per_point_step;
 } hj_launch_info;
 

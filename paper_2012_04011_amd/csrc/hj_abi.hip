@@ -66,6 +66,7 @@ struct hj_grid {
   // stage kernel: 2 = plane (LDS), 1 = streaming, 0 = generic
   int kernel = 0;
   int x_chunks = 1;
+  int v_seg = 0, n_seg = 1;  // plane kernel: v rows per block, v segments
   bool plane_ok = false, stream_ok = false;
   bool launch_fixed = false;   // kernel / chunks forced by the environment
   bool autotune_on = true, autotuned = false;
@@ -528,7 +529,10 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   a.run = run;
   a.runs_per_row = g.n[3] / run;
   a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
-  a.blocks_per_chunk = G->kernel == 2 ? g.n[1] : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  a.blocks_per_chunk =
+      G->kernel == 2 ? g.n[1] * G->n_seg : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  a.v_seg = G->v_seg;
+  a.n_seg = G->n_seg;
   a.n_chunks = G->x_chunks;
   a.chunk_len = (g.n[0] + a.n_chunks - 1) / a.n_chunks;
   a.n_chunks = (g.n[0] + a.chunk_len - 1) / a.chunk_len;
@@ -849,9 +853,26 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     // theta periodic; 32-bit byte offsets (buffer addressing) need each
     // array below 4 GiB
     bool stream_ok = bit(grid->periodic_mask, 3) && G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
-    int64_t plane_runs = (int64_t)grid->n[2] * (grid->n[3] / run);
-    bool plane_ok = stream_ok && plane_runs <= hj::kPlaneMaxThreads &&
-                    2 * (int64_t)grid->n[2] * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
+    const int rpr = grid->n[3] / run, nv = grid->n[2];
+    int64_t plane_runs = (int64_t)nv * rpr;
+    // The plane kernel holds the whole (v, theta) plane in one block when it
+    // has at most kPlaneMaxThreads runs, else the fewest v segments that fit
+    // (HJ_PLANE_VSEG caps the rows per block, to exercise the split).
+    int max_rows = hj::kPlaneMaxThreads / rpr;
+    const char *vseg_env = getenv("HJ_PLANE_VSEG");
+    if (vseg_env && atoi(vseg_env) > 0 && atoi(vseg_env) < max_rows) max_rows = atoi(vseg_env);
+    int n_seg = 1, v_seg = nv;
+    if (max_rows > 0 && nv > max_rows) {
+      n_seg = (nv + max_rows - 1) / max_rows;
+      v_seg = (nv + n_seg - 1) / n_seg;
+      n_seg = (nv + v_seg - 1) / v_seg;
+    }
+    const int64_t lds_rows = n_seg > 1 ? v_seg + 4 : nv;
+    bool plane_ok = stream_ok && max_rows > 0 && (n_seg == 1 || v_seg >= hj::kPlaneMinSegRows) &&
+                    2 * lds_rows * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
+    (void)plane_runs;
+    G->v_seg = v_seg;
+    G->n_seg = plane_ok ? n_seg : 1;
     G->plane_ok = plane_ok;
     G->stream_ok = stream_ok;
     G->kernel = plane_ok ? 2 : (stream_ok ? 1 : 0);
@@ -863,7 +884,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     }
     if (getenv("HJ_X_CHUNKS")) G->launch_fixed = true;
     int64_t slab_runs = (int64_t)grid->n[1] * plane_runs;
-    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1], slab_runs, G->kernel == 2);
+    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * G->n_seg, slab_runs, G->kernel == 2);
   }
   hipError_t e = hipGetDevice(&G->device);
   size_t bytes = G->npts * G->elem;
@@ -1299,6 +1320,8 @@ hj_status hj_get_launch_info(hj_grid *G, hj_launch_info *out) {
   out->x_chunks = G->x_chunks;
   out->target_xy = G->target_xy && G->kernel > 0;
   out->autotuned = G->autotuned;
+  out->plane_segments = G->kernel == 2 ? G->n_seg : 0;
+  out->reserved = 0;
   // arrays per stage: read the stencil input, write the output; stage 2 of
   // TVD-RK2 also reads V^n; the clamp reads V0 unless it is the xy table
   double arrays;

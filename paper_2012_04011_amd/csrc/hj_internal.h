@@ -72,6 +72,8 @@ struct StreamArgs {
   int32_t blocks_per_chunk;
   int32_t chunk_len;       // x planes per block
   int32_t n_chunks;
+  int32_t v_seg;     // plane kernel: v rows per block (n[2] unless the plane is split)
+  int32_t n_seg;     // plane kernel: v segments (1: the whole plane in one block)
   const T *coef_th;  // kp_theta | km_theta | sg_theta, each n[2] values (per v)
   T kp_v, km_v;
   T sg[4];
@@ -100,9 +102,13 @@ hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream
 
 // The plane kernel: one block per (y row, x chunk) holds the whole
 // (v, theta) plane of the current x in LDS; it needs n[2] * n[3] / R <= 768
-// runs and 2 n[2] n[3] values of LDS.  Uses blocks_per_chunk = n[1].
+// runs and 2 n[2] n[3] values of LDS.  A larger plane is split along v into
+// n_seg segments of v_seg rows (v_seg * n[3] / R <= 768 runs), each block
+// holding its segment and two halo rows per side: 2 (v_seg + 4) n[3] values.
+// blocks_per_chunk = n[1] * n_seg (segment-major, y fastest).
 constexpr int kPlaneMaxThreads = 768;
 constexpr int kPlaneMaxLdsBytes = 64 * 1024;
+constexpr int kPlaneMinSegRows = 4;  // a split plane keeps at least this many rows per block
 
 template <typename T>
 hipError_t launch_plane(const StreamArgs<T> &a, int deriv, bool ball, hipStream_t s);

@@ -663,7 +663,11 @@ __device__ inline void lds_pair(const T *p, T &a, T &b) {
   b = x[1];
 }
 
-template <typename T, int R, int DERIV, bool SG, bool BALL>
+// SEG: the block holds one v segment [va, va + v_seg) of the plane plus two
+// halo rows on each side (copied from global memory by the first 4 * rpr
+// threads, one plane ahead), for planes with more runs than a block has
+// threads.
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG>
 __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
   if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -671,17 +675,23 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   constexpr uint32_t E = sizeof(T);
   const int nx = a.n[0], ny = a.n[1], nv = a.n[2], nth = a.n[3];
   const int rpr = a.runs_per_row;
-  const int runs = nv * rpr;  // runs of one (v, theta) plane
   const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
-  const int chunk = lb / ny;
-  const int y = lb - chunk * ny;
+  const int chunk = lb / a.blocks_per_chunk;
+  const int rem = lb - chunk * a.blocks_per_chunk;  // segment-major, y fastest
+  const int seg = SEG ? rem / ny : 0;
+  const int y = SEG ? rem - seg * ny : rem;
+  const int va = seg * a.v_seg;                            // first v of the segment
+  const int nvs = SEG ? min(a.v_seg, nv - va) : nv;        // its rows
+  const int vbase = SEG ? va - 2 : 0;                      // v of LDS row 0
+  const int runs = nvs * rpr;                              // runs of the block
   const bool active = (int)threadIdx.x < runs;
   const int r = active ? (int)threadIdx.x : runs - 1;  // idle lanes shadow the last run
   const bool perx = a.periodic_mask & 1u, pery = (a.periodic_mask >> 1) & 1u, perv = (a.periodic_mask >> 2) & 1u;
   const int t = r % rpr;
-  const int v = r / rpr;
+  const int v = va + r / rpr;
   const int th0 = t * R;
-  const int pl = v * nth + th0;  // offset inside the (v, theta) plane
+  const int pl = v * nth + th0;             // offset inside the (v, theta) plane
+  const int pll = (v - vbase) * nth + th0;  // the same inside the LDS copy
   const int offe = y * nv * nth + pl;
   const uint32_t oc = (uint32_t)offe * E;
   uint32_t oy[4];
@@ -691,11 +701,13 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
-      lv[k] = wrap_or_clamp(v + o[k], nv, perv) * nth + th0;
+      // a segment's halo rows hold v - 2 .. v + 2 unwrapped on a periodic v
+      const int vk = (SEG && perv) ? v + o[k] : wrap_or_clamp(v + o[k], nv, perv);
+      lv[k] = (vk - vbase) * nth + th0;
     }
   }
   uint32_t lh[4];  // theta halos inside the LDS plane (see the streaming kernel)
-  theta_halo_offsets<R>(v * nth, th0, nth, lh);
+  theta_halo_offsets<R>((v - vbase) * nth, th0, nth, lh);
   const bool vedge = !perv && (v < 2 || v >= nv - 2);
   const bool yedge = !pery && (y < 2 || y >= ny - 2);
   // theta-axis coefficients of this thread's v (see StreamArgs::coef_th)
@@ -719,7 +731,22 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   const int x0 = chunk * a.chunk_len;
   const int x1 = min(nx, x0 + a.chunk_len);
   constexpr int FR = DERIV == kEno2 ? 2 : 1;
-  const int psz = nv * nth;  // values per LDS buffer
+  const int psz = (SEG ? a.v_seg + 4 : nv) * nth;  // values per LDS buffer
+  // SEG halo rows va-2, va-1, va+nvs, va+nvs+1 (those that exist): thread
+  // h < 4 rpr copies run h % rpr of row h / rpr, loading it one plane ahead
+  bool hcopy = false;
+  uint32_t hoff = 0;
+  int hl = 0;
+  T H[R];
+  if constexpr (SEG) {
+    const int h = (int)threadIdx.x, hk = h / rpr, ht = h - hk * rpr;
+    const int hv = hk < 2 ? va - 2 + hk : va + nvs + (hk - 2);
+    hcopy = h < 4 * rpr && (perv || (hv >= 0 && hv < nv));
+    const int hw = hv < 0 ? hv + nv : (hv >= nv ? hv - nv : hv);
+    hoff = (uint32_t)((y * nv + (hcopy ? hw : 0)) * nth + ht * R) * E;
+    hl = (hv - vbase) * nth + ht * R;
+    if (hcopy) bload<T, R>(rs, hoff, (uint32_t)x0 * pb, H);
+  }
 
   // x ring: slot S[(P + k) & 3] holds V(X + k) at phase P = (X - x0) & 3
   // (k = 0 .. FR, and the front of the next plane loading into the last);
@@ -787,7 +814,17 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       V cv;
 #pragma unroll
       for (int j = 0; j < R; ++j) cv[j] = c[j];
-      *reinterpret_cast<V *>(buf + pl) = cv;
+      *reinterpret_cast<V *>(buf + pll) = cv;
+    }
+    if constexpr (SEG) {
+      if (hcopy) {
+        typedef typename VecT<T, R>::type V;
+        V hv;
+#pragma unroll
+        for (int j = 0; j < R; ++j) hv[j] = H[j];
+        *reinterpret_cast<V *>(buf + hl) = hv;
+        if (X + 1 < x1) bload<T, R>(rs, hoff, sX + pb, H);
+      }
     }
     T L[R], b2[R];
 #pragma unroll
@@ -1038,11 +1075,21 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
 
 template <typename T, int R, int DERIV, bool SG, bool BALL>
 hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
-  int runs = a.n[2] * a.runs_per_row;
-  int threads = (runs + 63) / 64 * 64;
-  size_t lds = 2 * (size_t)a.n[2] * a.n[3] * sizeof(T);
-  unsigned blocks = (unsigned)(a.n[1] * a.n_chunks);
-  hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL>), dim3(blocks), dim3(threads), lds, s, a);
+  const bool seg = a.n_seg > 1;
+  const int rows = seg ? a.v_seg : a.n[2];
+  const int runs = rows * a.runs_per_row;
+  if (runs > kPlaneMaxThreads || a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1) ||
+      (seg && (a.v_seg < kPlaneMinSegRows || (int64_t)a.v_seg * a.n_seg < a.n[2] ||
+               (int64_t)a.v_seg * (a.n_seg - 1) >= a.n[2])))
+    return hipErrorInvalidValue;
+  const int threads = (runs + 63) / 64 * 64;
+  const size_t lds = 2 * (size_t)(seg ? a.v_seg + 4 : a.n[2]) * a.n[3] * sizeof(T);
+  if (lds > (size_t)kPlaneMaxLdsBytes) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)(a.blocks_per_chunk * a.n_chunks);
+  if (seg)
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, true>), dim3(blocks), dim3(threads), lds, s, a);
+  else
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, false>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 

@@ -80,7 +80,8 @@ class hj_solve_info(ctypes.Structure):
 
 class hj_launch_info(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("x_chunks", ctypes.c_int32), ("target_xy", ctypes.c_int32),
-                ("autotuned", ctypes.c_int32), ("bytes_per_point_step", ctypes.c_double)]
+                ("autotuned", ctypes.c_int32), ("plane_segments", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bytes_per_point_step", ctypes.c_double)]
 
 
 KERNEL_NAMES = {0: "generic", 1: "stream", 2: "plane"}
@@ -351,7 +352,8 @@ def hj_get_launch_info(h: int) -> dict:
     li = hj_launch_info()
     _check(load_library().hj_get_launch_info(h, ctypes.byref(li)), "hj_get_launch_info")
     return {"kernel": KERNEL_NAMES.get(li.kernel, li.kernel), "x_chunks": li.x_chunks, "target_xy": bool(li.target_xy),
-            "autotuned": bool(li.autotuned), "bytes_per_point_step": li.bytes_per_point_step}
+            "autotuned": bool(li.autotuned), "plane_segments": li.plane_segments,
+            "bytes_per_point_step": li.bytes_per_point_step}
 
 
 def hj_autotune(h: int) -> None:
