@@ -340,14 +340,22 @@ hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);
  * The paper's use is a robot re-solving its BRT whenever the obstacle map
  * changes (section "Hardware Correctness": V0 handed to the solver, the BRT
  * read back).  A server keeps grids resident on the device ("slots": the
- * handle's arrays, table and CFL step) and steps every admitted request
- * together: each tick admits queued requests (first in, first out) while
- * fewer than max_inflight run and a slot is free or the budget allows a new
- * one, then advances every running request by a few time steps: grids of
- * fewer than 4 Mi nodes share one launch per stage and step (each at its own
- * step), larger ones fill the device alone and step with their own tuned
- * stage kernel.  Every request restarts from its own
- * V0 and gets exactly the V of hj_solve_brt on a fresh handle (bitwise). */
+ * handle's arrays, table and CFL step).  Each tick admits queued requests
+ * (first in, first out) while fewer than max_inflight run and a slot is free
+ * or the budget allows a new one, then advances running requests by a few
+ * time steps.  Which ones, by `policy`:
+ *   HJ_SERVE_SMALL_FIRST: requests of fewer than 4 Mi nodes (too small to
+ *     fill the device alone) first, least remaining work (nodes times steps
+ *     left) first, then the larger ones in the order they were submitted;
+ *     requests are taken in that order until they hold 4 Mi nodes, the
+ *     others wait for a later tick;
+ *   HJ_SERVE_SHARE: every running request, every tick.
+ * Among the requests of a tick, grids of fewer than 4 Mi nodes share one
+ * launch per stage and step (each at its own step), larger ones fill the
+ * device alone and step with their own tuned stage kernel.  Every request
+ * restarts from its own V0 and gets exactly the V of hj_solve_brt on a fresh
+ * handle (bitwise), whatever the policy. */
+enum { HJ_SERVE_SMALL_FIRST = 0, HJ_SERVE_SHARE = 1 };
 typedef struct hj_server hj_server;
 
 typedef struct {
@@ -357,7 +365,7 @@ typedef struct {
   int32_t x_planes;      /* tile length in x planes (0 = cut x so each launch has ~1024 blocks) */
   int32_t steps_per_tick; /* time steps one tick enqueues for the running requests (0 = 4); at most
                            * two ticks are in flight, so new requests wait for <= 2 ticks */
-  int32_t reserved;      /* 0 */
+  int32_t policy;        /* HJ_SERVE_SMALL_FIRST or HJ_SERVE_SHARE */
 } hj_server_desc;
 
 typedef struct {

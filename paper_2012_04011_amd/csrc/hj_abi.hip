@@ -1433,6 +1433,7 @@ void batch_free(hj_batch *b) {
 constexpr int32_t kBatchDefaultXPlanes = 16;
 constexpr int64_t kServerBlocks = 1024;
 constexpr int64_t kServerAlonePoints = (int64_t)4 << 20;  // grids this large step on their own kernel
+constexpr int64_t kServerFillPoints = kServerAlonePoints;  // small-first: nodes that fill the device
 
 int32_t batch_x_planes(const hj_batch *b) { return b->x_planes > 0 ? b->x_planes : kBatchDefaultXPlanes; }
 
@@ -1998,14 +1999,31 @@ hj_status server_step_alone(hj_server *S, hj_server::Req &q, int64_t k) {
 
 template <typename T>
 hj_status server_step(hj_server *S) {
-  const int m = (int)S->running.size();
-  if (m == 0) return HJ_OK;
+  if (S->running.empty()) return HJ_OK;
   const int r = S->ring;
   S->ring = (r + 1) % hj_server::kRing;
   HJ_HIP(hipEventSynchronize(S->ring_ev[r]));  // this ring slot's previous launches are done
+  // the requests that step this tick: all of them (sharing), or, in the
+  // order small ones (least remaining work first) then large ones (first
+  // submitted first), as many as it takes to fill the device
+  std::vector<int64_t> sel(S->running), wait;
+  if (S->d.policy == HJ_SERVE_SMALL_FIRST) {
+    auto npts = [&](int64_t id) { return S->slots[S->reqs[id].slot].g->npts; };
+    auto key = [&](int64_t id) {
+      const hj_server::Req &q = S->reqs[id];
+      const bool large = npts(id) >= kServerFillPoints;
+      return std::make_pair(large ? 1 : 0, large ? id : npts(id) * (q.n - q.k));
+    };
+    std::stable_sort(sel.begin(), sel.end(), [&](int64_t x, int64_t y) { return key(x) < key(y); });
+    size_t take = 0;
+    for (int64_t pts = 0; take < sel.size() && pts < kServerFillPoints; ++take) pts += npts(sel[take]);
+    wait.assign(sel.begin() + take, sel.end());
+    sel.resize(take);
+  }
+  const int m = (int)sel.size();
   // longest remaining first, so the requests still stepping at step s of
   // this tick are a prefix of each group
-  std::stable_sort(S->running.begin(), S->running.end(), [&](int64_t x, int64_t y) {
+  std::stable_sort(sel.begin(), sel.end(), [&](int64_t x, int64_t y) {
     const hj_server::Req &a = S->reqs[x], &b = S->reqs[y];
     return a.n - a.k > b.n - b.k;
   });
@@ -2014,7 +2032,7 @@ hj_status server_step(hj_server *S) {
   // kernel; the others share one launch per stage and step
   std::vector<int> big, small;
   for (int i = 0; i < m; ++i) {
-    const hj_grid *G = S->slots[S->reqs[S->running[i]].slot].g;
+    const hj_grid *G = S->slots[S->reqs[sel[i]].slot].g;
     (G->npts >= kServerAlonePoints ? big : small).push_back(i);
   }
   hj::BatchInst<T> *inst = static_cast<hj::BatchInst<T> *>(S->inst_host[r]);
@@ -2023,7 +2041,7 @@ hj_status server_step(hj_server *S) {
   // requests has about kServerBlocks blocks
   int64_t row_blocks = 0;
   for (int i : small) {
-    const hj_grid *G = S->slots[S->reqs[S->running[i]].slot].g;
+    const hj_grid *G = S->slots[S->reqs[sel[i]].slot].g;
     int run = hj::run_length((int)sizeof(T), G->g.n[3]);
     row_blocks += ((int64_t)G->g.n[1] * G->g.n[2] * (G->g.n[3] / run) + hj::kStreamBlock - 1) / hj::kStreamBlock;
   }
@@ -2032,11 +2050,11 @@ hj_status server_step(hj_server *S) {
   int64_t acc = 0;
   std::vector<int64_t> remain(m);
   for (int i = 0; i < m; ++i) {
-    hj_server::Req &q = S->reqs[S->running[i]];
+    hj_server::Req &q = S->reqs[sel[i]];
     remain[i] = q.n - q.k;
   }
   for (size_t u = 0; u < small.size(); ++u) {
-    hj_server::Req &q = S->reqs[S->running[small[u]]];
+    hj_server::Req &q = S->reqs[sel[small[u]]];
     hj_grid *G = S->slots[q.slot].g;
     hj::BatchInst<T> &in = inst[u];
     memset(&in, 0, sizeof in);
@@ -2079,7 +2097,7 @@ hj_status server_step(hj_server *S) {
     // the launches enqueued so far have run
     for (int i = 0; i < m; ++i)
       if (remain[i] == s) {
-        hj_server::Req &q = S->reqs[S->running[i]];
+        hj_server::Req &q = S->reqs[sel[i]];
         hj_status st = server_event(S, &q.ev);
         if (st != HJ_OK) return st;
         HJ_HIP(hipEventRecord(q.ev, S->stream));
@@ -2090,7 +2108,7 @@ hj_status server_step(hj_server *S) {
                                  sg, ball, S->stream));
     for (int i : big)
       if (remain[i] > s) {
-        hj_server::Req &q = S->reqs[S->running[i]];
+        hj_server::Req &q = S->reqs[sel[i]];
         hj_status st = server_step_alone<T>(S, q, q.k + s);
         if (st != HJ_OK) return st;
       }
@@ -2099,7 +2117,7 @@ hj_status server_step(hj_server *S) {
   // advance; retire the requests that took their last step
   std::vector<int64_t> still;
   for (int i = 0; i < m; ++i) {
-    const int64_t id = S->running[i];
+    const int64_t id = sel[i];
     hj_server::Req &q = S->reqs[id];
     q.k += remain[i] < nsteps ? remain[i] : nsteps;
     if (q.k < q.n) {
@@ -2119,6 +2137,7 @@ hj_status server_step(hj_server *S) {
     }
     q.state = 2;
   }
+  still.insert(still.end(), wait.begin(), wait.end());
   S->running.swap(still);
   return HJ_OK;
 }
@@ -2160,6 +2179,8 @@ hj_status hj_server_create(const hj_server_desc *desc, void *hip_stream, hj_serv
     return fail(HJ_ERR_INVALID_ARG, "max_inflight must be 1..%d", hj::kMaxBatch);
   if (desc->hbm_budget < 0 || desc->x_planes < 0 || desc->steps_per_tick < 0)
     return fail(HJ_ERR_INVALID_ARG, "negative budget, tile or steps per tick");
+  if (desc->policy != HJ_SERVE_SMALL_FIRST && desc->policy != HJ_SERVE_SHARE)
+    return fail(HJ_ERR_INVALID_ARG, "unknown server policy %d", desc->policy);
   const hj_scheme_desc &sc = desc->scheme;
   if ((sc.deriv != HJ_UPWIND1 && sc.deriv != HJ_ENO2) || (sc.integrator != HJ_EULER && sc.integrator != HJ_TVD_RK2) ||
       (sc.precision != HJ_F32 && sc.precision != HJ_F64) || (sc.clamp != HJ_CLAMP_NONE && sc.clamp != HJ_CLAMP_MIN_V0) ||

@@ -640,11 +640,12 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // Plane kernel.  Block (y, x chunk) owns every run of the (v, theta) plane at
-// one y and sweeps the chunk's x planes.  Each thread keeps the x ring of its
-// run in registers; per plane it writes its centre run into a double-buffered
-// LDS copy of the plane, and after one barrier reads its theta halos and its
-// v neighbours from LDS.  Only the x front (prefetched one plane ahead) and
-// the four y-neighbour runs are global loads.
+// one y (or of one v segment of it, see SEG) and sweeps the chunk's x
+// planes.  Each thread keeps the x ring of its run in registers; per plane it
+// writes its centre run into a double-buffered LDS copy of the plane, and
+// after one barrier reads its theta halos and its v neighbours from LDS.
+// Only the x front (prefetched one plane ahead), the four y-neighbour runs
+// and the pointwise streams (V^n, V0) are global loads.
 // ---------------------------------------------------------------------------
 
 template <typename T, int R>

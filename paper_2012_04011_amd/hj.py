@@ -33,6 +33,8 @@ HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
 HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
 HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT = 0, 1, 2
 HJ_ALPHA_STATE, HJ_ALPHA_DERIV_RANGE = 0, 1
+HJ_SERVE_SMALL_FIRST, HJ_SERVE_SHARE = 0, 1
+SERVE_POLICIES = {"small_first": HJ_SERVE_SMALL_FIRST, "share": HJ_SERVE_SHARE}
 BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT}
 
 STATUS_NAMES = {0: "HJ_OK", 1: "HJ_ERR_INVALID_ARG", 2: "HJ_ERR_OUT_OF_MEMORY", 3: "HJ_ERR_DEVICE",
@@ -100,7 +102,7 @@ class hj_batch_info(ctypes.Structure):
 
 class hj_server_desc(ctypes.Structure):
     _fields_ = [("scheme", hj_scheme_desc), ("hbm_budget", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("x_planes", ctypes.c_int32), ("steps_per_tick", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("x_planes", ctypes.c_int32), ("steps_per_tick", ctypes.c_int32), ("policy", ctypes.c_int32)]
 
 
 class hj_server_stats(ctypes.Structure):
@@ -439,11 +441,12 @@ def hj_batch_get_info(b: int) -> dict:
 
 
 def hj_server_create(scheme: dict, precision: str = "f32", hbm_budget: int = 0, max_inflight: int = 64,
-                     x_planes: int = 0, stream=None, steps_per_tick: int = 0) -> int:
+                     x_planes: int = 0, stream=None, steps_per_tick: int = 0, policy: str = "small_first") -> int:
     d = hj_server_desc()
     d.scheme = scheme_desc(scheme, precision)
     d.hbm_budget, d.max_inflight, d.x_planes = int(hbm_budget), int(max_inflight), int(x_planes)
     d.steps_per_tick = int(steps_per_tick)
+    d.policy = SERVE_POLICIES[policy] if isinstance(policy, str) else int(policy)
     out = ctypes.c_void_p()
     _check(_lib.hj_server_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(out)), "hj_server_create")
     return out.value
@@ -631,8 +634,9 @@ class Server:
     """Continuous-batching re-solve server (see hj_server_create)."""
 
     def __init__(self, scheme: dict, precision: str = "f32", hbm_budget: int = 0, max_inflight: int = 64,
-                 x_planes: int = 0, stream=None, steps_per_tick: int = 0):
-        self.handle = hj_server_create(scheme, precision, hbm_budget, max_inflight, x_planes, stream, steps_per_tick)
+                 x_planes: int = 0, stream=None, steps_per_tick: int = 0, policy: str = "small_first"):
+        self.handle = hj_server_create(scheme, precision, hbm_budget, max_inflight, x_planes, stream, steps_per_tick,
+                                       policy)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -158,6 +158,9 @@ def test_server_null_and_range_arguments(lib):
     d.hbm_budget = -1
     assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
     d.hbm_budget = 0
+    d.policy = 7  # neither small-first nor sharing
+    assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
+    d.policy = hj.HJ_SERVE_SHARE
     d.scheme.cfl = 0.0
     assert lib.hj_server_create(ctypes.byref(d), None, ctypes.byref(out)) == hj.HJ_ERR_INVALID_ARG
     assert lib.hj_server_create(ctypes.byref(d), None, None) == hj.HJ_ERR_INVALID_ARG

@@ -55,8 +55,9 @@ def drain(srv, ids, results, shapes, max_ticks=100000):
     return ticks
 
 
+@pytest.mark.parametrize("policy", ["small_first", "share"])
 @pytest.mark.parametrize("max_inflight,steps_per_tick", [(3, 1), (5, 3), (64, 0)])
-def test_served_equals_alone(max_inflight, steps_per_tick):
+def test_served_equals_alone(max_inflight, steps_per_tick, policy):
     """Requests submitted between ticks (others already stepping), a queue
     when max_inflight is small, slots reused across requests of one shape,
     requests finishing inside a multi-step tick."""
@@ -65,7 +66,7 @@ def test_served_equals_alone(max_inflight, steps_per_tick):
     reqs = small_requests(10)
     ref = [alone(hj, r)[0] for r in reqs]
     with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=max_inflight,
-                   steps_per_tick=steps_per_tick) as srv:
+                   steps_per_tick=steps_per_tick, policy=policy) as srv:
         ids, shapes, results = [], {}, {}
         for i, r in enumerate(reqs):
             rid = srv.submit(r.grid, r.dyn, r.cylinders, r.horizon)
@@ -177,3 +178,41 @@ def test_served_mix_of_large_and_small_equals_alone():
         drain(srv, ids, results, shapes)
     for rid, r in zip(ids, ref):
         assert np.array_equal(results[rid], r), rid
+
+
+@pytest.mark.parametrize("policy", ["small_first", "share"])
+def test_policy_order_of_completion(policy):
+    """Two 60x60x20x36 requests with a long horizon (less work each than the
+    100x100x24x48 request beside them, but more steps) and the large one,
+    submitted together.  Small-first steps the two small ones (together they
+    fill the device) and holds the large one, so both small ones finish
+    first; sharing steps all three and the large one, with fewer steps,
+    finishes first.  Every result equals its solve alone."""
+    from paper_2012_04011_amd import hj
+
+    small, large = W.SERVE_GRIDS
+    reqs = [W.Request(0.0, 1, large, W.car_dynamics(), W.cylinders(80, 3), 1.5),
+            W.Request(0.0, 0, small, W.car_dynamics(), W.cylinders(81, 2), 5.0),
+            W.Request(0.0, 0, small, W.car_dynamics(), W.cylinders(82, 2), 5.0)]
+    ref = [alone(hj, r) for r in reqs]
+    work = [int(np.prod(r.grid["n"])) * info["steps"] for r, (_, info) in zip(reqs, ref)]
+    assert work[1] < work[0] and work[2] < work[0] and ref[1][1]["steps"] > ref[0][1]["steps"]
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=8, steps_per_tick=4, policy=policy) as srv:
+        ids = [srv.submit(r.grid, r.dyn, r.cylinders, r.horizon) for r in reqs]
+        shapes = {rid: tuple(r.grid["n"]) for rid, r in zip(ids, reqs)}
+        order, results = [], {}
+        for _ in range(100000):
+            if len(results) == len(ids):
+                break
+            srv.tick()
+            for rid in srv.poll():
+                out = np.empty(shapes[rid], np.float64)
+                srv.take(rid, out)
+                results[rid] = out
+                order.append(rid)
+    if policy == "small_first":
+        assert order[-1] == ids[0], order
+    else:
+        assert order[0] == ids[0], order
+    for rid, (V, _) in zip(ids, ref):
+        assert np.array_equal(results[rid], V), rid
