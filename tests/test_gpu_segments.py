@@ -49,7 +49,7 @@ def _segments(nv: int, rows: int) -> int:
     return -(-nv // per)
 
 
-def _one_step(monkeypatch, shape, pmask, rows, precision, deriv, integ, kernel):
+def _one_step(monkeypatch, shape, pmask, rows, precision, deriv, integ, kernel, dyn=None):
     from paper_2012_04011_amd import hj
 
     if kernel == "stream":
@@ -60,7 +60,7 @@ def _one_step(monkeypatch, shape, pmask, rows, precision, deriv, integ, kernel):
         monkeypatch.setenv("HJ_PLANE_VSEG", str(rows))
     monkeypatch.setenv("HJ_X_CHUNKS", "3")
     grid = dict(W.car_grid(*shape), periodic_mask=pmask)
-    dyn = W.car_dynamics(d_max=0.1)
+    dyn = dyn or W.car_dynamics(d_max=0.1)
     sch = W.scheme(deriv, integ)
     V0 = oracle.target_cylinders(grid, *W.cylinders(5, 4))
     rng = np.random.default_rng(sum(shape))
@@ -94,6 +94,29 @@ def test_split_plane_one_step(monkeypatch, shape, pmask, rows, deriv, integ, pre
     u = U32 if precision == "f32" else U64
     bad = np.abs(V - ref) > 16 * u * np.maximum(np.abs(ref), 1.0)
     if precision == "f64" or deriv == "upwind1":
+        assert not bad.any(), (int(bad.sum()), float(np.abs(V - ref).max()))
+    else:
+        assert bad.mean() <= 1e-4, int(bad.sum())
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_split_plane_ball_input(monkeypatch, precision):
+    """The test dynamics with a Euclidean-ball input on x, y and theta (the
+    ball term couples the axes) and drift on every axis, on a split plane
+    with a periodic v axis: bitwise the streaming kernel, the oracle to
+    rounding."""
+    dyn = {"kind": "drift_input", "drift": (0.3, -0.2, 0.15, 0.4), "in_axes": (0, 1, 3), "in_speed": 0.6,
+           "in_norm": "ball", "in_role": "min"}
+    shape, pmask, rows = (11, 10, 13, 16), W.THETA_PERIODIC | 4, 5
+    grid, dyn, sch, V0, Vk, dt, V, info = _one_step(monkeypatch, shape, pmask, rows, precision, "eno2", "rk2",
+                                                     "plane", dyn)
+    assert info["kernel"] == "plane" and info["plane_segments"] == _segments(shape[2], rows), info
+    *_, Vs, _ = _one_step(monkeypatch, shape, pmask, rows, precision, "eno2", "rk2", "stream", dyn)
+    assert np.array_equal(V, Vs)
+    ref = oracle.step(grid, dyn, sch, V0, Vk, dt)
+    u = U32 if precision == "f32" else U64
+    bad = np.abs(V - ref) > 16 * u * np.maximum(np.abs(ref), 1.0)
+    if precision == "f64":
         assert not bad.any(), (int(bad.sum()), float(np.abs(V - ref).max()))
     else:
         assert bad.mean() <= 1e-4, int(bad.sum())
