@@ -61,15 +61,17 @@ def algorithmic_bytes_per_launch(npts: int, info: dict, integrator: str) -> floa
     return info["bytes_per_point_step"] * npts / launches
 
 
-def measured_traffic(npts_expected: int):
+def measured_traffic(npts_expected: int, x_chunks: int):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    committed under profiles/, if they were taken on the current kernels."""
+    committed under profiles/, if they were taken on the current kernels in
+    the same launch configuration (x chunks: each adds halo planes)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("points") != npts_expected:
+    if (t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("points") != npts_expected or
+            t.get("x_chunks") != x_chunks):
         return None
     return t.get("bytes_per_launch")
 
@@ -123,6 +125,20 @@ def summarize_traffic(root: str, last: int = 200) -> int:
     from paper_2012_04011_amd import workloads as W
 
     copy_bytes = COPY_MIB * 2**20
+    # the launch configuration of the counted runs, from the JSON line each
+    # printed
+    chunks = set()
+    for key in ("fetch", "write"):
+        try:
+            with open(os.path.join(root, f"stage_{key}.log")) as fh:
+                for line in fh:
+                    if line.startswith("{"):
+                        chunks.add(json.loads(line)["config"]["x_chunks"])
+        except (OSError, ValueError, KeyError):
+            pass
+    if len(chunks) != 1:
+        print(f"summarize-traffic: the stage runs' x chunks are not one known value: {sorted(chunks)}", file=sys.stderr)
+        return 1
     res = {}
     for counter, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         stage = [r for r in _counter_rows(os.path.join(root, "stage_" + key), counter) if "stage_" in r[1]]
@@ -143,6 +159,7 @@ def summarize_traffic(root: str, last: int = 200) -> int:
     out = {
         "kernel_source_sha256_16": kernel_source_hash(),
         "points": W.LARGE_120.points,
+        "x_chunks": chunks.pop(),
         "bytes_per_launch": (s1 + s2) / 2.0,
         "stage1_bytes": s1,
         "stage2_bytes": s2,
@@ -483,7 +500,7 @@ def main() -> int:
     bpl = algorithmic_bytes_per_launch(npts, launch, wl.scheme["integrator"])
     avg_launch_s = prof["loop_ms"] / 1e3 / prof["step_launches"]
     achieved = bpl / avg_launch_s / 1e9
-    traffic = measured_traffic(npts) if prec == "f32" else None
+    traffic = measured_traffic(npts, launch["x_chunks"]) if prec == "f32" else None
     out = {
         "metric": METRIC,
         "value": value,

@@ -514,10 +514,12 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
     T vn[R], t0[R], tv = T(0);
     if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
     if (a.clamp) {
-      if (a.v0xy)
-        tv = a.v0xy[X * ny + y];
-      else
-        bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+      // one load feeds tv with either target form (the full-target form
+      // reads a value it does not use): no path then overwrites tv while a
+      // load into it may be in flight, which would cost a wait for them all
+      const T *tp = a.v0xy ? a.v0xy + (X * ny + y) : a.vs;
+      tv = *tp;
+      if (!a.v0xy) bload<T, R, kCacheStream>(rv0, oc, sX, t0);
     }
     T front[R];
 #pragma unroll
