@@ -274,7 +274,13 @@ hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
  * not depend on the choice (every candidate evaluates each node with the
  * same arithmetic).  hj_solve_brt calls it on first use unless disabled by
  * hj_set_autotune(g, 0) or fixed by the HJ_X_CHUNKS / HJ_STAGE_KERNEL
- * environment variables.  Requires a target (HJ_ERR_NOT_READY). */
+ * environment variables.  Requires a target (HJ_ERR_NOT_READY).
+ * Environment (for tests and measurements; read when a handle is created,
+ * HJ_AUTOTUNE_VERBOSE when it autotunes):
+ * HJ_STAGE_KERNEL=stream|generic forces a stage kernel; HJ_X_CHUNKS=n fixes
+ * the x chunks; HJ_PLANE_VSEG=r splits the plane kernel's (v, theta) plane
+ * into segments of at most r v rows (r >= 4) even when it fits one block;
+ * HJ_AUTOTUNE_VERBOSE prints each candidate's time to stderr. */
 hj_status hj_autotune(hj_grid *g);
 hj_status hj_set_autotune(hj_grid *g, int32_t enable);
 
