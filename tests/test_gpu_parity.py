@@ -123,6 +123,7 @@ RAGGED = [
     ((9, 6, 11, 4), 0b1010),
     ((4, 5, 6, 7), 0),
     ((3, 3, 3, 3), 0b1111),
+    ((6, 3, 4, 8), W.THETA_PERIODIC),  # three open y nodes: both ends' closed forms on one node
 ]
 DYNS = {
     "car": W.car_dynamics(),
