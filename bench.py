@@ -79,6 +79,28 @@ def measured_traffic(npts_expected: int, x_chunks: int):
 COPY_MIB = 512
 
 
+def copy_bandwidth_gbs(stream) -> float:
+    """Read + write GB/s of a plain 1 GiB device-to-device copy on `stream`
+    (best of 5): the practical bandwidth ceiling beside the nominal 8 TB/s."""
+    import torch
+
+    n = 2**30 // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    return 2 * n * 4 / best / 1e9
+
+
 def copy_calibration() -> int:
     """A plain device-to-device copy of COPY_MIB MiB, five times: the known
     byte count that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
@@ -501,6 +523,7 @@ def main() -> int:
     avg_launch_s = prof["loop_ms"] / 1e3 / prof["step_launches"]
     achieved = bpl / avg_launch_s / 1e9
     traffic = measured_traffic(npts, launch["x_chunks"]) if prec == "f32" else None
+    copy_gbs = copy_bandwidth_gbs(stream)
     out = {
         "metric": METRIC,
         "value": value,
@@ -539,6 +562,8 @@ def main() -> int:
             "bytes_per_point_step": launch["bytes_per_point_step"],
             "avg_launch_us": avg_launch_s * 1e6,
             "launches_timed": prof["step_launches"],
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "min": float(lat.min())},
