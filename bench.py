@@ -17,6 +17,8 @@ timed on a bounded sample of the same workload.
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
     python bench.py --workload batch64     # the uneven 64-instance batch
     python bench.py --workload serve       # the Poisson re-solve stream, served and one at a time
+    python bench.py --workload context     # the paper's grid and car, 67 iterations
+    python bench.py --precision f64        # the headline workload in FP64
 
 HBM traffic of the stage kernel (the roofline's `traffic`) comes from two
 rocprofv3 counter runs of this script (FETCH_SIZE, then WRITE_SIZE), each
@@ -413,6 +415,58 @@ def bench_serve(args) -> int:
     return 0
 
 
+def bench_context(args) -> int:
+    """The paper's own experiment shape beside its FPGA figure: the steering
+    car of eq (6) on the 60x60x20x36 grid, first-order upwind + Euler, FP32,
+    a BRT solve of 67 iterations (the paper's Table II count; the horizon is
+    67 CFL steps of this grid).  GPU-event time per solve, the target already
+    on the device.  The FPGA took 0.176 s for its 67 iterations."""
+    import numpy as np
+    import torch
+
+    from paper_2012_04011_amd import hj
+    from paper_2012_04011_amd import workloads as W
+
+    hj.load_library()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    grid = W.car_grid(60, 60, 20, 36)
+    sch = W.scheme("upwind1", "euler")
+    with hj.Grid(grid, W.steer_dynamics(), sch, "f32", stream) as g:
+        horizon = 67 * g.cfl_dt()
+        sets = [W.cylinders(70 + s, 3) for s in range(args.warmup + args.steps)]
+        for s in range(args.warmup):
+            g.set_target_cylinders(*sets[s])
+            info = g.solve_brt(horizon)
+        lat = []
+        for s in range(args.steps):
+            g.set_target_cylinders(*sets[args.warmup + s])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            info = g.solve_brt(horizon)
+            e1.record(stream)
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        launch = g.launch_info()
+    npts = int(np.prod(grid["n"]))
+    med = float(np.median(lat))
+    out = {
+        "metric": "BRT solve latency, 67 iterations (context beside the paper's FPGA)", "value": med,
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded cylinder obstacles)",
+        "config": {"workload": "paper shape: steering car (eq 6), 60x60x20x36, upwind + Euler FP32, 67 iterations",
+                   "iterations": info["steps"], "dt": info["dt"], "stage_kernel": launch["kernel"],
+                   "x_chunks": launch["x_chunks"]},
+        "latency_ms": {"p50": med, "min": float(np.min(lat)), "max": float(np.max(lat))},
+        "point_steps_per_s": npts * info["steps"] / (med / 1e3),
+        "paper_fpga_s": 0.176,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     """The FP64 oracle on the host cores: whole RK2 steps of the same
     workload from its seed-0 target, as many as fit the time budget."""
@@ -425,22 +479,44 @@ def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     cx, cy, r = W.cylinders(0, wl.obstacles)
     V0 = oracle.target_cylinders(wl.grid, cx, cy, r)
     dt = oracle.cfl_dt(wl.grid, wl.dyn, wl.scheme["cfl"], wl.horizon)
-    V = V0.copy()
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        V = oracle.step(wl.grid, wl.dyn, wl.scheme, V0, V, dt)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el + el / steps > budget_s:
-            break
-    del V, V0
+    def sample(budget):
+        V = V0.copy()
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            V = oracle.step(wl.grid, wl.dyn, wl.scheme, V0, V, dt)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el + el / steps > budget:
+                return steps, el
+
+    cores = oracle.threads()
+    steps, el = sample(budget_s)
+    # the same on one thread (at least one whole step)
+    oracle.set_threads(1)
+    try:
+        steps1, el1 = sample(0.6 * budget_s)
+    finally:
+        oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    grid = "x".join(map(str, wl.grid["n"]))
+    scheme = {"eno2": "ENO2", "upwind1": "upwind"}[wl.scheme["deriv"]] + "+" + \
+        {"rk2": "TVD-RK2", "euler": "Euler"}[wl.scheme["integrator"]]
     return {
         "value": wl.points * steps / el,
         "unit": UNIT,
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"{steps} full ENO2+TVD-RK2 FP64 step(s) of the {'x'.join(map(str, wl.grid['n']))} grid "
+        "sample": f"{steps} full {scheme} FP64 step(s) of the {grid} grid "
                   f"({wl.points * steps / 1e6:.1f}M point-steps, {el:.1f} s)",
+        "value_1_thread": wl.points * steps1 / el1,
+        "sample_1_thread": f"{steps1} step(s) of the same grid on one thread ({el1:.1f} s)",
+        "cpu_model": model,
+        "nproc": os.cpu_count(),
     }
 
 
@@ -452,7 +528,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", choices=["large120", "batch64", "serve"], default="large120")
+    ap.add_argument("--workload", choices=["large120", "batch64", "serve", "context"], default="large120")
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32",
                     help="large120: arithmetic of the solve (the headline is FP32)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
@@ -481,6 +557,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "context":
+        return bench_context(args)
     hj.load_library()
     torch.cuda.set_device(0)
     wl = W.LARGE_120
