@@ -257,12 +257,15 @@ hj_status hj_optimal_control(hj_grid *g, const double *states, int64_t m, int32_
  * hj_set_target_cylinders) and the clamp reads an Nx*Ny table instead of
  * the 4D V0.  plane_segments: with the plane kernel, how many blocks share
  * one (v, theta) plane (split along v when it has more than 768 runs of
- * theta nodes); 0 with the other kernels.  bytes_per_point_step: algorithmic
+ * theta nodes); 0 with the other kernels.  solve_graph: 1 if hj_solve_brt
+ * replays its time loop as a captured HIP graph (grids of at most 64 MiB per
+ * array, or as HJ_SOLVE_GRAPH=0/1 forces; bitwise the same result).
+ * bytes_per_point_step: algorithmic
  * HBM bytes one full step moves per grid node in this mode (each array read
  * once and written once per stage). */
 typedef struct {
   int32_t kernel, x_chunks, target_xy, autotuned;
-  int32_t plane_segments, reserved;
+  int32_t plane_segments, solve_graph;
   double bytes_per_point_step;
 } hj_launch_info;
 

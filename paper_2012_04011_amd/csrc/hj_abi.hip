@@ -113,6 +113,22 @@ struct hj_grid {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;  // pairs recorded since the last fold
   hj_profile prof = {0, 0, 0.0};
+
+  // hj_solve_brt's time loop captured as a HIP graph and replayed (small
+  // grids, where launch gaps are a large part of a step): one graph per
+  // step count, step sizes, starting buffers and launch configuration
+  struct SolveGraph {
+    int64_t n;
+    double dt, dt_last;
+    void *v_in, *w2_in, *v_out, *w2_out;
+    int kernel, x_chunks;
+    bool target_xy;
+    const int32_t *skip;
+    hipGraphExec_t exec;
+  };
+  std::vector<SolveGraph> graphs;  // most recent last
+  hipStream_t cap_stream = nullptr;  // private stream the loop is captured on
+  int graph_mode = -1;  // -1: by grid size, 0: never, 1: always (HJ_SOLVE_GRAPH)
 };
 
 namespace {
@@ -314,6 +330,10 @@ void free_all(hj_grid *G) {
   if (G->flag_host) (void)hipHostFree(G->flag_host);
   for (hipEvent_t e : G->ev_pool) (void)hipEventDestroy(e);
   G->ev_pool.clear();
+  for (auto &e : G->graphs) (void)hipGraphExecDestroy(e.exec);
+  G->graphs.clear();
+  if (G->cap_stream) (void)hipStreamDestroy(G->cap_stream);
+  G->cap_stream = nullptr;
 }
 
 // Fold the recorded event pairs into the profile (synchronises on them).
@@ -608,6 +628,86 @@ hj_status enqueue_step(hj_grid *G, double dt, int64_t *launches) {
 hj_status step_once(hj_grid *G, double dt, int64_t *launches) {
   if (G->elem == 4) return enqueue_step<float>(G, dt, launches);
   return enqueue_step<double>(G, dt, launches);
+}
+
+// ---- the solve loop as a HIP graph ----------------------------------------
+
+constexpr size_t kSolveGraphs = 4;                      // graphs kept per handle
+constexpr int64_t kSolveGraphMaxBytes = (int64_t)64 << 20;  // auto: arrays up to this size
+
+bool use_solve_graph(hj_grid *G, int64_t n) {
+  if (G->graph_mode < 0) {
+    const char *env = getenv("HJ_SOLVE_GRAPH");
+    G->graph_mode = env ? (atoi(env) != 0 ? 1 : 0) : 2;  // 2: by grid size
+  }
+  if (n < 2 || G->graph_mode == 0) return false;
+  return G->graph_mode == 1 || G->npts * (int64_t)G->elem <= kSolveGraphMaxBytes;
+}
+
+// The n steps of a solve: replay the graph captured for this (n, dt,
+// dt_last, starting buffers, launch configuration), capturing it first if
+// needed.  The loop is captured on a private stream and launched on the
+// handle's stream; the buffer roles end as the plain loop leaves them.
+hj_status solve_graph(hj_grid *G, int64_t n, double dt, double dt_last, int64_t *launches) {
+  const int per_step = G->sch.integrator == HJ_EULER ? 1 : 2;
+  for (size_t i = 0; i < G->graphs.size(); ++i) {
+    hj_grid::SolveGraph e = G->graphs[i];
+    if (e.n == n && e.dt == dt && e.dt_last == dt_last && e.v_in == G->v && e.w2_in == G->w2 &&
+        e.kernel == G->kernel && e.x_chunks == G->x_chunks && e.target_xy == G->target_xy && e.skip == G->skip) {
+      HJ_HIP(hipGraphLaunch(e.exec, S(G)));
+      G->v = e.v_out;
+      G->w2 = e.w2_out;
+      G->graphs.erase(G->graphs.begin() + i);
+      G->graphs.push_back(e);
+      *launches += per_step * n;
+      return HJ_OK;
+    }
+  }
+  if (!G->cap_stream) HJ_HIP(hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking));
+  hj_grid::SolveGraph e;
+  e.n = n;
+  e.dt = dt;
+  e.dt_last = dt_last;
+  e.v_in = G->v;
+  e.w2_in = G->w2;
+  e.kernel = G->kernel;
+  e.x_chunks = G->x_chunks;
+  e.target_xy = G->target_xy;
+  e.skip = G->skip;
+  e.exec = nullptr;
+  hipStream_t user = G->stream;
+  HJ_HIP(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
+  G->stream = G->cap_stream;
+  int64_t captured = 0;
+  hj_status st = HJ_OK;
+  for (int64_t k = 0; k < n && st == HJ_OK; ++k) st = step_once(G, k + 1 < n ? dt : dt_last, &captured);
+  G->stream = user;
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(G->cap_stream, &graph);
+  e.v_out = G->v;
+  e.w2_out = G->w2;
+  if (st != HJ_OK || ce != hipSuccess) {
+    G->v = e.v_in;  // nothing ran: the buffer roles stay as they were
+    G->w2 = e.w2_in;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != HJ_OK) return st;
+    return fail(HJ_ERR_DEVICE, "HIP error %d (%s) capturing the solve loop", (int)ce, hipGetErrorString(ce));
+  }
+  hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    G->v = e.v_in;
+    G->w2 = e.w2_in;
+    return fail(HJ_ERR_DEVICE, "HIP error %d (%s) instantiating the solve loop", (int)ie, hipGetErrorString(ie));
+  }
+  if (G->graphs.size() >= kSolveGraphs) {
+    (void)hipGraphExecDestroy(G->graphs.front().exec);
+    G->graphs.erase(G->graphs.begin());
+  }
+  G->graphs.push_back(e);
+  HJ_HIP(hipGraphLaunch(e.exec, S(G)));
+  *launches += captured;
+  return HJ_OK;
 }
 
 // ---- Algorithm 1's derivative-range alpha ----------------------------------
@@ -1089,8 +1189,12 @@ hj_status hj_solve_brt(hj_grid *G, double horizon, hj_solve_info *info) {
     HJ_HIP(hipEventRecord(ev_b, S(G)));
   }
   int64_t launches = 0;
-  for (int64_t k = 0; k < n; ++k)
-    if ((st = step_once(G, k + 1 < n ? dt : dt_last, &launches)) != HJ_OK) return st;
+  if (use_solve_graph(G, n)) {
+    if ((st = solve_graph(G, n, dt, dt_last, &launches)) != HJ_OK) return st;
+  } else {
+    for (int64_t k = 0; k < n; ++k)
+      if ((st = step_once(G, k + 1 < n ? dt : dt_last, &launches)) != HJ_OK) return st;
+  }
   if (timed) {
     HJ_HIP(hipEventRecord(ev_e, S(G)));
     G->prof.solves += 1;
@@ -1321,7 +1425,7 @@ hj_status hj_get_launch_info(hj_grid *G, hj_launch_info *out) {
   out->target_xy = G->target_xy && G->kernel > 0;
   out->autotuned = G->autotuned;
   out->plane_segments = G->kernel == 2 ? G->n_seg : 0;
-  out->reserved = 0;
+  out->solve_graph = G->sch.alpha_mode == HJ_ALPHA_STATE && use_solve_graph(G, 2) ? 1 : 0;
   // arrays per stage: read the stencil input, write the output; stage 2 of
   // TVD-RK2 also reads V^n; the clamp reads V0 unless it is the xy table
   double arrays;
