@@ -397,6 +397,11 @@ __device__ inline void x_plane_b(__amdgpu_buffer_rsrc_t rs, int xi, int nx, bool
 // This equals the ghost-layer evaluation up to its rounding (a few units in
 // the last place of V); the windows of these nodes were loaded with clamped
 // indices, and pm, pp computed from them are replaced here.
+// An empty volatile asm statement: the compiler may not speculate it, so a
+// block holding it stays behind its (wave-uniform) branch instead of being
+// turned into selects that every wave executes.
+__device__ inline void keep_branch() { asm volatile(""); }
+
 template <typename T>
 __device__ inline void edge_diffs(int i, int n, T m1, T c, T p1, T &pm, T &pp) {
   const T dl = c - m1, dr = p1 - c;
@@ -437,8 +442,10 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
       oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
     }
   }
-  const bool vedge = !perv && (v < 2 || v >= nv - 2);
-  const bool yedge = !pery && (y < 2 || y >= ny - 2);
+  // the edge fix-ups run in the waves that hold an edge lane (branching on a
+  // wave-uniform flag keeps the selects out of every other wave)
+  const bool vedge = __ballot(!perv && (v < 2 || v >= nv - 2)) != 0;
+  const bool yedge = __ballot(!pery && (y < 2 || y >= ny - 2)) != 0;
   // theta-axis coefficients of this thread's v (see StreamArgs::coef_th)
   const T kpt = a.coef_th[v], kmt = a.coef_th[nv + v], sgt = a.coef_th[2 * nv + v];
   T kpx[R], kmx[R], kpy[R], kmy[R];
@@ -591,21 +598,29 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
       }
     }
     // ---- v
+    T pmv[R], ppv[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      T pm, pp;
-      window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pm, pp);
-      if (vedge) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pm, pp);
-      accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
+    for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pmv[j], ppv[j]);
+    if (vedge) {
+      keep_branch();
+#pragma unroll
+      for (int j = 0; j < R; ++j) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pmv[j], ppv[j]);
     }
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
     // ---- y
+    T pmy[R], ppy[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      T pm, pp;
-      window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pm, pp);
-      if (yedge) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pm, pp);
-      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
+    for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pmy[j], ppy[j]);
+    if (yedge) {
+      keep_branch();
+#pragma unroll
+      for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pmy[j], ppy[j]);
     }
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
     // ---- update
     T res[R];
 #pragma unroll
@@ -711,7 +726,10 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   }
   uint32_t lh[4];  // theta halos inside the LDS plane (see the streaming kernel)
   theta_halo_offsets<R>((v - vbase) * nth, th0, nth, lh);
-  const bool vedge = !perv && (v < 2 || v >= nv - 2);
+  // the v fix-ups run in the waves that hold an edge lane (branching on a
+  // wave-uniform flag keeps the selects out of every other wave); y is the
+  // block's
+  const bool vedge = __ballot(!perv && (v < 2 || v >= nv - 2)) != 0;
   const bool yedge = !pery && (y < 2 || y >= ny - 2);
   // theta-axis coefficients of this thread's v (see StreamArgs::coef_th)
   const T kpt = a.coef_th[v], kmt = a.coef_th[nv + v], sgt = a.coef_th[2 * nv + v];
@@ -896,22 +914,30 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       lds_run<T, R>(buf + lv[1], vn1);
       lds_run<T, R>(buf + lv[2], vp1);
       if (DERIV == kEno2) lds_run<T, R>(buf + lv[3], vp2);
+      T pmv[R], ppv[R];
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        T pm, pp;
-        window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pm, pp);
-        if (vedge) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pm, pp);
-        accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], pp, pm, ball_v, a.half_inv_h[2]);
+      for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pmv[j], ppv[j]);
+      if (vedge) {
+        keep_branch();
+#pragma unroll
+        for (int j = 0; j < R; ++j) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pmv[j], ppv[j]);
       }
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
     }
     // ---- y: neighbours from global memory
+    T pmy[R], ppy[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      T pm, pp;
-      window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pm, pp);
-      if (yedge) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pm, pp);
-      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], pp, pm, ball_y, a.half_inv_h[1]);
+    for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pmy[j], ppy[j]);
+    if (yedge) {
+      keep_branch();
+#pragma unroll
+      for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pmy[j], ppy[j]);
     }
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
     // ---- update
     T res[R];
 #pragma unroll
