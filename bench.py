@@ -207,7 +207,8 @@ def bench_batch(args) -> int:
     """The uneven 64-instance batch: every mode of hj_batch_solve beside the
     same solves run one grid at a time, fixed 16-plane tiles beside the
     autotuned tile length.  One JSON line; throughput is whole-batch
-    point-steps over the graph-mode solve time."""
+    point-steps over the solve time of the faster of the autotuned graph mode
+    and the concurrent-streams mode."""
     import numpy as np
     import torch
 
@@ -249,12 +250,13 @@ def bench_batch(args) -> int:
         res[mode] = timed(lambda: b.solve(H, mode), max(1, args.steps // 3))
     tuned = b.autotune(H, "graph")
     res["graph_tuned"] = timed(lambda: b.solve(H, "graph"), args.steps)
+    res["streams"] = timed(lambda: b.solve(H, "streams"), args.steps)
     info = b.info()
     b.close()
     for g in grids:
         g.close()
-    t = res["graph_tuned"]
-    ms = float(np.median(t))
+    best = min(("graph_tuned", "streams"), key=lambda k: float(np.median(res[k])))
+    ms = float(np.median(res[best]))
     value = point_steps / (ms / 1e3)
     bpps = 20.0  # FP32 TVD-RK2 with the cylinder x-y target (see the single-grid byte model)
     achieved = value * bpps / 1e9
@@ -265,7 +267,8 @@ def bench_batch(args) -> int:
         "config": {
             "workload": "batch: 64 uneven car4d instances 30x30x12x18..80x80x24x48, 1-8 cylinders, horizons "
                         "0.5-2 s, ENO2+TVD-RK2 FP32",
-            "points": info["points"], "point_steps": point_steps, "mode": "graph",
+            "points": info["points"], "point_steps": point_steps,
+            "mode": "graph" if best == "graph_tuned" else "streams",
             "x_planes_autotuned": tuned, "tiles_per_sweep": info["tiles_per_sweep"],
             "graph_nodes": info["graph_nodes"],
         },
@@ -274,11 +277,14 @@ def bench_batch(args) -> int:
             "launches_fixed16": float(np.median(res["launches"])),
             "graph_fixed16": float(np.median(res["graph"])),
             "persistent_fixed16": float(np.median(res["persistent"])),
-            "graph_autotuned": ms,
+            "graph_autotuned": float(np.median(res["graph_tuned"])),
+            "streams": float(np.median(res["streams"])),
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "batched stage kernel (whole solve, both stages)", "bytes_per_point_step": bpps},
+                     "kernel": ("batched stage kernel" if best == "graph_tuned" else
+                                "single-grid stage kernels on four concurrent streams") +
+                               " (whole solve, both stages)", "bytes_per_point_step": bpps},
     }
     print(json.dumps(out), flush=True)
     return 0

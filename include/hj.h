@@ -298,7 +298,8 @@ typedef struct hj_batch hj_batch;
 enum {
   HJ_BATCH_LAUNCHES = 0,   /* one launch per (step, stage) over every instance still running */
   HJ_BATCH_GRAPH = 1,      /* the same launches, captured once as a hipGraph and replayed */
-  HJ_BATCH_PERSISTENT = 2  /* one persistent launch for the whole batch (work queue) */
+  HJ_BATCH_PERSISTENT = 2, /* one persistent launch for the whole batch (work queue) */
+  HJ_BATCH_STREAMS = 3     /* each instance's own single-grid solve, on 4 concurrent private streams */
 };
 
 typedef struct {
@@ -307,7 +308,7 @@ typedef struct {
   int32_t persistent_blocks;  /* blocks of the last persistent launch */
   int32_t graph_nodes;        /* kernel nodes of the cached graph (0: none) */
   int64_t tiles_per_sweep;    /* tiles of one stage over all instances */
-  int64_t work_items;         /* tiles over all stages of the last solve */
+  int64_t work_items;         /* tiles over all stages of the last solve (0 after a streams-mode solve) */
   int64_t points;             /* grid nodes over all instances */
 } hj_batch_info;
 
@@ -326,8 +327,13 @@ hj_status hj_batch_destroy(hj_batch *b);
  * leave V in its handle; infos (m entries) may be NULL.  Launch-mode and
  * graph-mode calls are stream-ordered and return without waiting; the
  * persistent mode synchronises the stream to read the work queue's error
- * flag.  HJ_ERR_NOT_READY if an instance has no target; HJ_ERR_DEVICE if a
- * persistent tile waited past the spin limit (values then undefined). */
+ * flag.  The streams mode runs hj_solve_brt of every instance (its own
+ * kernel, launch configuration and solve graph; a first solve may autotune
+ * and synchronise) on four private streams forked from the batch stream and
+ * joined back into it, so the call is stream-ordered too; instances go to the
+ * least-loaded stream in decreasing order of nodes x steps; tile settings do
+ * not apply.  HJ_ERR_NOT_READY if an instance has no target; HJ_ERR_DEVICE
+ * if a persistent tile waited past the spin limit (values then undefined). */
 hj_status hj_batch_solve(hj_batch *b, const double *horizons, int32_t mode, hj_solve_info *infos);
 
 /* Tile shape: x planes per tile for every instance (0 = the default, 16). */
@@ -340,7 +346,8 @@ hj_status hj_batch_set_spin_limit(hj_batch *b, int64_t polls);
 
 /* Time complete batch solves (horizons, mode) for each candidate tile
  * length (4, 8, 12, 16, 24, 32, 48, 80 x planes), keep the fastest and
- * report it.  Synchronises; leaves every instance holding its solve. */
+ * report it.  Synchronises; leaves every instance holding its solve.  The
+ * streams mode has no tiles: HJ_ERR_INVALID_ARG. */
 hj_status hj_batch_autotune(hj_batch *b, const double *horizons, int32_t mode, int32_t *x_planes_out);
 
 hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);

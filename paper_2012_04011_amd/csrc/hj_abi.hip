@@ -1489,6 +1489,10 @@ hj_status hj_get_profile(hj_grid *G, hj_profile *out) {
 // Batched solves
 // ===========================================================================
 
+// Streams of the concurrent batch mode: one per hardware queue a process
+// gets by default, so that independent solves can run side by side.
+constexpr int kBatchLanes = 4;
+
 struct hj_batch {
   std::vector<hj_grid *> g;
   int m = 0;
@@ -1516,12 +1520,23 @@ struct hj_batch {
   std::vector<int64_t> gkey;
   int32_t graph_nodes = 0;
 
+  // HJ_BATCH_STREAMS: private lanes (created on first use), the fork event
+  // they wait on and the join events the batch stream waits on
+  hipStream_t lanes[kBatchLanes] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kBatchLanes] = {};
+
   hj_batch_info info = {};
 };
 
 namespace {
 
 void batch_free(hj_batch *b) {
+  for (int k = 0; k < kBatchLanes; ++k) {
+    if (b->lanes[k]) (void)hipStreamDestroy(b->lanes[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -1768,6 +1783,56 @@ hj_status check_batch(hj_batch *b) {
   return HJ_OK;
 }
 
+// HJ_BATCH_STREAMS: each instance runs its own single-grid solve (its own
+// kernel and launch configuration, its own solve graph) on one of the
+// batch's lanes, so that small solves share the device.  The lanes fork from
+// the batch stream and the batch stream joins them at the end; instances go
+// to the least-loaded lane in decreasing order of work (nodes x steps).
+hj_status batch_solve_streams(hj_batch *b, const double *horizons, hj_solve_info *infos) {
+  hj_status st;
+  for (int k = 0; k < kBatchLanes; ++k) {
+    if (!b->lanes[k]) HJ_HIP(hipStreamCreateWithFlags(&b->lanes[k], hipStreamNonBlocking));
+    if (!b->join[k]) HJ_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+  }
+  if (!b->fork) HJ_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  std::vector<std::pair<double, int>> work((size_t)b->m);
+  b->info.points = 0;
+  b->info.work_items = 0;  // no tiles: every instance runs its own solve
+  for (int j = 0; j < b->m; ++j) {
+    hj_grid *G = b->g[j];
+    b->info.points += G->npts;
+    if ((st = ensure_dt(G)) != HJ_OK) return st;
+    double dt, dt_last;
+    int64_t n;
+    schedule(G, horizons[j], &n, &dt, &dt_last);
+    work[(size_t)j] = {-(double)G->npts * (double)n, j};
+  }
+  std::stable_sort(work.begin(), work.end());
+  HJ_HIP(hipEventRecord(b->fork, b->stream));
+  for (int k = 0; k < kBatchLanes; ++k) HJ_HIP(hipStreamWaitEvent(b->lanes[k], b->fork, 0));
+  double load[kBatchLanes] = {};
+  st = HJ_OK;
+  for (const auto &w : work) {
+    int k = 0;
+    for (int i = 1; i < kBatchLanes; ++i)
+      if (load[i] < load[k]) k = i;
+    load[k] -= w.first;
+    hj_grid *G = b->g[(size_t)w.second];
+    hipStream_t own = G->stream;
+    G->stream = b->lanes[k];
+    st = hj_solve_brt(G, horizons[w.second], infos ? &infos[w.second] : nullptr);
+    G->stream = own;
+    if (st != HJ_OK) break;
+  }
+  // join every lane, also after a failed solve, so that the batch stream is
+  // ordered after whatever was enqueued
+  for (int k = 0; k < kBatchLanes; ++k) {
+    HJ_HIP(hipEventRecord(b->join[k], b->lanes[k]));
+    HJ_HIP(hipStreamWaitEvent(b->stream, b->join[k], 0));
+  }
+  return st;
+}
+
 hj_status check_horizons(const hj_batch *b, const double *horizons) {
   if (!horizons) return fail(HJ_ERR_INVALID_ARG, "null horizons");
   for (int j = 0; j < b->m; ++j)
@@ -1848,10 +1913,11 @@ hj_status hj_batch_destroy(hj_batch *b) {
 hj_status hj_batch_solve(hj_batch *b, const double *horizons, int32_t mode, hj_solve_info *infos) {
   hj_status st = check_batch(b);
   if (st != HJ_OK) return st;
-  if (mode != HJ_BATCH_LAUNCHES && mode != HJ_BATCH_GRAPH && mode != HJ_BATCH_PERSISTENT)
+  if (mode != HJ_BATCH_LAUNCHES && mode != HJ_BATCH_GRAPH && mode != HJ_BATCH_PERSISTENT && mode != HJ_BATCH_STREAMS)
     return fail(HJ_ERR_INVALID_ARG, "unknown batch mode %d", mode);
   if ((st = check_horizons(b, horizons)) != HJ_OK) return st;
   HJ_HIP(hipSetDevice(b->device));
+  if (mode == HJ_BATCH_STREAMS) return batch_solve_streams(b, horizons, infos);
   return b->elem == 4 ? batch_solve_t<float>(b, horizons, mode, infos) : batch_solve_t<double>(b, horizons, mode, infos);
 }
 
@@ -1875,7 +1941,7 @@ hj_status hj_batch_autotune(hj_batch *b, const double *horizons, int32_t mode, i
   hj_status st = check_batch(b);
   if (st != HJ_OK) return st;
   if (mode != HJ_BATCH_LAUNCHES && mode != HJ_BATCH_GRAPH && mode != HJ_BATCH_PERSISTENT)
-    return fail(HJ_ERR_INVALID_ARG, "unknown batch mode %d", mode);
+    return fail(HJ_ERR_INVALID_ARG, "batch mode %d has no tile length to tune", mode);
   if ((st = check_horizons(b, horizons)) != HJ_OK) return st;
   HJ_HIP(hipSetDevice(b->device));
   const int32_t cand[] = {4, 8, 12, 16, 24, 32, 48, 80};

@@ -31,11 +31,12 @@ HJ_EULER, HJ_TVD_RK2 = 0, 1
 HJ_CLAMP_NONE, HJ_CLAMP_MIN_V0 = 0, 1
 HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
 HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
-HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT = 0, 1, 2
+HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT, HJ_BATCH_STREAMS = 0, 1, 2, 3
 HJ_ALPHA_STATE, HJ_ALPHA_DERIV_RANGE = 0, 1
 HJ_SERVE_SMALL_FIRST, HJ_SERVE_SHARE = 0, 1
 SERVE_POLICIES = {"small_first": HJ_SERVE_SMALL_FIRST, "share": HJ_SERVE_SHARE}
-BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT}
+BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT,
+               "streams": HJ_BATCH_STREAMS}
 
 STATUS_NAMES = {0: "HJ_OK", 1: "HJ_ERR_INVALID_ARG", 2: "HJ_ERR_OUT_OF_MEMORY", 3: "HJ_ERR_DEVICE",
                 4: "HJ_ERR_NOT_READY", 5: "HJ_ERR_NONFINITE", 6: "HJ_ERR_UNSUPPORTED"}

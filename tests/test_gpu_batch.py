@@ -1,8 +1,9 @@
 """Batched solves through the C ABI (hj_batch_*): every instance of a batch
 must equal the single-grid solve of the same handle bit for bit (the batch
 kernels evaluate each node with the single-grid kernels' arithmetic), in all
-three modes (one launch per step and stage; the same launches replayed from
-a hipGraph; one persistent launch); and the batch must match the oracle."""
+four modes (one launch per step and stage; the same launches replayed from
+a hipGraph; one persistent launch; each instance's own solve on concurrent
+streams); and the batch must match the oracle."""
 
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ def _gpu():
 
     hj.load_library()
 
-MODES = ["launches", "graph", "persistent"]
+MODES = ["launches", "graph", "persistent", "streams"]
 
 
 def small_batch(precision: str):
@@ -174,17 +175,18 @@ def test_batch_autotune_picks_a_candidate():
         g.close()
 
 
-def test_batch_64_uneven_sampled():
+@pytest.mark.parametrize("mode", ["persistent", "streams"])
+def test_batch_64_uneven_sampled(mode):
     """The 64-instance uneven batch (30x30x12x18 .. 80x80x24x48, 1-8
-    cylinders, horizons 0.5-2 s) in one persistent launch: four instances
-    (the largest, the smallest, the longest and the shortest horizon) equal
-    their single-grid solves bit for bit."""
+    cylinders, horizons 0.5-2 s) in one persistent launch and on concurrent
+    streams: four instances (the largest, the smallest, the longest and the
+    shortest horizon) equal their single-grid solves bit for bit."""
     from paper_2012_04011_amd import hj
 
     insts = W.batch_instances(**W.BATCH_64)
     grids = make_grids(hj, insts, "f32")
     with hj.Batch(grids) as b:
-        infos = b.solve([i.horizon for i in insts], "persistent")
+        infos = b.solve([i.horizon for i in insts], mode)
         assert b.info()["points"] == sum(i.points for i in insts)
     pick = {int(np.argmax([i.points for i in insts])), int(np.argmin([i.points for i in insts])),
             int(np.argmax([i.horizon for i in insts])), int(np.argmin([i.horizon for i in insts]))}
@@ -193,5 +195,30 @@ def test_batch_64_uneven_sampled():
     for r, ri, j in zip(ref, ref_infos, sorted(pick)):
         assert infos[j]["steps"] == ri["steps"]
         assert np.array_equal(grids[j].value(np.float64), r), j
+    for g in grids:
+        g.close()
+
+
+def test_batch_streams_mode_ordering_and_errors():
+    """The streams mode is ordered on the batch stream (eager work enqueued
+    before and after it sees the right values), repeats bitwise, and has no
+    tile length to tune."""
+    from paper_2012_04011_amd import hj
+
+    insts = small_batch("f32")
+    ref, _ = single_solutions(hj, insts, "f32")
+    grids = make_grids(hj, insts, "f32")
+    H = [i.horizon for i in insts]
+    with hj.Batch(grids) as b:
+        for rep in range(3):
+            for g, ins in zip(grids, insts):
+                g.set_target_cylinders(*W.cylinders(90 + rep, 2))  # replaced below, same stream
+                g.set_target_cylinders(*ins.cylinders)
+            b.solve(H, "streams")
+            for j, g in enumerate(grids):
+                assert np.array_equal(g.value(np.float64), ref[j]), (rep, j)
+        with pytest.raises(hj.HJError) as e:
+            b.autotune(H, "streams")
+        assert e.value.status == hj.HJ_ERR_INVALID_ARG
     for g in grids:
         g.close()
