@@ -799,6 +799,13 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     for (int j = 0; j < R; ++j) D[0][j] = S[0][j] - wm1[j];
   }
   x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, S[FR]);
+  // y neighbours of the current plane (y - 2, y - 1, y + 1, y + 2): loaded
+  // at the end of the previous plane, as soon as that plane has used them
+  T Y[4][R];
+  if (DERIV == kEno2) bload<T, R>(rs, oy[0], (uint32_t)x0 * pb, Y[0]);
+  bload<T, R>(rs, oy[1], (uint32_t)x0 * pb, Y[1]);
+  bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
+  if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
 
   auto plane = [&](auto phase, const int X) {
     constexpr int P = decltype(phase)::value;
@@ -806,12 +813,11 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     constexpr int DC = P & 1, DN = (P + 1) & 1;
     const uint32_t sX = (uint32_t)X * pb;
     T *buf = lds + ((X - x0) & 1) * psz;
-    // ---- global loads: y neighbours of this plane, then the next front
-    T yn2[R], yn1[R], yp1[R], yp2[R];
-    if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX, yn2);
-    bload<T, R>(rs, oy[1], sX, yn1);
-    bload<T, R>(rs, oy[2], sX, yp1);
-    if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
+    // ---- global loads of this plane (its y neighbours are in flight), then the next front
+    T(&yn2)[R] = Y[0];
+    T(&yn1)[R] = Y[1];
+    T(&yp1)[R] = Y[2];
+    T(&yp2)[R] = Y[3];
     // pointwise streams of this plane (V^n, V0): issued now, used at the end
     T vn[R], t0[R], tv = T(0);
     if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
@@ -938,6 +944,12 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
 #pragma unroll
     for (int j = 0; j < R; ++j)
       accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
+    if (X + 1 < x1) {
+      if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX + pb, Y[0]);
+      bload<T, R>(rs, oy[1], sX + pb, Y[1]);
+      bload<T, R>(rs, oy[2], sX + pb, Y[2]);
+      if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX + pb, Y[3]);
+    }
     // ---- update
     T res[R];
 #pragma unroll
