@@ -473,6 +473,123 @@ def bench_context(args) -> int:
     return 0
 
 
+def bench_adjacent(args) -> int:
+    """The method's adjacent parts on the 120x120x40x72 grid, FP32, beside
+    the fixed-horizon solve of the same grid (GPU-event time, the target on
+    the device):
+      converge     the convergence mode with a zero threshold, so that it runs
+                   exactly the n steps of a 2 s solve: the cost of the
+                   per-step stop test (eps = max |V_t+1 - V_t|, 8 B per node)
+      alpha_range  Algorithm 1's derivative-range dissipation: a range pass
+                   over V and a host round trip before every step
+      control      the optimal-control query of eq (9) at 2^20 random states
+                   on the device, and at one state from the host (latency)"""
+    import numpy as np
+    import torch
+
+    from paper_2012_04011_amd import hj
+    from paper_2012_04011_amd import workloads as W
+
+    hj.load_library()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    wl = W.LARGE_120
+    npts = wl.points
+    cyl = W.cylinders(0, wl.obstacles)
+    reps = max(1, args.steps)
+
+    def timed(fn):
+        fn()  # warm-up: autotune, graph capture, first allocations
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return float(np.median(t))
+
+    out = {"n_gpus": 1, "steps": reps, "warmup": 1, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded cylinder obstacles)"}
+    if args.workload == "converge":
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32", stream) as g:
+            g.set_target_cylinders(*cyl)
+            n = g.solve_brt(wl.horizon)["steps"]
+            short = (n - 0.5) * g.cfl_dt()  # n steps, the last one halved
+            assert g.solve_brt(short)["steps"] == n
+            plain = timed(lambda: g.solve_brt(short))
+            info = {}
+
+            def conv():
+                info.update(g.solve_converge(0.0, n))
+
+            conv_ms = timed(conv)
+        assert info["steps"] == n and not info["converged"]
+        extra_us = (conv_ms - plain) / n * 1e3
+        out.update({
+            "metric": "convergence-mode solve time (eps test every step)", "value": conv_ms, "unit": "ms",
+            "ms_per_step": conv_ms / n, "higher_is_better": False,
+            "config": {"workload": "car4d 120x120x40x72 ENO2+TVD-RK2 FP32, convergence mode, zero threshold "
+                                   f"({n} steps, the 2 s solve's count)", "steps_per_solve": n},
+            "fixed_horizon_ms": plain, "stop_test_us_per_step": extra_us,
+            "stop_test_bytes_per_step": 8.0 * npts,
+            "stop_test_gbs": 8.0 * npts / (extra_us * 1e3) if extra_us > 0 else None,
+        })
+    elif args.workload == "alpha_range":
+        sch = dict(wl.scheme, alpha="deriv_range")
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32", stream) as g0:
+            g0.set_target_cylinders(*cyl)
+            dt0 = g0.cfl_dt()
+            horizon = 20 * dt0
+            n0 = g0.solve_brt(horizon)["steps"]
+            plain = timed(lambda: g0.solve_brt(horizon))
+        info = {}
+        with hj.Grid(wl.grid, wl.dyn, sch, "f32", stream) as g:
+            g.set_target_cylinders(*cyl)
+
+            def solve():
+                info.update(g.solve_brt(horizon))
+
+            rng_ms = timed(solve)
+        per = rng_ms / info["steps"]
+        out.update({
+            "metric": "derivative-range (Algorithm 1) solve time per step", "value": per, "unit": "ms",
+            "ms_per_step": per, "higher_is_better": False,
+            "config": {"workload": "car4d 120x120x40x72 ENO2+TVD-RK2 FP32, alpha from each step's derivative "
+                                   f"range, horizon {horizon:.4f} s", "steps": info["steps"], "first_dt": info["dt"]},
+            "state_alpha_ms_per_step": plain / n0, "state_alpha_steps": n0,
+            "range_pass_us_per_step": (per - plain / n0) * 1e3,
+        })
+    elif args.workload == "control":
+        m = 1 << 20
+        rng = np.random.default_rng(7)
+        lo, hi = np.array(wl.grid["lo"]), np.array(wl.grid["hi"])
+        z = lo + (hi - lo) * rng.random((m, 4))
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32", stream) as g:
+            g.set_target_cylinders(*cyl)
+            g.solve_brt(wl.horizon)
+            zd = torch.from_numpy(z).to("cuda")
+            u = torch.empty((m, 2), dtype=torch.float64, device="cuda")
+            val = torch.empty(m, dtype=torch.float64, device="cuda")
+            dev_ms = timed(lambda: hj.hj_optimal_control(g.handle, zd, u, val))
+            one = []
+            for k in range(200):
+                t0 = time.perf_counter()
+                g.optimal_control(z[k:k + 1])
+                one.append((time.perf_counter() - t0) * 1e3)
+        out.update({
+            "metric": "optimal-control queries/s (eq 9 at arbitrary states)", "value": m / (dev_ms / 1e3),
+            "unit": "queries/s", "ms_per_step": dev_ms, "higher_is_better": True, "dtype": "f64",
+            "config": {"workload": "car4d 120x120x40x72 FP32 V after a 2 s solve, 2^20 uniform random states, "
+                                   "device arrays", "states": m},
+            "host_single_query_ms": {"p50": float(np.percentile(one, 50)), "p99": float(np.percentile(one, 99))},
+        })
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     """The FP64 oracle on the host cores: whole RK2 steps of the same
     workload from its seed-0 target, as many as fit the time budget."""
@@ -534,7 +651,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", choices=["large120", "batch64", "serve", "context"], default="large120")
+    ap.add_argument("--workload", choices=["large120", "batch64", "serve", "context", "converge", "alpha_range",
+                                           "control"], default="large120")
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32",
                     help="large120: arithmetic of the solve (the headline is FP32)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
@@ -563,6 +681,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload in ("converge", "alpha_range", "control"):
+        return bench_adjacent(args)
     if args.workload == "context":
         return bench_context(args)
     hj.load_library()
