@@ -1293,44 +1293,94 @@ __device__ inline unsigned long long order_key(double x) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+constexpr int kRangeXSeg = 16;  // x planes per thread in the derivative-range pass
+
 template <typename T, int DERIV>
 __global__ __launch_bounds__(256) void deriv_range_kernel(StageArgs<T> a, unsigned long long *keys) {
   __shared__ unsigned long long part[8][4];
-  double lo[4], hi[4];
+  T lo[4], hi[4];  // min and max are exact in T; widened for the keys
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    lo[d] = INFINITY;
-    hi[d] = -INFINITY;
+    lo[d] = T(INFINITY);
+    hi[d] = T(-INFINITY);
   }
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npts; p += (int64_t)gridDim.x * blockDim.x) {
+  // A thread takes an x segment of one (y, v, theta) column: the column's
+  // index is split once and the node moves by one x plane per iteration.
+  // Where every axis's window lies on the grid (or wraps on a periodic
+  // axis) the window values are loads at offsets fixed for the thread, and
+  // the loop is unrolled so that several nodes' loads are in flight at once;
+  // windows that need extrapolated ghosts go through axis_value.  Node
+  // indices fit 32 bits (grids have fewer than 2^31 nodes).
+  constexpr int RW = DERIV == kUpwind1 ? 1 : 2;
+  const int cols = (int)a.st[0];  // n[1] n[2] n[3]
+  const int nx = a.n[0];
+  const int nseg = (nx + kRangeXSeg - 1) / kRangeXSeg;
+  auto reduce = [&](int d, T pm, T pp) {
+    const T mn = pm < pp ? pm : pp, mx = pm < pp ? pp : pm;
+    lo[d] = mn < lo[d] ? mn : lo[d];
+    hi[d] = mx > hi[d] ? mx : hi[d];
+  };
+  for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < (int64_t)cols * nseg;
+       item += (int64_t)gridDim.x * blockDim.x) {
+    const int seg = (int)(item / cols), col = (int)(item - (int64_t)seg * cols);
     int idx[4];
-    int64_t q = p;
-    idx[3] = (int)(q % a.n[3]);
-    q /= a.n[3];
-    idx[2] = (int)(q % a.n[2]);
-    q /= a.n[2];
-    idx[1] = (int)(q % a.n[1]);
-    idx[0] = (int)(q / a.n[1]);
+    idx[3] = col % a.n[3];
+    idx[2] = (col / a.n[3]) % a.n[2];
+    idx[1] = col / (a.n[3] * a.n[2]);
+    int off[4][5];
+    bool direct = true;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      T w[5], pm, pp;
+    for (int d = 1; d < 4; ++d) {
       const bool per = (a.periodic_mask >> d) & 1u;
-      const int R = DERIV == kUpwind1 ? 1 : 2;
+      direct = direct && (per || (idx[d] >= RW && idx[d] + RW < a.n[d]));
 #pragma unroll
-      for (int o = -2; o <= 2; ++o)
-        w[o + 2] = (o < -R || o > R) ? T(0) : axis_value(a.vs, p, idx[d], o, a.n[d], a.st[d], per);
-      one_sided<T, DERIV>(w, a.inv_h[d], pm, pp);
-      double x = (double)pm, y = (double)pp;
-      double mn = x < y ? x : y, mx = x < y ? y : x;
-      lo[d] = mn < lo[d] ? mn : lo[d];
-      hi[d] = mx > hi[d] ? mx : hi[d];
+      for (int o = -2; o <= 2; ++o) {
+        int t = idx[d] + o;
+        t = t < 0 ? t + a.n[d] : (t >= a.n[d] ? t - a.n[d] : t);
+        off[d][o + 2] = (t - idx[d]) * (int)a.st[d];
+      }
+    }
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) off[0][o + 2] = o * cols;
+    const int xa = seg * kRangeXSeg, xb = min(nx, xa + kRangeXSeg);
+    // the x range whose windows are all plain loads
+    const int fa = direct ? max(xa, RW) : xb, fb = direct ? min(xb, nx - RW) : xb;
+    for (int x = xa; x < xb; ++x) {
+      if (x == fa && fa < fb) {
+#pragma unroll 4
+        for (int xf = fa; xf < fb; ++xf) {
+          const int p = xf * cols + col;
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            T w[5], pm, pp;
+#pragma unroll
+            for (int o = -2; o <= 2; ++o) w[o + 2] = (o < -RW || o > RW) ? T(0) : a.vs[p + off[d][o + 2]];
+            one_sided<T, DERIV>(w, a.inv_h[d], pm, pp);
+            reduce(d, pm, pp);
+          }
+        }
+        x = fb - 1;
+        continue;
+      }
+      idx[0] = x;
+      const int p = x * cols + col;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        T w[5], pm, pp;
+        const bool per = (a.periodic_mask >> d) & 1u;
+#pragma unroll
+        for (int o = -2; o <= 2; ++o)
+          w[o + 2] = (o < -RW || o > RW) ? T(0) : axis_value(a.vs, p, idx[d], o, a.n[d], a.st[d], per);
+        one_sided<T, DERIV>(w, a.inv_h[d], pm, pp);
+        reduce(d, pm, pp);
+      }
     }
   }
   // block reduction in key space: min of the lows, max of the highs
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    unsigned long long kl = order_key(lo[d]), kh = order_key(hi[d]);
+    unsigned long long kl = order_key((double)lo[d]), kh = order_key((double)hi[d]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       unsigned long long ol = __shfl_xor(kl, o, 64), oh = __shfl_xor(kh, o, 64);
@@ -1689,8 +1739,9 @@ template hipError_t launch_control<double>(const ControlArgs<double> &, hipStrea
 template <typename T>
 hipError_t launch_deriv_range(const StageArgs<T> &a, int deriv, unsigned long long *keys, hipStream_t s) {
   hipLaunchKernelGGL(range_reset_kernel, dim3(1), dim3(64), 0, s, keys);
-  int64_t blocks = (a.npts + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  const int64_t items = a.st[0] * ((a.n[0] + kRangeXSeg - 1) / kRangeXSeg);  // (column, x segment) pairs
+  int64_t blocks = (items + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
   if (deriv == kUpwind1)
     hipLaunchKernelGGL((deriv_range_kernel<T, kUpwind1>), dim3((unsigned)blocks), dim3(256), 0, s, a, keys);
   else
