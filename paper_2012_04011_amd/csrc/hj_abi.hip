@@ -768,8 +768,8 @@ hj_status range_alpha_update(hj_grid *G, double *dt_allowed) {
   hj_status st0 = ensure_dt(G);  // caches the state-bound step before av is rewritten below
   if (st0 != HJ_OK) return st0;
   if (!G->range_keys) {
-    HJ_HIP(hipMalloc((void **)&G->range_keys, 8 * sizeof(unsigned long long)));
-    HJ_HIP(hipHostMalloc((void **)&G->range_host, 8 * sizeof(unsigned long long), 0));
+    HJ_HIP(hipMalloc((void **)&G->range_keys, 8 * hj::kRangeSlots * sizeof(unsigned long long)));
+    HJ_HIP(hipHostMalloc((void **)&G->range_host, 8 * hj::kRangeSlots * sizeof(unsigned long long), 0));
   }
   if (G->elem == 4) {
     hj::StageArgs<float> a = stage_args<float>(G);
@@ -780,12 +780,18 @@ hj_status range_alpha_update(hj_grid *G, double *dt_allowed) {
     a.vs = buf<const double>(G->v);
     HJ_HIP(hj::launch_deriv_range(a, G->sch.deriv, G->range_keys, S(G)));
   }
-  HJ_HIP(hipMemcpyAsync(G->range_host, G->range_keys, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, S(G)));
+  HJ_HIP(hipMemcpyAsync(G->range_host, G->range_keys, 8 * hj::kRangeSlots * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, S(G)));
   HJ_HIP(hipStreamSynchronize(S(G)));  // also retires the previous update's uploads
   double lo[4], hi[4];
   for (int d = 0; d < 4; ++d) {
-    lo[d] = key_to_double(G->range_host[d]);
-    hi[d] = key_to_double(G->range_host[4 + d]);
+    unsigned long long kl = G->range_host[d], kh = G->range_host[4 + d];
+    for (int k = 1; k < hj::kRangeSlots; ++k) {
+      kl = std::min(kl, G->range_host[8 * k + d]);
+      kh = std::max(kh, G->range_host[8 * k + 4 + d]);
+    }
+    lo[d] = key_to_double(kl);
+    hi[d] = key_to_double(kh);
   }
   const hj_dynamics_desc &dy = G->dyn;
   const int n2 = G->g.n[2], n3 = G->g.n[3];

@@ -180,8 +180,12 @@ int persistent_blocks_per_cu(int deriv, bool sg, bool ball);
 hipError_t launch_batch_reset(BatchQueue *queue, int m, hipStream_t s);
 
 // ---- Algorithm 1's derivative range -----------------------------------------
-// keys[d] / keys[4 + d] = order-preserving keys of the smallest / largest
-// one-sided derivative (p- or p+) on axis d over every node of a.vs.
+// kRangeSlots sets of eight keys: set k holds, over the blocks with
+// blockIdx % kRangeSlots == k, in keys[8k + d] / keys[8k + 4 + d] the
+// order-preserving keys of the smallest / largest one-sided derivative (p-
+// or p+) on axis d over the nodes of a.vs; the caller reduces the sets (the
+// blocks' atomics spread over the sets instead of meeting on eight words).
+constexpr int kRangeSlots = 64;
 template <typename T>
 hipError_t launch_deriv_range(const StageArgs<T> &a, int deriv, unsigned long long *keys, hipStream_t s);
 

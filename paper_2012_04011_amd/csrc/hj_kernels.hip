@@ -1400,16 +1400,14 @@ __global__ __launch_bounds__(256) void deriv_range_kernel(StageArgs<T> a, unsign
       kl = part[d][w] < kl ? part[d][w] : kl;
       kh = part[4 + d][w] > kh ? part[4 + d][w] : kh;
     }
-    atomicMin(&keys[d], kl);
-    atomicMax(&keys[4 + d], kh);
+    unsigned long long *set = keys + 8 * (blockIdx.x % kRangeSlots);
+    atomicMin(&set[d], kl);
+    atomicMax(&set[4 + d], kh);
   }
 }
 
 __global__ void range_reset_kernel(unsigned long long *keys) {
-  if (threadIdx.x < 4) {
-    keys[threadIdx.x] = ~0ull;
-    keys[4 + threadIdx.x] = 0ull;
-  }
+  for (int i = threadIdx.x; i < 8 * kRangeSlots; i += blockDim.x) keys[i] = (i & 7) < 4 ? ~0ull : 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -1738,7 +1736,7 @@ template hipError_t launch_control<float>(const ControlArgs<float> &, hipStream_
 template hipError_t launch_control<double>(const ControlArgs<double> &, hipStream_t);
 template <typename T>
 hipError_t launch_deriv_range(const StageArgs<T> &a, int deriv, unsigned long long *keys, hipStream_t s) {
-  hipLaunchKernelGGL(range_reset_kernel, dim3(1), dim3(64), 0, s, keys);
+  hipLaunchKernelGGL(range_reset_kernel, dim3(1), dim3(256), 0, s, keys);
   const int64_t items = a.st[0] * ((a.n[0] + kRangeXSeg - 1) / kRangeXSeg);  // (column, x segment) pairs
   int64_t blocks = (items + 255) / 256;
   if (blocks > 16384) blocks = 16384;
