@@ -1425,15 +1425,27 @@ __device__ inline double wave_max_d(double x) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void delta_max_kernel(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
-                                                        unsigned long long *acc, const int32_t *skip) {
+                                                        int64_t nvec, unsigned long long *acc, const int32_t *skip) {
   if (skip && *skip) return;
   __shared__ double part[4];
   double m = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double d = fabs((double)a[i] - (double)b[i]);
+  // |a - b| in FP64 (exact for FP32 inputs); NaN counts as infinitely large
+  auto take = [&](T x, T y) {
+    double d = fabs((double)x - (double)y);
     if (d != d) d = INFINITY;
     m = d > m ? d : m;
+  };
+  // nvec 16-byte vectors (both arrays 16-byte aligned, else nvec = 0), then
+  // the remaining elements one by one
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef typename VecT<T, VW>::type V;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    const V x = reinterpret_cast<const V *>(a)[i], y = reinterpret_cast<const V *>(b)[i];
+#pragma unroll
+    for (int j = 0; j < VW; ++j) take(x[j], y[j]);
   }
+  for (int64_t i = nvec * VW + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) take(a[i], b[i]);
   m = wave_max_d(m);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -1703,10 +1715,12 @@ template int persistent_blocks_per_cu<double>(int, bool, bool);
 template <typename T>
 hipError_t launch_delta_max(const T *a, const T *b, int64_t n, unsigned long long *acc, const int32_t *skip,
                             hipStream_t s) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  const int64_t vw = 16 / (int64_t)sizeof(T);
+  const int64_t nvec = (((uintptr_t)a | (uintptr_t)b) & 15) == 0 ? n / vw : 0;
+  int64_t blocks = ((nvec > 0 ? nvec : n) + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(delta_max_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n, acc, skip);
+  hipLaunchKernelGGL(delta_max_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n, nvec, acc, skip);
   return hipGetLastError();
 }
 
