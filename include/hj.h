@@ -223,8 +223,9 @@ hj_status hj_get_profile(hj_grid *g, hj_profile *out);
  * of a step, eps = max over nodes |V_{t+1} - V_t|, is at or above threshold
  * (the printed test is inverted; read as: stop once eps < threshold), at
  * most max_steps steps (>= 1).  The stop test runs on the device after every
- * step; the host looks at it every 32 steps, and steps enqueued past the
- * stop do nothing.  Synchronises.  A grid on which nothing moves takes
+ * step (with the LDS plane kernel, eps is folded into the step's last stage;
+ * otherwise a pass over V_t and V_t+1 computes it); the host looks at it
+ * every 32 steps, and steps enqueued past the stop do nothing.  Synchronises.  A grid on which nothing moves takes
  * steps of one time unit. */
 typedef struct {
   int64_t steps;     /* steps taken */

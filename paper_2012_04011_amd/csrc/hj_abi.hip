@@ -87,6 +87,7 @@ struct hj_grid {
   // convergence mode: the stop flag the stage kernels test (null otherwise)
   const int32_t *skip = nullptr;
   unsigned long long *conv_acc = nullptr;  // device: max |dV| of the step (bits)
+  unsigned long long *eps_acc = nullptr;   // set: the plane kernel's last stage folds max |dV| into it
   int32_t *conv_state = nullptr;           // device: stopped, step count
   double *conv_eps = nullptr;              // device: eps of the last steps
   int32_t *conv_host = nullptr;            // pinned: state
@@ -573,7 +574,8 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
 }
 
 template <typename T>
-hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mode, int clamp, double dt) {
+hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mode, int clamp, double dt,
+                           bool last = false) {
   bool ball = G->ball_mask != 0;
   if (G->kernel > 0) {
     hj::StreamArgs<T> a = stream_args<T>(G);
@@ -584,6 +586,7 @@ hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mod
     a.mode = mode;
     a.clamp = clamp;
     a.dt = (T)dt;
+    if (last && G->kernel == 2) a.eps = G->eps_acc;
     if (G->kernel == 2)
       HJ_HIP(hj::launch_plane(a, G->sch.deriv, ball, S(G)));
     else
@@ -609,13 +612,14 @@ hj_status enqueue_step(hj_grid *G, double dt, int64_t *launches) {
   hj_status st;
   int clamp = G->sch.clamp == HJ_CLAMP_MIN_V0;
   if (G->sch.integrator == HJ_EULER) {
-    st = launch_one_stage<T>(G, buf<const T>(G->v), nullptr, buf<T>(G->w2), hj::kPlain, clamp, dt);
+    st = launch_one_stage<T>(G, buf<const T>(G->v), nullptr, buf<T>(G->w2), hj::kPlain, clamp, dt, true);
     if (st != HJ_OK) return st;
     *launches += 1;
   } else {
-    st = launch_one_stage<T>(G, buf<const T>(G->v), nullptr, buf<T>(G->w1), hj::kPlain, 0, dt);
+    st = launch_one_stage<T>(G, buf<const T>(G->v), nullptr, buf<T>(G->w1), hj::kPlain, 0, dt, false);
     if (st != HJ_OK) return st;
-    st = launch_one_stage<T>(G, buf<const T>(G->w1), buf<const T>(G->v), buf<T>(G->w2), hj::kAverage, clamp, dt);
+    st = launch_one_stage<T>(G, buf<const T>(G->w1), buf<const T>(G->v), buf<T>(G->w2), hj::kAverage, clamp, dt,
+                             true);
     if (st != HJ_OK) return st;
     *launches += 2;
   }
@@ -1264,6 +1268,10 @@ hj_status hj_solve_converge(hj_grid *G, double threshold, int64_t max_steps, hj_
     if ((st = autotune(G)) != HJ_OK) return st;
   HJ_HIP(hj::launch_converge_reset(G->conv_acc, G->conv_state, S(G)));
   G->skip = G->conv_state;
+  // the plane kernel folds each step's largest change into its last stage;
+  // the other kernels leave it to a separate pass over V_t and V_t+1
+  const bool fused = G->kernel == 2;
+  G->eps_acc = fused ? G->conv_acc : nullptr;
   int64_t k = 0, steps = max_steps;
   bool stopped = false;
   double eps_last = 0.0;
@@ -1273,10 +1281,12 @@ hj_status hj_solve_converge(hj_grid *G, double threshold, int64_t max_steps, hj_
     for (int64_t j = 0; j < chunk && st == HJ_OK; ++j) {
       st = step_once(G, dt, &launches);  // reads v, writes w2, swaps: v new, w2 old
       if (st != HJ_OK) break;
-      hipError_t e = G->elem == 4 ? hj::launch_delta_max<float>(buf<const float>(G->v), buf<const float>(G->w2),
-                                                                G->npts, G->conv_acc, G->skip, S(G))
-                                  : hj::launch_delta_max<double>(buf<const double>(G->v), buf<const double>(G->w2),
-                                                                 G->npts, G->conv_acc, G->skip, S(G));
+      hipError_t e = hipSuccess;
+      if (!fused)
+        e = G->elem == 4 ? hj::launch_delta_max<float>(buf<const float>(G->v), buf<const float>(G->w2), G->npts,
+                                                       G->conv_acc, G->skip, S(G))
+                         : hj::launch_delta_max<double>(buf<const double>(G->v), buf<const double>(G->w2), G->npts,
+                                                        G->conv_acc, G->skip, S(G));
       if (e == hipSuccess) e = hj::launch_converge_check(G->conv_acc, threshold, G->conv_state, G->conv_eps, (int)j, k + j, S(G));
       if (e != hipSuccess) st = fail(HJ_ERR_DEVICE, "hj_solve_converge: %s", hipGetErrorString(e));
     }
@@ -1306,6 +1316,7 @@ hj_status hj_solve_converge(hj_grid *G, double threshold, int64_t max_steps, hj_
     k += chunk;
   }
   G->skip = nullptr;
+  G->eps_acc = nullptr;
   if (st != HJ_OK) return st;
   if (info) {
     info->steps = steps;

@@ -84,6 +84,10 @@ struct StreamArgs {
   int32_t mode;
   int32_t clamp;
   const int32_t *skip;  // when non-null and *skip != 0 the launch does nothing
+  // Plane kernel, last stage of a step: when non-null, the largest change of
+  // a node, max |out - V^n| in FP64 (NaN as infinity), is folded in with an
+  // atomic max of its bits (non-negative doubles order as their bits)
+  unsigned long long *eps;
 };
 
 constexpr int kStreamBlock = 256;

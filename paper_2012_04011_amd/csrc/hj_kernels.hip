@@ -681,6 +681,15 @@ __device__ inline void lds_pair(const T *p, T &a, T &b) {
   b = x[1];
 }
 
+__device__ inline double wave_max_d(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
 // SEG: the block holds one v segment [va, va + v_seg) of the plane plus two
 // halo rows on each side (copied from global memory by the first 4 * rpr
 // threads, one plane ahead), for planes with more runs than a block has
@@ -807,6 +816,7 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
   if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
 
+  double em = 0.0;  // largest change of this thread's nodes (when a.eps is set)
   auto plane = [&](auto phase, const int X) {
     constexpr int P = decltype(phase)::value;
     constexpr int I0 = P & 3, I1 = (P + 1) & 3, IF = (P + FR) & 3, IL = (P + FR + 1) & 3;
@@ -971,6 +981,14 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
         for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
       }
     }
+    if (a.eps) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        double d = fabs((double)res[j] - (double)(a.mode == kAverage ? vn[j] : c[j]));
+        if (d != d) d = INFINITY;
+        em = (active && d > em) ? d : em;
+      }
+    }
     if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
   };
 
@@ -985,6 +1003,10 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     plane(std::integral_constant<int, 2>(), X++);
     if (X >= x1) break;
     plane(std::integral_constant<int, 3>(), X++);
+  }
+  if (a.eps) {
+    em = wave_max_d(em);
+    if ((threadIdx.x & 63) == 0) atomicMax(a.eps, (unsigned long long)__double_as_longlong(em));
   }
 }
 
@@ -1413,15 +1435,6 @@ __global__ void range_reset_kernel(unsigned long long *keys) {
 // ---------------------------------------------------------------------------
 // Convergence mode: the largest change of a step, and the stop test.
 // ---------------------------------------------------------------------------
-
-__device__ inline double wave_max_d(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double y = __shfl_xor(x, o, 64);
-    x = y > x ? y : x;
-  }
-  return x;
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void delta_max_kernel(const T *__restrict__ a, const T *__restrict__ b, int64_t n,

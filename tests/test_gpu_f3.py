@@ -144,6 +144,44 @@ def test_converge_cap_equals_plain_steps():
         assert np.array_equal(g.value(np.float64), V)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("deriv,integ", [("eno2", "rk2"), ("upwind1", "euler")])
+def test_converge_fused_eps_equals_separate_pass(monkeypatch, precision, deriv, integ):
+    """The plane kernel folds each step's largest change into its last stage
+    (the whole plane, and a plane split into v segments); the streaming
+    kernel leaves it to a separate pass over V_t and V_t+1.  Every step's
+    eps, the stop and V are bitwise the same either way."""
+    from paper_2012_04011_amd import hj
+
+    sch = W.scheme(deriv, integ)
+    dyn = W.car_dynamics(d_max=0.1)
+    runs = {}
+    monkeypatch.setenv("HJ_X_CHUNKS", "2")  # a fixed launch configuration: no autotuning in between
+    for kernel, vseg in (("stream", None), ("plane", None), ("plane", "4")):
+        if kernel == "stream":
+            monkeypatch.setenv("HJ_STAGE_KERNEL", "stream")
+        else:
+            monkeypatch.delenv("HJ_STAGE_KERNEL", raising=False)
+        if vseg:
+            monkeypatch.setenv("HJ_PLANE_VSEG", vseg)
+        else:
+            monkeypatch.delenv("HJ_PLANE_VSEG", raising=False)
+        with hj.Grid(GRID_C, dyn, sch, precision) as g:
+            info_li = g.launch_info()
+            assert info_li["kernel"] == kernel and (info_li["plane_segments"] > 1) == (vseg is not None)
+            g.set_target_cylinders(*CYL_C)
+            capped = g.solve_converge(0.0, 40)
+            Vc = g.value(np.float64)
+            thr = 0.5 * (capped["eps_last"] + g.solve_converge(0.0, 10)["eps_last"])
+            stop = g.solve_converge(thr, 100)
+            assert g.launch_info()["kernel"] == kernel
+            runs[(kernel, vseg)] = (capped, Vc, stop, g.value(np.float64))
+    ref = runs[("stream", None)]
+    for key, r in runs.items():
+        assert r[0] == ref[0] and r[2] == ref[2], key
+        assert np.array_equal(r[1], ref[1]) and np.array_equal(r[3], ref[3]), key
+
+
 def test_converge_zero_dynamics_one_step():
     from paper_2012_04011_amd import hj
 
