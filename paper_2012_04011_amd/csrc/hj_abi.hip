@@ -775,7 +775,19 @@ hj_status range_alpha_update(hj_grid *G, double *dt_allowed) {
     HJ_HIP(hipMalloc((void **)&G->range_keys, 8 * hj::kRangeSlots * sizeof(unsigned long long)));
     HJ_HIP(hipHostMalloc((void **)&G->range_host, 8 * hj::kRangeSlots * sizeof(unsigned long long), 0));
   }
-  if (G->elem == 4) {
+  // the plane kernel's own traversal where it runs the grid, else the
+  // one-thread-per-column pass
+  if (G->kernel == 2 && G->elem == 4) {
+    hj::StreamArgs<float> a = stream_args<float>(G);
+    a.vs = buf<const float>(G->v);
+    a.range = G->range_keys;
+    HJ_HIP(hj::launch_plane_range(a, G->sch.deriv, S(G)));
+  } else if (G->kernel == 2) {
+    hj::StreamArgs<double> a = stream_args<double>(G);
+    a.vs = buf<const double>(G->v);
+    a.range = G->range_keys;
+    HJ_HIP(hj::launch_plane_range(a, G->sch.deriv, S(G)));
+  } else if (G->elem == 4) {
     hj::StageArgs<float> a = stage_args<float>(G);
     a.vs = buf<const float>(G->v);
     HJ_HIP(hj::launch_deriv_range(a, G->sch.deriv, G->range_keys, S(G)));

@@ -88,6 +88,9 @@ struct StreamArgs {
   // a node, max |out - V^n| in FP64 (NaN as infinity), is folded in with an
   // atomic max of its bits (non-negative doubles order as their bits)
   unsigned long long *eps;
+  // Range pass (plane kernel, RANGE instance): kRangeSlots sets of keys of
+  // the per-axis extremes of the one-sided derivatives (see launch_deriv_range)
+  unsigned long long *range;
 };
 
 constexpr int kStreamBlock = 256;
@@ -190,6 +193,10 @@ hipError_t launch_batch_reset(BatchQueue *queue, int m, hipStream_t s);
 // or p+) on axis d over the nodes of a.vs; the caller reduces the sets (the
 // blocks' atomics spread over the sets instead of meeting on eight words).
 constexpr int kRangeSlots = 64;
+// The same keys from the plane kernel's traversal (grids the plane kernel
+// runs; a.vs = V, a.range = the key sets)
+template <typename T>
+hipError_t launch_plane_range(StreamArgs<T> a, int deriv, hipStream_t s);
 template <typename T>
 hipError_t launch_deriv_range(const StageArgs<T> &a, int deriv, unsigned long long *keys, hipStream_t s);
 

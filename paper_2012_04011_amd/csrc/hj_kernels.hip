@@ -690,11 +690,16 @@ __device__ inline double wave_max_d(double x) {
   return x;
 }
 
+__device__ inline unsigned long long order_key(double x) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
 // SEG: the block holds one v segment [va, va + v_seg) of the plane plus two
 // halo rows on each side (copied from global memory by the first 4 * rpr
 // threads, one plane ahead), for planes with more runs than a block has
 // threads.
-template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG>
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE>
 __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
   if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -816,6 +821,20 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
   if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
 
+  // RANGE: the smallest and largest one-sided difference (unscaled, h p)
+  // per axis over this thread's nodes; nothing is written but the keys
+  T rlo[4], rhi[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    rlo[d] = T(INFINITY);
+    rhi[d] = T(-INFINITY);
+  }
+  auto rng = [&](int d, T pm, T pp) {
+    if (!active) return;
+    const T mn = pm < pp ? pm : pp, mx = pm < pp ? pp : pm;
+    rlo[d] = mn < rlo[d] ? mn : rlo[d];
+    rhi[d] = mx > rhi[d] ? mx : rhi[d];
+  };
   double em = 0.0;  // largest change of this thread's nodes (when a.eps is set)
   auto plane = [&](auto phase, const int X) {
     constexpr int P = decltype(phase)::value;
@@ -884,7 +903,10 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
         pm = D[P & 3][j];
         pp = D[(P + 1) & 3][j];
       }
-      accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
+      if constexpr (RANGE)
+        rng(0, pm, pp);
+      else
+        accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
     }
     __syncthreads();
     // ---- theta: halos from LDS
@@ -920,7 +942,10 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
           pm = e[j + 1];
           pp = e[j + 2];
         }
-        accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
+        if constexpr (RANGE)
+          rng(3, pm, pp);
+        else
+          accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
       }
     }
     // ---- v: neighbours from LDS
@@ -939,8 +964,12 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
         for (int j = 0; j < R; ++j) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pmv[j], ppv[j]);
       }
 #pragma unroll
-      for (int j = 0; j < R; ++j)
-        accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
+      for (int j = 0; j < R; ++j) {
+        if constexpr (RANGE)
+          rng(2, pmv[j], ppv[j]);
+        else
+          accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
+      }
     }
     // ---- y: neighbours from global memory
     T pmy[R], ppy[R];
@@ -952,44 +981,50 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
       for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pmy[j], ppy[j]);
     }
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-      accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
+    for (int j = 0; j < R; ++j) {
+      if constexpr (RANGE)
+        rng(1, pmy[j], ppy[j]);
+      else
+        accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
+    }
     if (X + 1 < x1) {
       if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX + pb, Y[0]);
       bload<T, R>(rs, oy[1], sX + pb, Y[1]);
       bload<T, R>(rs, oy[2], sX + pb, Y[2]);
       if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX + pb, Y[3]);
     }
-    // ---- update
-    T res[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      T Lj = L[j];
-      if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
-      res[j] = fma(a.dt, Lj, c[j]);
-    }
-    if (a.mode == kAverage) {
-#pragma unroll
-      for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
-    }
-    if (a.clamp) {
-      if (a.v0xy) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) res[j] = tv < res[j] ? tv : res[j];
-      } else {
-#pragma unroll
-        for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
-      }
-    }
-    if (a.eps) {
-#pragma unroll
+    if constexpr (!RANGE) {
+      // ---- update
+      T res[R];
+  #pragma unroll
       for (int j = 0; j < R; ++j) {
-        double d = fabs((double)res[j] - (double)(a.mode == kAverage ? vn[j] : c[j]));
-        if (d != d) d = INFINITY;
-        em = (active && d > em) ? d : em;
+        T Lj = L[j];
+        if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
+        res[j] = fma(a.dt, Lj, c[j]);
       }
+      if (a.mode == kAverage) {
+  #pragma unroll
+        for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
+      }
+      if (a.clamp) {
+        if (a.v0xy) {
+  #pragma unroll
+          for (int j = 0; j < R; ++j) res[j] = tv < res[j] ? tv : res[j];
+        } else {
+  #pragma unroll
+          for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+        }
+      }
+      if (a.eps) {
+  #pragma unroll
+        for (int j = 0; j < R; ++j) {
+          double d = fabs((double)res[j] - (double)(a.mode == kAverage ? vn[j] : c[j]));
+          if (d != d) d = INFINITY;
+          em = (active && d > em) ? d : em;
+        }
+      }
+      if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
     }
-    if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
   };
 
   // four planes per trip: every slot index above is a compile-time constant
@@ -1007,6 +1042,26 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   if (a.eps) {
     em = wave_max_d(em);
     if ((threadIdx.x & 63) == 0) atomicMax(a.eps, (unsigned long long)__double_as_longlong(em));
+  }
+  if constexpr (RANGE) {
+    // p = (h p) / h; the scaling is monotone, so the extremes scale as they
+    // are.  Keys per wave into one of kRangeSlots sets.
+    unsigned long long *set = a.range + 8 * ((blockIdx.x * 16 + (threadIdx.x >> 6)) % kRangeSlots);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const T ih = T(2) * a.half_inv_h[d];
+      unsigned long long kl = order_key((double)(rlo[d] * ih)), kh = order_key((double)(rhi[d] * ih));
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ol = __shfl_xor(kl, o, 64), oh = __shfl_xor(kh, o, 64);
+        kl = ol < kl ? ol : kl;
+        kh = oh > kh ? oh : kh;
+      }
+      if ((threadIdx.x & 63) == 0) {
+        atomicMin(&set[d], kl);
+        atomicMax(&set[4 + d], kh);
+      }
+    }
   }
 }
 
@@ -1136,7 +1191,7 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
   return sg ? launch_stream_v<T, DERIV, true, false>(a, s) : launch_stream_v<T, DERIV, false, false>(a, s);
 }
 
-template <typename T, int R, int DERIV, bool SG, bool BALL>
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool RANGE = false>
 hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
   const bool seg = a.n_seg > 1;
   const int rows = seg ? a.v_seg : a.n[2];
@@ -1150,11 +1205,13 @@ hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
   if (lds > (size_t)kPlaneMaxLdsBytes) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)(a.blocks_per_chunk * a.n_chunks);
   if (seg)
-    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, true>), dim3(blocks), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, true, RANGE>), dim3(blocks), dim3(threads), lds, s, a);
   else
-    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, false>), dim3(blocks), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, false, RANGE>), dim3(blocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
+
+
 
 template <typename T, int DERIV, bool SG, bool BALL>
 hipError_t launch_plane_v(const StreamArgs<T> &a, hipStream_t s) {
@@ -1310,10 +1367,6 @@ __global__ void batch_reset_kernel(BatchQueue *q, int m) {
 // all bits flipped for negative ones), so unsigned atomics give min and max.
 // ---------------------------------------------------------------------------
 
-__device__ inline unsigned long long order_key(double x) {
-  unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
 
 constexpr int kRangeXSeg = 16;  // x planes per thread in the derivative-range pass
 
@@ -1790,5 +1843,31 @@ template hipError_t launch_copy<float>(float *, const float *, int64_t, hipStrea
 template hipError_t launch_copy<double>(double *, const double *, int64_t, hipStream_t);
 template hipError_t launch_nonfinite<float>(const float *, int64_t, int32_t *, hipStream_t);
 template hipError_t launch_nonfinite<double>(const double *, int64_t, int32_t *, hipStream_t);
+
+// The derivative-range pass on the plane kernel's traversal (the one-sided
+// differences it computes for a stage, reduced instead of combined): a.vs =
+// V, a.range = kRangeSlots key sets, reset here; nothing else is written.
+template <typename T>
+hipError_t launch_plane_range(StreamArgs<T> a, int deriv, hipStream_t s) {
+  if (!a.range) return hipErrorInvalidValue;
+  a.mode = kPlain;
+  a.clamp = 0;
+  a.eps = nullptr;
+  a.out = nullptr;
+  hipLaunchKernelGGL(range_reset_kernel, dim3(1), dim3(256), 0, s, a.range);
+  auto by_run = [&](auto deriv_c) -> hipError_t {
+    constexpr int D = decltype(deriv_c)::value;
+    if (a.run == 1) return launch_plane_r<T, 1, D, false, false, true>(a, s);
+    if (a.run == 2) return launch_plane_r<T, 2, D, false, false, true>(a, s);
+    if constexpr (sizeof(T) == 4)
+      if (a.run == 4) return launch_plane_r<T, 4, D, false, false, true>(a, s);
+    return hipErrorInvalidValue;
+  };
+  if (deriv == kUpwind1) return by_run(std::integral_constant<int, kUpwind1>());
+  return by_run(std::integral_constant<int, kEno2>());
+}
+
+template hipError_t launch_plane_range<float>(StreamArgs<float>, int, hipStream_t);
+template hipError_t launch_plane_range<double>(StreamArgs<double>, int, hipStream_t);
 
 }  // namespace hj
