@@ -113,3 +113,44 @@ def test_range_alpha_rejected_where_a_fixed_step_is_needed():
     with pytest.raises(hj.HJError) as e:
         hj.Server(sch, "f32")
     assert e.value.status == hj.HJ_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("deriv,integ", [("eno2", "rk2"), ("upwind1", "euler")])
+def test_plane_range_pass_equals_column_pass(monkeypatch, precision, deriv, integ):
+    """On plane-kernel grids the derivative range comes from the plane
+    kernel's own traversal (the whole plane and a plane split into v
+    segments); elsewhere from the one-thread-per-column pass.  The step
+    sizes they give agree to rounding (the ends of the open axes take the
+    closed-form one-sided differences in the one, extrapolated ghosts in the
+    other), and so do the values."""
+    from paper_2012_04011_amd import hj
+
+    grid = W.car_grid(18, 16, 10, 24)
+    dyn = W.car_dynamics(d_max=0.1)
+    sch = W.scheme(deriv, integ, alpha="deriv_range")
+    V0 = oracle.target_cylinders(grid, *W.cylinders(21, 3))
+    monkeypatch.setenv("HJ_X_CHUNKS", "2")
+    out = {}
+    for kernel, vseg in (("stream", None), ("plane", None), ("plane", "4")):
+        if kernel == "stream":
+            monkeypatch.setenv("HJ_STAGE_KERNEL", "stream")
+        else:
+            monkeypatch.delenv("HJ_STAGE_KERNEL", raising=False)
+        if vseg:
+            monkeypatch.setenv("HJ_PLANE_VSEG", vseg)
+        else:
+            monkeypatch.delenv("HJ_PLANE_VSEG", raising=False)
+        with hj.Grid(grid, dyn, sch, precision) as g:
+            li = g.launch_info()
+            assert li["kernel"] == kernel and (li["plane_segments"] > 1) == (vseg is not None)
+            g.set_target(V0)
+            info = g.solve_brt(0.3)
+            out[(kernel, vseg)] = (info, g.value(np.float64))
+    ref_info, ref_v = out[("stream", None)]
+    rel = 1e-5 if precision == "f32" else 1e-12
+    for key, (info, v) in out.items():
+        assert info["steps"] == ref_info["steps"], key
+        assert info["dt"] == pytest.approx(ref_info["dt"], rel=rel), key
+        assert info["dt_last"] == pytest.approx(ref_info["dt_last"], rel=1e-3, abs=1e-9), key
+        assert np.abs(v - ref_v).max() <= (1e-4 if precision == "f32" else 1e-10), key
