@@ -113,8 +113,9 @@ typedef struct {
  * one-sided derivative per axis on the grid, takes alpha_d(z) = max |dH/dp_d|
  * over that box of gradients and dt = cfl / sum_d(alpha_d^max / dx_d), the
  * last step shortened to the horizon; both TVD-RK2 stages use the step's
- * alpha.  It needs a host round trip per step; batches, servers and the
- * convergence mode reject it.
+ * alpha (the range pass runs on the stage kernel's own traversal where the
+ * LDS plane kernel runs the grid).  It needs a host round trip per step;
+ * batches, servers and the convergence mode reject it.
  */
 enum { HJ_ALPHA_STATE = 0, HJ_ALPHA_DERIV_RANGE = 1 };
 
