@@ -492,12 +492,23 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
     for (int j = 0; j < R; ++j) dxm[j] = vx0[j] - wm1[j];
   }
   x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, pre);
+  // y neighbours of the current plane: loaded at the end of the previous
+  // plane, as soon as that plane has used them
+  T Y[4][R];
+  if (DERIV == kEno2) bload<T, R>(rs, oy[0], (uint32_t)x0 * pb, Y[0]);
+  bload<T, R>(rs, oy[1], (uint32_t)x0 * pb, Y[1]);
+  bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
+  if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
 
   for (int X = x0; X < x1; ++X) {
     const uint32_t sX = (uint32_t)X * pb;
     // ---- issue this plane's neighbour loads, then the next front
     T u[R + 4];
-    T vn2[R], vn1[R], vp1[R], vp2[R], yn2[R], yn1[R], yp1[R], yp2[R];
+    T vn2[R], vn1[R], vp1[R], vp2[R];
+    T(&yn2)[R] = Y[0];
+    T(&yn1)[R] = Y[1];
+    T(&yp1)[R] = Y[2];
+    T(&yp2)[R] = Y[3];
     if constexpr (R >= 2) {
       bload_pair<T>(rs, oh[0] * E, sX, u[0], u[1]);
       bload_pair<T>(rs, oh[2] * E, sX, u[R + 2], u[R + 3]);
@@ -511,10 +522,6 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
     bload<T, R>(rs, ov[1], sX, vn1);
     bload<T, R>(rs, ov[2], sX, vp1);
     if (DERIV == kEno2) bload<T, R>(rs, ov[3], sX, vp2);
-    if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX, yn2);
-    bload<T, R>(rs, oy[1], sX, yn1);
-    bload<T, R>(rs, oy[2], sX, yp1);
-    if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX, yp2);
     // pointwise streams of this plane (V^n, V0): issued now, used at the end
     // (the x-y table's value stays one register until the clamp: copying it
     // into t0 here would make the wave wait for every load issued above)
@@ -621,6 +628,12 @@ __device__ inline void stream_tile(const StreamArgs<T> &a, const int lb) {
 #pragma unroll
     for (int j = 0; j < R; ++j)
       accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
+    if (X + 1 < x1) {
+      if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX + pb, Y[0]);
+      bload<T, R>(rs, oy[1], sX + pb, Y[1]);
+      bload<T, R>(rs, oy[2], sX + pb, Y[2]);
+      if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX + pb, Y[3]);
+    }
     // ---- update
     T res[R];
 #pragma unroll
