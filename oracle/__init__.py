@@ -15,7 +15,7 @@ Problem descriptions are plain dicts (see ``paper_2012_04011_amd.workloads``):
              {"kind": "car4d_steer", "a_max": 1.5, "steer_max": pi/18, "wheelbase": 0.3,
               "d_max": (0.0, 0.0)}
     scheme = {"deriv": "upwind1"|"eno2", "integrator": "euler"|"rk2",
-              "clamp": True, "cfl": 0.8, "alpha": "state"|"deriv_range"}
+              "clamp": True, "cfl": 0.8, "alpha": "state"|"deriv_range"|"deriv_range_onesided"}
 
 Arrays are float64 numpy arrays of shape ``n`` in C order [x][y][v][theta].
 """
@@ -108,6 +108,9 @@ def _load():
         lib.hjo_derivs.argtypes = [g, sc, dp, ctypes.c_int32, dp, dp]
         lib.hjo_rhs.argtypes = [g, dy, sc, dp, dp]
         lib.hjo_step.argtypes = [g, dy, sc, dp, dp, ctypes.c_double, dp]
+        lib.hjo_step_f32dec.argtypes = [g, dy, sc, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        dp, dp]
+        lib.hjo_step_f32dec.restype = ctypes.c_int
         lib.hjo_solve.argtypes = [g, dy, sc, dp, ctypes.c_double, dp, P(ctypes.c_int64), dp, dp]
         lib.hjo_solve.restype = ctypes.c_int
         lib.hjo_solve_converge.argtypes = [g, dy, sc, dp, ctypes.c_double, ctypes.c_int64, dp, P(ctypes.c_int64),
@@ -130,7 +133,7 @@ _DERIV = {"upwind1": 0, "eno2": 1}
 _INTEG = {"euler": 0, "rk2": 1}
 _NORM = {"box": 0, "ball": 1}
 _ROLE = {"max": 0, "min": 1}
-_ALPHA = {"state": 0, "deriv_range": 1}
+_ALPHA = {"state": 0, "deriv_range": 1, "deriv_range_onesided": 2}
 
 
 def _grid(grid) -> _Grid:
@@ -263,6 +266,26 @@ def step(grid, dyn, scheme, V0, V, dt: float) -> np.ndarray:
     return out
 
 
+def step_f32_decisions(grid, dyn, scheme, V0, V, dt: float, tau1: float = 0.0, tau2: float = 0.0):
+    """One full step from V whose ENO choices are those a binary32 evaluation
+    takes (decided on binary32 second differences; all other arithmetic
+    binary64).  Returns (lo, hi): per node the smallest and largest result
+    over the choices left open -- those within tau * max(1, |window|) of a
+    tie, tau1 in the first stage, tau2 in the second TVD-RK2 stage (tau1 must
+    be 0 with TVD-RK2)."""
+    V0 = _f64(V0, _shape(grid))
+    V = _f64(V, _shape(grid))
+    lo = np.empty_like(V)
+    hi = np.empty_like(V)
+    rc = _load().hjo_step_f32dec(ctypes.byref(_grid(grid)), ctypes.byref(_dyn(dyn)), ctypes.byref(_scheme(scheme)),
+                                 _dptr(V0), _dptr(V), float(dt), float(tau1), float(tau2), _dptr(lo), _dptr(hi))
+    if rc == -2:
+        raise ValueError("tau1 > 0 needs a one-stage (Euler) step")
+    if rc != 0:
+        raise MemoryError("oracle step: out of memory")
+    return lo, hi
+
+
 def solve(grid, dyn, scheme, V0, horizon: float):
     """Fixed-horizon solve; returns (V, info) with info = {steps, dt, dt_last}."""
     V0 = _f64(V0, _shape(grid))
@@ -314,7 +337,9 @@ def optimal_control(grid, dyn, V, states):
 
 
 def deriv_range(grid, scheme, V):
-    """(pmin, pmax): smallest and largest one-sided derivative per axis."""
+    """(pmin, pmax) per axis: Algorithm 1's minDeriv / maxDeriv, over the
+    central derivative (alpha "deriv_range") or over both one-sided
+    derivatives (alpha "deriv_range_onesided")."""
     V = _f64(V, _shape(grid))
     lo, hi = np.empty(4), np.empty(4)
     _load().hjo_deriv_range(ctypes.byref(_grid(grid)), ctypes.byref(_scheme(scheme)), _dptr(V), _dptr(lo), _dptr(hi))

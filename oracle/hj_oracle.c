@@ -77,11 +77,17 @@ typedef struct {
 } hjo_dyn;
 
 /* alpha_mode: HJO_ALPHA_STATE = alpha_d(z) bounds |f_d| over every input
- * (state-local, the default); HJO_ALPHA_DERIV_RANGE = Algorithm 1's global
- * Lax-Friedrichs: alpha_d(z) = max |dH/dp_d (z, p)| over the box of
- * gradients spanned, axis by axis, by the smallest and largest one-sided
- * derivative on the grid, recomputed every step together with dt. */
-enum { HJO_ALPHA_STATE = 0, HJO_ALPHA_DERIV_RANGE = 1 };
+ * (state-local, the default).  The other two are Algorithm 1's global
+ * Lax-Friedrichs: alpha_d(z) = max |dH/dp_d (z, p)| over a box of gradients
+ * found on the grid, axis by axis, recomputed every step together with dt.
+ *   HJO_ALPHA_DERIV_RANGE: the box spans the smallest and largest central
+ *     derivative D_d V = (D+ V + D- V) / 2 of eq (5) over the nodes, as
+ *     Algorithm 1 prints it (the gradient at which H is evaluated).
+ *   HJO_ALPHA_DERIV_RANGE_ONESIDED: the box spans every one-sided derivative
+ *     (D- and D+ together), the textbook global Lax-Friedrichs bound: the
+ *     numerical Hamiltonian is then monotone over every pair of one-sided
+ *     values the grid holds, not only at each node's own average. */
+enum { HJO_ALPHA_STATE = 0, HJO_ALPHA_DERIV_RANGE = 1, HJO_ALPHA_DERIV_RANGE_ONESIDED = 2 };
 
 typedef struct {
   int32_t deriv, integrator, clamp, alpha_mode;
@@ -346,8 +352,9 @@ void hjo_derivs(const hjo_grid *g, const hjo_scheme *sc, const double *V, int32_
 /* L(V)(z) = H(z, (p+ + p-)/2) + sum_d alpha_d(z) (p+_d - p-_d) / 2. */
 /* ---------------------------------- Algorithm 1: derivative-range alpha --- */
 
-/* Smallest and largest one-sided derivative (p- and p+ together) per axis
- * over every node of V. */
+/* Algorithm 1's minDeriv / maxDeriv per axis over every node of V: of the
+ * central derivative (D+ + D-) / 2 (HJO_ALPHA_DERIV_RANGE), or of the two
+ * one-sided derivatives together (HJO_ALPHA_DERIV_RANGE_ONESIDED). */
 void hjo_deriv_range(const hjo_grid *g, const hjo_scheme *sc, const double *V, double pmin[4], double pmax[4]) {
   int64_t st[4];
   strides_of(g, st);
@@ -362,7 +369,13 @@ void hjo_deriv_range(const hjo_grid *g, const hjo_scheme *sc, const double *V, d
     for (int d = 0; d < 4; ++d) {
       double a, b;
       one_sided(g, sc->deriv, V, st, p, idx, d, &a, &b);
-      double lo = a < b ? a : b, hi = a < b ? b : a;
+      double lo, hi;
+      if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE_ONESIDED) {
+        lo = a < b ? a : b;
+        hi = a < b ? b : a;
+      } else {
+        lo = hi = (b + a) / 2.0; /* D_d V of eq (5) */
+      }
       if (lo < pmin[d]) pmin[d] = lo;
       if (hi > pmax[d]) pmax[d] = hi;
     }
@@ -445,23 +458,31 @@ void hjo_alpha_max_box(const hjo_grid *g, const hjo_dyn *dy, const double pmin[4
   }
 }
 
+/* L = H(z, (p+ + p-)/2) + sum_d alpha_d (p+_d - p-_d) / 2 from the one-sided
+ * derivatives of one node. */
+static double lf_combine(const hjo_dyn *dy, const double z[4], const double alpha[4], const double pm[4],
+                         const double pp[4]) {
+  double pbar[4];
+  for (int d = 0; d < 4; ++d) pbar[d] = (pp[d] + pm[d]) / 2.0;
+  double diss = 0.0;
+  for (int d = 0; d < 4; ++d) diss += alpha[d] * (pp[d] - pm[d]) / 2.0;
+  return hamiltonian(dy, z, pbar) + diss;
+}
+
 static double rhs_at(const hjo_grid *g, const hjo_dyn *dy, int deriv, const double *V,
                      const int64_t st[4], int64_t p, const double *box) {
   int idx[4];
-  double z[4], pm[4], pp[4], pbar[4], alpha[4];
+  double z[4], pm[4], pp[4], alpha[4];
   unravel(g, p, idx);
   for (int d = 0; d < 4; ++d) {
     z[d] = hjo_node(g, d, idx[d]);
     one_sided(g, deriv, V, st, p, idx, d, &pm[d], &pp[d]);
-    pbar[d] = (pp[d] + pm[d]) / 2.0;
   }
   if (box)
     hjo_alpha_box(dy, z, box, box + 4, alpha);
   else
     alpha_at(dy, z, alpha);
-  double diss = 0.0;
-  for (int d = 0; d < 4; ++d) diss += alpha[d] * (pp[d] - pm[d]) / 2.0;
-  return hamiltonian(dy, z, pbar) + diss;
+  return lf_combine(dy, z, alpha, pm, pp);
 }
 
 /* L(V) at every node (outermost axis split across OpenMP threads; every
@@ -483,8 +504,9 @@ static void rhs_all(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, 
 void hjo_rhs(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V,
              double *L) {
   double box[8];
-  if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE) hjo_deriv_range(g, sc, V, box, box + 4);
-  rhs_all(g, dy, sc, V, sc->alpha_mode == HJO_ALPHA_DERIV_RANGE ? box : NULL, L);
+  int range = sc->alpha_mode != HJO_ALPHA_STATE;
+  if (range) hjo_deriv_range(g, sc, V, box, box + 4);
+  rhs_all(g, dy, sc, V, range ? box : NULL, L);
 }
 
 /* ------------------------------------------------------------- steps --- */
@@ -522,8 +544,193 @@ static void step_with(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc
 void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0, double *V,
               double dt, double *work) {
   double box[8];
-  if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE) hjo_deriv_range(g, sc, V, box, box + 4);
-  step_with(g, dy, sc, V0, V, dt, sc->alpha_mode == HJO_ALPHA_DERIV_RANGE ? box : NULL, work);
+  int range = sc->alpha_mode != HJO_ALPHA_STATE;
+  if (range) hjo_deriv_range(g, sc, V, box, box + 4);
+  step_with(g, dy, sc, V0, V, dt, range ? box : NULL, work);
+}
+
+/* ------------------------- ENO choices as a binary32 evaluation takes them --- */
+
+/*
+ * The ENO choice is a comparison of two second differences, so where they are
+ * close in magnitude the rounding of the arithmetic decides it.  To check a
+ * binary32 (FP32) evaluation node by node, these functions take that decision
+ * in binary32 as well: the window values rounded to binary32 (ghosts
+ * extrapolated in binary32 by the rule of value_at), first and second
+ * differences formed in binary32 in the same divided-difference form,
+ * magnitudes compared, ties to the left.  Everything else -- the value of the
+ * chosen second difference, the derivatives, H, the dissipation, the update --
+ * stays binary64, as in the rest of this file.
+ */
+
+/* value_at in binary32: the node's value rounded to binary32, ghosts formed
+ * from the rounded end values in binary32 arithmetic. */
+static float value_at_f32(const hjo_grid *g, const double *V, const int64_t st[4], int64_t p, const int idx[4],
+                          int d, int off) {
+  int n = g->n[d];
+  int i = idx[d] + off;
+  int64_t base = p - (int64_t)idx[d] * st[d];
+  if (i >= 0 && i < n) return (float)V[base + (int64_t)i * st[d]];
+  if (is_periodic(g, d)) {
+    i = ((i % n) + n) % n;
+    return (float)V[base + (int64_t)i * st[d]];
+  }
+  if (i < 0) {
+    float e = (float)V[base], nx = (float)V[base + st[d]];
+    return e + (float)(-i) * (e - nx);
+  }
+  float e = (float)V[base + (int64_t)(n - 1) * st[d]], nx = (float)V[base + (int64_t)(n - 2) * st[d]];
+  return e + (float)(i - (n - 1)) * (e - nx);
+}
+
+/*
+ * One-sided derivatives along axis d with the ENO choices a binary32
+ * evaluation takes.  A choice is "open" when tau > 0 and the binary32
+ * magnitudes differ by at most tau * max(1, largest |window value|): inputs
+ * that differ from these by that much rounding may take either side.  An open
+ * choice returns both candidates: pm[0 .. *nm), pp[0 .. *np) hold one or two
+ * values each.  First-order upwind has no choice.
+ */
+static void one_sided_f32dec(const hjo_grid *g, int deriv, const double *V, const int64_t st[4], int64_t p,
+                             const int idx[4], int d, double tau, double pm[2], int *nm, double pp[2], int *np) {
+  if (deriv == HJO_UPWIND1) {
+    one_sided(g, deriv, V, st, p, idx, d, &pm[0], &pp[0]);
+    *nm = *np = 1;
+    return;
+  }
+  double h = hjo_spacing(g, d);
+  double w[5];
+  float f[5];
+  for (int k = -2; k <= 2; ++k) {
+    w[k + 2] = value_at(g, V, st, p, idx, d, k);
+    f[k + 2] = value_at_f32(g, V, st, p, idx, d, k);
+  }
+  double d0 = w[1] - w[0], d1 = w[2] - w[1], d2 = w[3] - w[2], d3 = w[4] - w[3];
+  double q_left = d1 - d0, q_mid = d2 - d1, q_right = d3 - d2;
+  float e0 = f[1] - f[0], e1 = f[2] - f[1], e2 = f[3] - f[2], e3 = f[4] - f[3];
+  float r_left = e1 - e0, r_mid = e2 - e1, r_right = e3 - e2;
+  double scale = 1.0;
+  for (int k = 0; k < 5; ++k)
+    if (fabs((double)f[k]) > scale) scale = fabs((double)f[k]);
+  double margin = tau * scale;
+  /* p-: Q_{i-1} against Q_i */
+  int left = fabsf(r_left) <= fabsf(r_mid);
+  int open = tau > 0.0 && fabs((double)fabsf(r_left) - (double)fabsf(r_mid)) <= margin;
+  pm[0] = d1 / h + (left ? q_left : q_mid) / (2.0 * h);
+  *nm = 1;
+  if (open) {
+    pm[1] = d1 / h + (left ? q_mid : q_left) / (2.0 * h);
+    *nm = 2;
+  }
+  /* p+: Q_i against Q_{i+1} */
+  left = fabsf(r_mid) <= fabsf(r_right);
+  open = tau > 0.0 && fabs((double)fabsf(r_mid) - (double)fabsf(r_right)) <= margin;
+  pp[0] = d2 / h - (left ? q_mid : q_right) / (2.0 * h);
+  *np = 1;
+  if (open) {
+    pp[1] = d2 / h - (left ? q_right : q_mid) / (2.0 * h);
+    *np = 2;
+  }
+}
+
+/*
+ * Smallest and largest L(V) at one node over its open choices.  L is
+ * nondecreasing in every p+_d and nonincreasing in every p-_d, because
+ * alpha_d bounds |dH/dp_d| (dL/dp+_d = (dH/dp_d + alpha_d) / 2 >= 0,
+ * dL/dp-_d = (dH/dp_d - alpha_d) / 2 <= 0): the smallest L takes on every
+ * axis the smallest p+ and the largest p-, the largest L the reverse.
+ */
+static void rhs_interval_at(const hjo_grid *g, const hjo_dyn *dy, int deriv, const double *V, const int64_t st[4],
+                            int64_t p, const double *box, double tau, double *Llo, double *Lhi) {
+  int idx[4];
+  double z[4], alpha[4], pm_lo[4], pm_hi[4], pp_lo[4], pp_hi[4];
+  unravel(g, p, idx);
+  for (int d = 0; d < 4; ++d) {
+    double pm[2], pp[2];
+    int nm, np;
+    z[d] = hjo_node(g, d, idx[d]);
+    one_sided_f32dec(g, deriv, V, st, p, idx, d, tau, pm, &nm, pp, &np);
+    pm_lo[d] = pm_hi[d] = pm[0];
+    if (nm == 2) {
+      if (pm[1] < pm_lo[d]) pm_lo[d] = pm[1];
+      if (pm[1] > pm_hi[d]) pm_hi[d] = pm[1];
+    }
+    pp_lo[d] = pp_hi[d] = pp[0];
+    if (np == 2) {
+      if (pp[1] < pp_lo[d]) pp_lo[d] = pp[1];
+      if (pp[1] > pp_hi[d]) pp_hi[d] = pp[1];
+    }
+  }
+  if (box)
+    hjo_alpha_box(dy, z, box, box + 4, alpha);
+  else
+    alpha_at(dy, z, alpha);
+  *Llo = lf_combine(dy, z, alpha, pm_hi, pp_lo);
+  *Lhi = lf_combine(dy, z, alpha, pm_lo, pp_hi);
+}
+
+/*
+ * One full step (as hjo_step, from V, leaving V unchanged) with the ENO
+ * choices of a binary32 evaluation; lo[p], hi[p] = the smallest and largest
+ * result at node p over its open choices (equal where none is open).  tau1
+ * opens the choices of the first (or only) stage, taken on the caller's V;
+ * tau2 those of the second TVD-RK2 stage, taken on V1 rounded to binary32 (a
+ * binary32 evaluation stores V1 so, and its V1 differs from this one by its
+ * rounding).  With TVD-RK2, tau1 must be 0: a first-stage choice left open
+ * would give V1 an interval at a node whose neighbours' second-stage windows
+ * hold it, and ENO2 is not monotone in its window.  Returns 0, -1 if memory
+ * runs out, -2 for tau1 > 0 with TVD-RK2.
+ */
+int hjo_step_f32dec(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0, const double *V,
+                    double dt, double tau1, double tau2, double *lo, double *hi) {
+  if (sc->integrator == HJO_TVD_RK2 && tau1 > 0.0) return -2;
+  int64_t np = hjo_num_points(g);
+  int64_t st[4];
+  strides_of(g, st);
+  double box[8];
+  int range = sc->alpha_mode != HJO_ALPHA_STATE;
+  if (range) hjo_deriv_range(g, sc, V, box, box + 4);
+  const double *bx = range ? box : NULL;
+  int n0 = g->n[0];
+  if (sc->integrator == HJO_EULER) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n0; ++i)
+      for (int64_t q = 0; q < st[0]; ++q) {
+        int64_t p = (int64_t)i * st[0] + q;
+        double a, b;
+        rhs_interval_at(g, dy, sc->deriv, V, st, p, bx, tau1, &a, &b);
+        lo[p] = V[p] + dt * a;
+        hi[p] = V[p] + dt * b;
+      }
+  } else {
+    double *V1 = (double *)malloc((size_t)np * sizeof(double));
+    if (!V1) return -1;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n0; ++i)
+      for (int64_t q = 0; q < st[0]; ++q) {
+        int64_t p = (int64_t)i * st[0] + q;
+        double a, b;
+        rhs_interval_at(g, dy, sc->deriv, V, st, p, bx, 0.0, &a, &b);
+        V1[p] = V[p] + dt * a;
+      }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n0; ++i)
+      for (int64_t q = 0; q < st[0]; ++q) {
+        int64_t p = (int64_t)i * st[0] + q;
+        double a, b;
+        rhs_interval_at(g, dy, sc->deriv, V1, st, p, bx, tau2, &a, &b);
+        double v2a = V1[p] + dt * a, v2b = V1[p] + dt * b;
+        lo[p] = (V[p] + v2a) / 2.0;
+        hi[p] = (V[p] + v2b) / 2.0;
+      }
+    free(V1);
+  }
+  if (sc->clamp)
+    for (int64_t p = 0; p < np; ++p) {
+      if (V0[p] < lo[p]) lo[p] = V0[p];
+      if (V0[p] < hi[p]) hi[p] = V0[p];
+    }
+  return 0;
 }
 
 /*
@@ -534,7 +741,7 @@ void hjo_step(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const 
 int hjo_solve(const hjo_grid *g, const hjo_dyn *dy, const hjo_scheme *sc, const double *V0,
               double horizon, double *V, int64_t *n_steps, double *dt_out, double *dt_last_out) {
   int64_t np = hjo_num_points(g);
-  if (sc->alpha_mode == HJO_ALPHA_DERIV_RANGE) {
+  if (sc->alpha_mode != HJO_ALPHA_STATE) {
     /* Algorithm 1: every step finds the derivative range, alpha and
      * dt = cfl / sum_d(alpha_d^max / dx_d); the step that would reach or pass
      * the horizon is shortened to end on it */

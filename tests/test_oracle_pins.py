@@ -795,3 +795,174 @@ def test_deriv_range_equals_state_bound_when_gradients_span_zero(oracle_lib, sch
     V2, i2 = oracle_lib.solve(g, dyn, sch, V0, 0.6)
     assert i1["steps"] == i2["steps"] and i1["dt"] == i2["dt"]
     assert np.abs(V1 - V2).max() < 1e-12
+
+
+def test_deriv_range_central_vs_onesided_sawtooth_periodic(oracle_lib):
+    """Algorithm 1 takes minDeriv / maxDeriv over the central derivative
+    D_d V = (D+ + D-) / 2 of eq (5); the one-sided option over D- and D+
+    together.  On a periodic axis with V_i = b (-1)^i (N even) every central
+    difference is 0 while the one-sided ones are +-2b/h.  With z' = 0.5 + u
+    on x, |u| <= 1 minimising (u = -1 where p >= 0, +1 where p < 0), the
+    central box [0, 0] gives alpha_x = |0.5 - 1| = 0.5; the one-sided box
+    [-2b/h, 2b/h] also admits u = +1, alpha_x = 1.5.  Nothing else moves,
+    so dt = 0.8 h / alpha_x."""
+    g = {"n": (8, 4, 3, 6), "lo": (0.0, -1.0, 0.0, -math.pi), "hi": (8.0, 1.0, 2.0, math.pi),
+         "periodic_mask": 1 | 8}
+    h, b = 1.0, 0.25
+    saw = b * (-1.0) ** np.arange(8)
+    V0 = np.broadcast_to(saw[:, None, None, None], g["n"]).copy()
+    dyn = drift_dyn((0.5, 0, 0, 0), (0,), 1.0, "box", "min")
+    central = W.scheme("upwind1", "euler", clamp=False, alpha="deriv_range")
+    onesided = dict(central, alpha="deriv_range_onesided")
+    lo, hi = oracle_lib.deriv_range(g, central, V0)
+    assert lo[0] == 0.0 and hi[0] == 0.0
+    lo, hi = oracle_lib.deriv_range(g, onesided, V0)
+    assert lo[0] == -2 * b / h and hi[0] == 2 * b / h
+    _, ic = oracle_lib.solve(g, dyn, central, V0, 10.0)
+    _, io = oracle_lib.solve(g, dyn, onesided, V0, 10.0)
+    assert ic["dt"] == pytest.approx(0.8 * h / 0.5, rel=1e-15)
+    assert io["dt"] == pytest.approx(0.8 * h / 1.5, rel=1e-15)
+
+
+def test_deriv_range_central_vs_onesided_ball_open_axes(oracle_lib):
+    """V = a x + b (-1)^i + c y on open x, y axes (N_x even; linear
+    extrapolation ghosts): interior central x-differences are a, the end
+    nodes' (both one-sided differences equal there) a - 2b/h; interior
+    one-sided ones a +- 2b/h.  So the central x box is [a - 2b/h, a], the
+    one-sided one [a - 2b/h, a + 2b/h]; y is c everywhere.  With a
+    maximising unit-ball input on (x, y) and no drift, dH/dp_x = p_x / |p|,
+    largest at the box's largest p_x and smallest |p_y|: alpha_x = M /
+    sqrt(M^2 + c^2), M = a (central) or a + 2b/h (one-sided); alpha_y =
+    c / sqrt(c^2 + (a - 2b/h)^2) either way.  dt = 0.8 / (alpha_x / h_x +
+    alpha_y / h_y)."""
+    nx = 10
+    g = {"n": (nx, 5, 3, 4), "lo": (-2.0, -1.0, 0.0, -math.pi), "hi": (2.5, 1.0, 2.0, math.pi),
+         "periodic_mask": 8}
+    hx, hy = 4.5 / (nx - 1), 2.0 / 4
+    a, c = 1.0, 1.0
+    b = 0.25 * hx  # 2b/h = 0.5
+    x, y = oracle_lib.nodes(g, 0), oracle_lib.nodes(g, 1)
+    V0 = (a * x + b * (-1.0) ** np.arange(nx))[:, None, None, None] + c * y[None, :, None, None] \
+        + np.zeros(g["n"])
+    dyn = drift_dyn((0, 0, 0, 0), (0, 1), 1.0, "ball", "max")
+    central = W.scheme("upwind1", "euler", clamp=False, alpha="deriv_range")
+    onesided = dict(central, alpha="deriv_range_onesided")
+    for sch, M in ((central, a), (onesided, a + 0.5)):
+        lo, hi = oracle_lib.deriv_range(g, sch, V0)
+        np.testing.assert_allclose([lo[0], hi[0], lo[1], hi[1]], [a - 0.5, M, c, c], rtol=0, atol=1e-12)
+        ax = M / math.sqrt(M * M + c * c)
+        ay = c / math.sqrt(c * c + (a - 0.5) ** 2)
+        _, info = oracle_lib.solve(g, dyn, sch, V0, 5.0)
+        assert info["dt"] == pytest.approx(0.8 / (ax / hx + ay / hy), rel=1e-12), sch["alpha"]
+
+
+# ------------------------- ENO choices taken in binary32 (FP32 parity checks) ---
+
+
+def _line_grid(nx=8, ny=3):
+    return {"n": (nx, ny, 3, 4), "lo": (0.0, 0.0, 0.0, -math.pi), "hi": (nx - 1.0, ny - 1.0, 2.0, math.pi),
+            "periodic_mask": 8}
+
+
+def _along_x(grid, prof):
+    return np.broadcast_to(np.asarray(prof, dtype=float)[:, None, None, None], grid["n"]).copy()
+
+
+@pytest.mark.parametrize("integ", ["euler", "rk2"])
+def test_f32_decisions_upwind_has_no_choice(oracle_lib, integ):
+    """First-order upwind takes no discrete choice: the binary32-decision step
+    is the plain step, bit for bit, and its interval is a point."""
+    g = W.car_grid(9, 8, 5, 8)
+    dyn = W.car_dynamics(d_max=0.1)
+    sch = W.scheme("upwind1", integ)
+    V0 = oracle_lib.target_cylinders(g, *W.cylinders(3, 2))
+    V = (V0 + 0.05 * np.random.default_rng(5).standard_normal(V0.shape)).astype(np.float32).astype(float)
+    lo, hi = oracle_lib.step_f32_decisions(g, dyn, sch, V0, V, 0.05, 0.0, 1e-5)
+    ref = oracle_lib.step(g, dyn, sch, V0, V, 0.05)
+    assert np.array_equal(lo, ref) and np.array_equal(hi, ref)
+
+
+def test_f32_decisions_equal_f64_where_binary32_is_exact(oracle_lib):
+    """Multiples of 1/64 below 2^10: every first and second difference is
+    exact in binary32, so binary32 takes the binary64 choices and the step
+    equals the plain ENO2 step bit for bit."""
+    g = W.car_grid(9, 8, 5, 8)
+    dyn = W.car_dynamics(d_max=0.1)
+    sch = W.scheme("eno2", "euler")
+    V = np.random.default_rng(8).integers(-256, 256, size=g["n"]) / 64.0
+    lo, hi = oracle_lib.step_f32_decisions(g, dyn, sch, V, V, 0.03)
+    ref = oracle_lib.step(g, dyn, sch, V, V, 0.03)
+    assert np.array_equal(lo, ref) and np.array_equal(hi, ref)
+
+
+def test_f32_decisions_binary32_tie(oracle_lib):
+    """An exact binary32 tie that binary64 does not see.  Along x (h = 1) the
+    values ... 0, -2^-30, 1, 1.5, 2.5 ... around node 3: binary64 has
+    Q_3 = 0.5 - (1 + 2^-30) = -0.5 - 2^-30 and Q_4 = 0.5, so |Q_3| > |Q_4|
+    and p+ takes Q_4; in binary32 1 + 2^-30 rounds to 1, Q_3 = -0.5 ties with
+    Q_4 and the tie takes the left one, Q_3.  With z' = 0.5 on x only, L =
+    0.5 p+ (upwind), p+ = (V_4 - V_3) - c+/2: binary64 p+ = 0.25, binary32
+    p+ = 0.75 + 2^-31; one Euler step of 0.5 from V_3 = 1 gives 1.0625 and
+    1.1875 + 2^-33."""
+    assert np.float32(1.0) - np.float32(-(2.0 ** -30)) == np.float32(1.0)  # the rounding that makes the tie
+    g = _line_grid()
+    V = _along_x(g, [0.0, 0.0, -(2.0 ** -30), 1.0, 1.5, 2.5, 3.5, 4.5])
+    dyn = {"kind": "drift_input", "drift": (0.5, 0.0, 0.0, 0.0), "in_axes": (), "in_speed": 0.0,
+           "in_norm": "box", "in_role": "max"}
+    sch = W.scheme("eno2", "euler", clamp=False)
+    lo, hi = oracle_lib.step_f32_decisions(g, dyn, sch, V, V, 0.5)
+    ref = oracle_lib.step(g, dyn, sch, V, V, 0.5)
+    assert np.all(lo[3] == 1.1875 + 2.0 ** -33) and np.all(hi[3] == lo[3])
+    assert np.all(ref[3] == 1.0625)
+
+
+def test_f32_decisions_open_choice_interval(oracle_lib):
+    """A binary32 margin of 2^-20 (Q_3 = -0.5 - 2^-30 against Q_4 = 0.5 +
+    2^-20): closed (tau = 0) binary32 takes Q_3, the value 1.1875 + 2^-33; left
+    open (tau = 1e-6 > 2^-20 / 2.5) the interval spans both candidates, p+ in
+    {0.75 + 2^-31, 0.25 - 2^-21}: [1.0625 - 2^-23, 1.1875 + 2^-33]."""
+    g = _line_grid()
+    V = _along_x(g, [0.0, 0.0, -(2.0 ** -30), 1.0, 1.5, 2.5 + 2.0 ** -20, 3.5, 4.5])
+    dyn = {"kind": "drift_input", "drift": (0.5, 0.0, 0.0, 0.0), "in_axes": (), "in_speed": 0.0,
+           "in_norm": "box", "in_role": "max"}
+    sch = W.scheme("eno2", "euler", clamp=False)
+    lo, hi = oracle_lib.step_f32_decisions(g, dyn, sch, V, V, 0.5)
+    assert np.all(lo[3] == 1.1875 + 2.0 ** -33) and np.all(hi[3] == lo[3])
+    lo, hi = oracle_lib.step_f32_decisions(g, dyn, sch, V, V, 0.5, tau1=1e-6)
+    assert np.all(lo[3] == 1.0625 - 2.0 ** -23) and np.all(hi[3] == 1.1875 + 2.0 ** -33)
+    with pytest.raises(ValueError):
+        oracle_lib.step_f32_decisions(g, dyn, W.scheme("eno2", "rk2"), V, V, 0.5, tau1=1e-6)
+
+
+def test_f32_decisions_interval_corners_ball(oracle_lib):
+    """The interval's ends are the corners of the open choices (L rises with
+    every p+ and falls with every p-), also for the non-separable ball
+    Hamiltonian: with open p+ choices on both x and y at node (3, 3), the
+    ends equal the smallest and largest of the four combinations evaluated
+    from the definition H = drift . pbar - s |pbar_xy| (a minimising unit
+    ball), alpha_d = |drift_d| + s."""
+    prof = np.array([0.0, 0.0, -(2.0 ** -30), 1.0, 1.5, 2.5 + 2.0 ** -20, 3.5, 4.5])
+    g = _line_grid(8, 8)
+    V = np.broadcast_to(prof[:, None, None, None] + 0.5 * prof[None, :, None, None], g["n"]).copy()
+    drift = (0.3, -0.2, 0.0, 0.0)
+    dyn = {"kind": "drift_input", "drift": drift, "in_axes": (0, 1), "in_speed": 1.0, "in_norm": "ball",
+           "in_role": "min"}
+    sch = W.scheme("eno2", "euler", clamp=False)
+    dt = 0.1
+    lo, hi = oracle_lib.step_f32_decisions(g, dyn, sch, V, V, dt, tau1=1e-6)
+    # one-sided differences at node 3 of the profile (h = 1): p- takes Q_3 (|Q_2| > |Q_3|);
+    # p+ candidates Q_3 = -0.5 - 2^-30 and Q_4 = 0.5 + 2^-20
+    d1, d2 = 1.0 + 2.0 ** -30, 0.5
+    q3, q4 = d2 - d1, (1.0 + 2.0 ** -20) - d2
+    pm = d1 + q3 / 2
+    cands = [d2 - q3 / 2, d2 - q4 / 2]
+    vals = []
+    for ppx in cands:
+        for ppy in cands:
+            p_plus, p_minus = np.array([ppx, 0.5 * ppy]), np.array([pm, 0.5 * pm])
+            pbar = (p_plus + p_minus) / 2
+            H = drift[0] * pbar[0] + drift[1] * pbar[1] - math.hypot(pbar[0], pbar[1])
+            al = np.array([abs(drift[0]) + 1.0, abs(drift[1]) + 1.0])
+            vals.append(V[3, 3, 0, 0] + dt * (H + float(np.sum(al * (p_plus - p_minus) / 2))))
+    np.testing.assert_allclose(lo[3, 3], min(vals), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(hi[3, 3], max(vals), rtol=0, atol=1e-14)
