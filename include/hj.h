@@ -109,15 +109,20 @@ typedef struct {
  * alpha_mode: HJ_ALPHA_STATE (default): the dissipation coefficient
  * alpha_d(z) bounds |f_d| over every input, fixed per grid, one CFL step
  * for the whole solve.  HJ_ALPHA_DERIV_RANGE (Algorithm 1, the general
- * Lax-Friedrichs scheme): every step first finds the smallest and largest
- * one-sided derivative per axis on the grid, takes alpha_d(z) = max |dH/dp_d|
- * over that box of gradients and dt = cfl / sum_d(alpha_d^max / dx_d), the
- * last step shortened to the horizon; both TVD-RK2 stages use the step's
- * alpha (the range pass runs on the stage kernel's own traversal where the
- * LDS plane kernel runs the grid).  It needs a host round trip per step;
- * batches, servers and the convergence mode reject it.
+ * Lax-Friedrichs scheme): every step first finds, per axis, the smallest
+ * and largest central derivative D_d V = (D+ V + D- V) / 2 (eq (5); with
+ * ENO2 the average of its one-sided derivatives) over the grid's nodes,
+ * takes alpha_d(z) = max |dH/dp_d| over that box of gradients and
+ * dt = cfl / sum_d(alpha_d^max / dx_d), the last step shortened to the
+ * horizon; both TVD-RK2 stages use the step's alpha (the range pass runs on
+ * the stage kernel's own traversal where the LDS plane kernel runs the
+ * grid).  HJ_ALPHA_DERIV_RANGE_ONESIDED: the same with the box spanned by
+ * both one-sided derivatives of every node (the textbook global
+ * Lax-Friedrichs bound, monotone over every pair of one-sided values on the
+ * grid; never smaller than the central box).  Both need a host round trip
+ * per step; batches, servers and the convergence mode reject them.
  */
-enum { HJ_ALPHA_STATE = 0, HJ_ALPHA_DERIV_RANGE = 1 };
+enum { HJ_ALPHA_STATE = 0, HJ_ALPHA_DERIV_RANGE = 1, HJ_ALPHA_DERIV_RANGE_ONESIDED = 2 };
 
 typedef struct {
   int32_t deriv, integrator, precision, clamp;

@@ -183,7 +183,8 @@ hj_status validate(const hj_grid_desc *g, const hj_dynamics_desc *dy, const hj_s
   if (s->clamp != HJ_CLAMP_NONE && s->clamp != HJ_CLAMP_MIN_V0)
     return fail(HJ_ERR_INVALID_ARG, "unknown clamp %d", s->clamp);
   if (!(s->cfl > 0.0 && s->cfl <= 1.0)) return fail(HJ_ERR_INVALID_ARG, "cfl must lie in (0, 1]");
-  if (s->alpha_mode != HJ_ALPHA_STATE && s->alpha_mode != HJ_ALPHA_DERIV_RANGE)
+  if (s->alpha_mode != HJ_ALPHA_STATE && s->alpha_mode != HJ_ALPHA_DERIV_RANGE &&
+      s->alpha_mode != HJ_ALPHA_DERIV_RANGE_ONESIDED)
     return fail(HJ_ERR_INVALID_ARG, "unknown alpha_mode %d", s->alpha_mode);
   return HJ_OK;
 }
@@ -777,23 +778,28 @@ hj_status range_alpha_update(hj_grid *G, double *dt_allowed) {
   }
   // the plane kernel's own traversal where it runs the grid, else the
   // one-thread-per-column pass
+  const int32_t onesided = G->sch.alpha_mode == HJ_ALPHA_DERIV_RANGE_ONESIDED ? 1 : 0;
   if (G->kernel == 2 && G->elem == 4) {
     hj::StreamArgs<float> a = stream_args<float>(G);
     a.vs = buf<const float>(G->v);
     a.range = G->range_keys;
+    a.range_onesided = onesided;
     HJ_HIP(hj::launch_plane_range(a, G->sch.deriv, S(G)));
   } else if (G->kernel == 2) {
     hj::StreamArgs<double> a = stream_args<double>(G);
     a.vs = buf<const double>(G->v);
     a.range = G->range_keys;
+    a.range_onesided = onesided;
     HJ_HIP(hj::launch_plane_range(a, G->sch.deriv, S(G)));
   } else if (G->elem == 4) {
     hj::StageArgs<float> a = stage_args<float>(G);
     a.vs = buf<const float>(G->v);
+    a.range_onesided = onesided;
     HJ_HIP(hj::launch_deriv_range(a, G->sch.deriv, G->range_keys, S(G)));
   } else {
     hj::StageArgs<double> a = stage_args<double>(G);
     a.vs = buf<const double>(G->v);
+    a.range_onesided = onesided;
     HJ_HIP(hj::launch_deriv_range(a, G->sch.deriv, G->range_keys, S(G)));
   }
   HJ_HIP(hipMemcpyAsync(G->range_host, G->range_keys, 8 * hj::kRangeSlots * sizeof(unsigned long long),
@@ -968,7 +974,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
   build_table(G, tab);
   build_coef(G, tab, coef);
   build_theta(G, th);
-  if (scheme->alpha_mode == HJ_ALPHA_DERIV_RANGE) G->tab64 = tab;
+  if (scheme->alpha_mode != HJ_ALPHA_STATE) G->tab64 = tab;
   int64_t m = (int64_t)grid->n[2] * grid->n[3];
   {
     int run = hj::run_length(G->elem, grid->n[3]);
@@ -1172,7 +1178,7 @@ hj_status hj_solve_brt(hj_grid *G, double horizon, hj_solve_info *info) {
   if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
   if ((st = set_device(G)) != HJ_OK) return st;
   if ((st = ensure_dt(G)) != HJ_OK) return st;
-  if (G->sch.alpha_mode == HJ_ALPHA_DERIV_RANGE) {
+  if (G->sch.alpha_mode != HJ_ALPHA_STATE) {
     // Algorithm 1: alpha and dt from each step's derivative range; the step
     // that would reach or pass the horizon is shortened to end on it
     if ((st = reset_value(G)) != HJ_OK) return st;
@@ -1237,7 +1243,7 @@ hj_status hj_step(hj_grid *G, double dt, double *dt_taken) {
   if (!G->has_target) return fail(HJ_ERR_NOT_READY, "no target set");
   if (isnan(dt) || isinf(dt)) return fail(HJ_ERR_INVALID_ARG, "dt must be finite");
   if ((st = set_device(G)) != HJ_OK) return st;
-  if (G->sch.alpha_mode == HJ_ALPHA_DERIV_RANGE) {
+  if (G->sch.alpha_mode != HJ_ALPHA_STATE) {
     double allowed;
     if ((st = range_alpha_update(G, &allowed)) != HJ_OK) return st;
     if (dt <= 0) {

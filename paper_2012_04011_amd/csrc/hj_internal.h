@@ -42,6 +42,9 @@ struct StageArgs {
   int32_t clamp;
   int64_t npts;
   const int32_t *skip;  // when non-null and *skip != 0 the launch does nothing
+  // Derivative-range pass: 0 = range of the central derivative (p- + p+) / 2
+  // (Algorithm 1), 1 = range of both one-sided derivatives
+  int32_t range_onesided;
 };
 
 // The streaming stage kernel (see hj_kernels.hip).  Each thread owns a run
@@ -89,8 +92,11 @@ struct StreamArgs {
   // atomic max of its bits (non-negative doubles order as their bits)
   unsigned long long *eps;
   // Range pass (plane kernel, RANGE instance): kRangeSlots sets of keys of
-  // the per-axis extremes of the one-sided derivatives (see launch_deriv_range)
+  // the per-axis extremes of the derivatives (see launch_deriv_range): of
+  // the central derivative (p- + p+) / 2 (Algorithm 1), or of both one-sided
+  // derivatives when range_onesided is set
   unsigned long long *range;
+  int32_t range_onesided;
 };
 
 constexpr int kStreamBlock = 256;

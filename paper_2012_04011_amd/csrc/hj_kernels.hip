@@ -834,17 +834,20 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
   if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
 
-  // RANGE: the smallest and largest one-sided difference (unscaled, h p)
-  // per axis over this thread's nodes; nothing is written but the keys
+  // RANGE: the smallest and largest derivative (unscaled, h p) per axis
+  // over this thread's nodes -- of the central one (p- + p+) / 2, or of both
+  // one-sided ones; nothing is written but the keys
   T rlo[4], rhi[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     rlo[d] = T(INFINITY);
     rhi[d] = T(-INFINITY);
   }
+  const bool onesided = a.range_onesided != 0;
   auto rng = [&](int d, T pm, T pp) {
     if (!active) return;
-    const T mn = pm < pp ? pm : pp, mx = pm < pp ? pp : pm;
+    const T cen = T(0.5) * (pm + pp);
+    const T mn = onesided ? (pm < pp ? pm : pp) : cen, mx = onesided ? (pm < pp ? pp : pm) : cen;
     rlo[d] = mn < rlo[d] ? mn : rlo[d];
     rhi[d] = mx > rhi[d] ? mx : rhi[d];
   };
@@ -1374,8 +1377,9 @@ __global__ void batch_reset_kernel(BatchQueue *q, int m) {
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 1's derivative range: the smallest and largest one-sided
-// derivative per axis over the grid.  Doubles are compared through an
+// Algorithm 1's derivative range: the smallest and largest derivative per
+// axis over the grid -- of the central derivative (p- + p+) / 2 of eq (5),
+// or (range_onesided) of both one-sided derivatives.  Doubles are compared through an
 // order-preserving 64-bit key (sign bit flipped for non-negative values,
 // all bits flipped for negative ones), so unsigned atomics give min and max.
 // ---------------------------------------------------------------------------
@@ -1403,8 +1407,10 @@ __global__ __launch_bounds__(256) void deriv_range_kernel(StageArgs<T> a, unsign
   const int cols = (int)a.st[0];  // n[1] n[2] n[3]
   const int nx = a.n[0];
   const int nseg = (nx + kRangeXSeg - 1) / kRangeXSeg;
+  const bool onesided = a.range_onesided != 0;
   auto reduce = [&](int d, T pm, T pp) {
-    const T mn = pm < pp ? pm : pp, mx = pm < pp ? pp : pm;
+    const T cen = T(0.5) * (pm + pp);
+    const T mn = onesided ? (pm < pp ? pm : pp) : cen, mx = onesided ? (pm < pp ? pp : pm) : cen;
     lo[d] = mn < lo[d] ? mn : lo[d];
     hi[d] = mx > hi[d] ? mx : hi[d];
   };

@@ -32,7 +32,7 @@ HJ_CLAMP_NONE, HJ_CLAMP_MIN_V0 = 0, 1
 HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
 HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
 HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT, HJ_BATCH_STREAMS = 0, 1, 2, 3
-HJ_ALPHA_STATE, HJ_ALPHA_DERIV_RANGE = 0, 1
+HJ_ALPHA_STATE, HJ_ALPHA_DERIV_RANGE, HJ_ALPHA_DERIV_RANGE_ONESIDED = 0, 1, 2
 HJ_SERVE_SMALL_FIRST, HJ_SERVE_SHARE = 0, 1
 SERVE_POLICIES = {"small_first": HJ_SERVE_SMALL_FIRST, "share": HJ_SERVE_SHARE}
 BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT,
@@ -230,7 +230,8 @@ def scheme_desc(scheme: dict, precision: str) -> hj_scheme_desc:
     s.integrator = _INTEG[scheme["integrator"]]
     s.precision = _PREC[precision]
     s.clamp = HJ_CLAMP_MIN_V0 if scheme.get("clamp", True) else HJ_CLAMP_NONE
-    s.alpha_mode = {"state": HJ_ALPHA_STATE, "deriv_range": HJ_ALPHA_DERIV_RANGE}[scheme.get("alpha", "state")]
+    s.alpha_mode = {"state": HJ_ALPHA_STATE, "deriv_range": HJ_ALPHA_DERIV_RANGE,
+                    "deriv_range_onesided": HJ_ALPHA_DERIV_RANGE_ONESIDED}[scheme.get("alpha", "state")]
     s.cfl = float(scheme.get("cfl", 0.8))
     return s
 

@@ -51,8 +51,10 @@ def steer_dynamics(a_max: float = 1.5, steer_max: float = math.pi / 18, wheelbas
 
 
 def scheme(deriv: str, integrator: str, cfl: float = 0.8, clamp: bool = True, alpha: str = "state") -> dict:
-    """alpha: "state" (the bound on |f_d| over all inputs) or "deriv_range"
-    (Algorithm 1's global Lax-Friedrichs over the grid's derivative range)."""
+    """alpha: "state" (the bound on |f_d| over all inputs), "deriv_range"
+    (Algorithm 1's global Lax-Friedrichs over the range of the central
+    derivative of eq (5) on the grid) or "deriv_range_onesided" (over the
+    range of both one-sided derivatives)."""
     return {"deriv": deriv, "integrator": integrator, "clamp": clamp, "cfl": cfl, "alpha": alpha}
 
 

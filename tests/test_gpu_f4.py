@@ -62,13 +62,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("alpha", ["deriv_range", "deriv_range_onesided"], ids=["central", "onesided"])
 @pytest.mark.parametrize("kernel", ["plane", "stream", "generic"])
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 @pytest.mark.parametrize("name,dyn,target", CASES, ids=[c[0] for c in CASES])
-def test_range_alpha_solve_matches_oracle(monkeypatch, kernel, precision, name, dyn, target):
-    """Whole solves in the derivative-range mode on every stage kernel: the
-    same steps as the oracle, V within the parity bars.  Targets: a tilted
-    half plane (one-signed x and y gradients: alpha shrinks) or a disk."""
+def test_range_alpha_solve_matches_oracle(monkeypatch, kernel, precision, name, dyn, target, alpha):
+    """Whole solves in both derivative-range modes (Algorithm 1's central
+    derivative, and both one-sided ones) on every stage kernel: the same
+    steps as the oracle, V within the parity bars.  Targets: a tilted half
+    plane (one-signed x and y gradients: alpha shrinks) or a disk."""
     from paper_2012_04011_amd import hj
 
     if kernel != "plane":
@@ -80,7 +82,7 @@ def test_range_alpha_solve_matches_oracle(monkeypatch, kernel, precision, name, 
         V0 = 0.8 * X + 0.6 * Y - 1.0 + np.zeros(g["n"])
     else:
         V0 = np.sqrt(X * X + Y * Y) - 1.0 + np.zeros(g["n"])
-    sch = W.scheme("upwind1", "rk2", alpha="deriv_range")
+    sch = W.scheme("upwind1", "rk2", alpha=alpha)
     ref, oinfo = oracle.solve(g, dyn, sch, V0, 0.6)
     with hj.Grid(g, dyn, sch, precision) as h:
         h.set_target(V0)
@@ -92,7 +94,7 @@ def test_range_alpha_solve_matches_oracle(monkeypatch, kernel, precision, name, 
     if precision == "f64":
         assert_f64_close(V, ref)
     else:
-        assert_f32_close(V, ref, g, "upwind1")
+        assert_f32_close(V, ref, g)
 
 
 def test_range_alpha_rejected_where_a_fixed_step_is_needed():
@@ -154,3 +156,65 @@ def test_plane_range_pass_equals_column_pass(monkeypatch, precision, deriv, inte
         assert info["dt"] == pytest.approx(ref_info["dt"], rel=rel), key
         assert info["dt_last"] == pytest.approx(ref_info["dt_last"], rel=1e-3, abs=1e-9), key
         assert np.abs(v - ref_v).max() <= (1e-4 if precision == "f32" else 1e-10), key
+
+
+@pytest.mark.parametrize("kernel", ["plane", "stream", "generic"])
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_range_modes_differ_on_sawtooth(monkeypatch, kernel, precision):
+    """V_i = b (-1)^i on a periodic x axis: every central difference is 0,
+    the one-sided ones are +-2b/h.  With z' = 0.5 + u on x, |u| <= 1
+    minimising, Algorithm 1's central box gives alpha_x = 0.5 and the
+    one-sided box 1.5 (hand-derived; the oracle pin checks the same), so
+    dt = 0.8 h / 0.5 or 0.8 h / 1.5; V stays a sawtooth, so every step
+    keeps that dt."""
+    from paper_2012_04011_amd import hj
+
+    if kernel != "plane":
+        monkeypatch.setenv("HJ_STAGE_KERNEL", kernel)
+    g = {"n": (8, 6, 4, 8), "lo": (0.0, -1.0, 0.0, -math.pi), "hi": (8.0, 1.0, 2.0, math.pi),
+         "periodic_mask": 1 | 8}
+    saw = 0.25 * (-1.0) ** np.arange(8)
+    V0 = np.broadcast_to(saw[:, None, None, None], g["n"]).copy()
+    dyn = drift_dyn((0.5, 0, 0, 0), (0,), 1.0, "box", "min")
+    for alpha, ax in (("deriv_range", 0.5), ("deriv_range_onesided", 1.5)):
+        sch = W.scheme("upwind1", "euler", clamp=False, alpha=alpha)
+        ref, oinfo = oracle.solve(g, dyn, sch, V0, 4.0)
+        with hj.Grid(g, dyn, sch, precision) as h:
+            h.set_target(V0)
+            info = h.solve_brt(4.0)
+            assert h.launch_info()["kernel"] == kernel
+            V = h.value(np.float64)
+        assert info["dt"] == pytest.approx(0.8 / ax, rel=1e-12 if precision == "f64" else 1e-6), alpha
+        assert info["steps"] == oinfo["steps"], alpha
+        np.testing.assert_allclose(V, ref, rtol=0, atol=1e-12 if precision == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_range_modes_differ_ball_open_axes(precision):
+    """V = a x + b (-1)^i + c y on open x, y axes with a unit-ball input on
+    (x, y): the central x box is [a - 2b/h, a], the one-sided one
+    [a - 2b/h, a + 2b/h], so alpha_x = M / sqrt(M^2 + c^2) with M = a or
+    a + 2b/h and alpha_y = c / sqrt(c^2 + (a - 2b/h)^2); the first step is
+    0.8 / (alpha_x / h_x + alpha_y / h_y) (hand-derived, as in the oracle
+    pin)."""
+    from paper_2012_04011_amd import hj
+
+    nx = 10
+    g = {"n": (nx, 6, 4, 8), "lo": (-2.0, -1.0, 0.0, -math.pi), "hi": (2.5, 1.5, 2.0, math.pi),
+         "periodic_mask": 8}
+    hx, hy = 4.5 / (nx - 1), 2.5 / 5
+    a, c = 1.0, 1.0
+    b = 0.25 * hx
+    x, y = oracle.nodes(g, 0), oracle.nodes(g, 1)
+    V0 = (a * x + b * (-1.0) ** np.arange(nx))[:, None, None, None] + c * y[None, :, None, None] \
+        + np.zeros(g["n"])
+    dyn = drift_dyn((0, 0, 0, 0), (0, 1), 1.0, "ball", "max")
+    for alpha, M in (("deriv_range", a), ("deriv_range_onesided", a + 0.5)):
+        sch = W.scheme("upwind1", "euler", clamp=False, alpha=alpha)
+        ax = M / math.sqrt(M * M + c * c)
+        ay = c / math.sqrt(c * c + (a - 0.5) ** 2)
+        with hj.Grid(g, dyn, sch, precision) as h:
+            h.set_target(V0)
+            info = h.solve_brt(5.0)
+        dt = 0.8 / (ax / hx + ay / hy)
+        assert info["dt"] == pytest.approx(dt, rel=1e-12 if precision == "f64" else 1e-5), alpha
