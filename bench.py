@@ -590,9 +590,13 @@ def bench_adjacent(args) -> int:
     return 0
 
 
-def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
+def cpu_baseline(wl, budget_s: float = 15.0, coarse=None) -> dict:
     """The FP64 oracle on the host cores: whole RK2 steps of the same
-    workload from its seed-0 target, as many as fit the time budget."""
+    workload from its seed-0 target, as many as fit the time budget.  With
+    `coarse` (the 2x-coarsened companion workload) it also solves that grid
+    whole from the same obstacles, timed, and returns its V under the key
+    "_coarse_V" (the accuracy report compares the GPU's solves with it; the
+    caller removes the key before printing)."""
     import numpy as np
 
     import oracle
@@ -620,6 +624,20 @@ def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
         steps1, el1 = sample(0.6 * budget_s)
     finally:
         oracle.set_threads(cores)
+    coarse_out = {}
+    if coarse is not None:
+        V0c = oracle.target_cylinders(coarse.grid, cx, cy, r)
+        t0 = time.perf_counter()
+        Vc, ic = oracle.solve(coarse.grid, coarse.dyn, coarse.scheme, V0c, coarse.horizon)
+        elc = time.perf_counter() - t0
+        npc = int(np.prod(coarse.grid["n"]))
+        gridc = "x".join(map(str, coarse.grid["n"]))
+        coarse_out = {
+            "value_coarse_solve": npc * ic["steps"] / elc,
+            "sample_coarse_solve": f"the whole {ic['steps']}-step solve of the 2x-coarsened {gridc} grid "
+                                   f"({npc * ic['steps'] / 1e6:.1f}M point-steps, {elc:.1f} s)",
+            "_coarse_V": Vc,
+        }
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -640,7 +658,54 @@ def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
         "sample_1_thread": f"{steps1} step(s) of the same grid on one thread ({el1:.1f} s)",
         "cpu_model": model,
         "nproc": os.cpu_count(),
+        **coarse_out,
     }
+
+
+def accuracy_gpu(wl, stream) -> tuple:
+    """The precision report's GPU part (outside the timed loop): the seed-0
+    solve of the workload in FP32 and in FP64 on the GPU, compared node by
+    node (tol = 1e-4 min(dx, dy): band and all-node max, RMS, membership
+    flips), and the FP64 solve of its 2x-coarsened companion.  Returns
+    (report, V_fine_f64, V_coarse_f64)."""
+    import numpy as np
+
+    from paper_2012_04011_amd import accuracy, hj
+    from paper_2012_04011_amd import workloads as W
+
+    cyl = W.cylinders(0, wl.obstacles)
+    out = {}
+    for prec in ("f32", "f64"):
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, prec, stream) as g:
+            g.set_target_cylinders(*cyl)
+            g.solve_brt(wl.horizon)
+            out[prec] = g.value(np.float32 if prec == "f32" else np.float64)
+    wc = W.LARGE_120_COARSE
+    with hj.Grid(wc.grid, wc.dyn, wc.scheme, "f64", stream) as g:
+        g.set_target_cylinders(*cyl)
+        g.solve_brt(wc.horizon)
+        Vc = g.value(np.float64)
+    m = accuracy.precision_metrics(out["f32"], out["f64"], wl.grid)
+    m["within_tol"] = bool(m["max_band"] <= m["tol"] and m["rms"] <= m["tol"] and m["flips_outside"] == 0)
+    rep = {"fp32_vs_fp64_gpu": m,
+           "note": "seed-0 solves; tol = 1e-4 min(dx, dy) over the band |V| <= 1, RMS over all nodes, flips farther "
+                   "than tol from the zero level set"}
+    return rep, out["f64"], Vc
+
+
+def accuracy_oracle(rep, wl, V64, Vc_gpu, Vc_oracle) -> None:
+    """The precision report's oracle part: the coarse FP64 GPU solve against
+    the coarse oracle solve (parity), and the fine FP64 GPU solve sampled
+    multilinearly at the coarse nodes against the coarse oracle solve
+    (consistency of the two resolutions; flips counted where |V| > 2 dx)."""
+    import numpy as np
+
+    from paper_2012_04011_amd import accuracy
+    from paper_2012_04011_amd import workloads as W
+
+    rep["fp64_gpu_vs_oracle_coarse"] = {"max_abs": float(np.abs(Vc_gpu - Vc_oracle).max())}
+    rep["fine_fp64_gpu_vs_coarse_oracle"] = accuracy.consistency_metrics(V64, wl.grid, Vc_oracle,
+                                                                         W.LARGE_120_COARSE.grid)
 
 
 def main() -> int:
@@ -658,6 +723,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
     ap.add_argument("--hbm-budget", type=int, default=8 << 30, help="serve: slot memory budget in bytes")
     ap.add_argument("--summarize-traffic", metavar="DIR")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="large120: skip the precision report (FP32 vs FP64 GPU solves, coarse-grid comparison)")
     args = ap.parse_args()
     if args.summarize_traffic:
         return summarize_traffic(args.summarize_traffic)
@@ -772,8 +839,16 @@ def main() -> int:
         "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "min": float(lat.min())},
     }
+    acc = None
+    if prec == "f32" and not args.no_accuracy:
+        acc, V64, Vc_gpu = accuracy_gpu(wl, stream)
+        out["accuracy"] = acc
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        cb = cpu_baseline(wl, args.cpu_budget, W.LARGE_120_COARSE if acc is not None else None)
+        Vc_oracle = cb.pop("_coarse_V", None)
+        if acc is not None and Vc_oracle is not None:
+            accuracy_oracle(acc, wl, V64, Vc_gpu, Vc_oracle)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
     return 0
 

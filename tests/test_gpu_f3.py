@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2012_04011_amd import workloads as W
 
-from helpers import assert_f32_close, assert_f64_close
+from helpers import assert_f32_close, assert_f64_close, check_f32_solve
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_steering_car_solve_matches_oracle(monkeypatch, kernel, precision):
     if precision == "f64":
         assert_f64_close(V, ref)
     else:
-        assert_f32_close(V, ref, grid, "eno2")
+        check_f32_solve(V, ref, grid, "eno2")
 
 
 def test_paper_context_run_grid():
@@ -79,7 +79,7 @@ def test_paper_context_run_grid():
         for _ in range(67):
             g.step(0.007497)
         V = g.value(np.float64)
-    assert_f32_close(V, ref, grid, "upwind1")
+    assert_f32_close(V, ref, grid)
 
 
 # ----------------------------------------------------- convergence mode ---
@@ -124,7 +124,7 @@ def test_converge_stops_where_oracle_stops(stop, precision, dyn):
     if precision == "f64":
         assert_f64_close(V, ref)
     else:
-        assert_f32_close(V, ref, GRID_C, "upwind1")
+        assert_f32_close(V, ref, GRID_C)
 
 
 def test_converge_cap_equals_plain_steps():
