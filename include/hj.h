@@ -257,6 +257,23 @@ hj_status hj_solve_converge(hj_grid *g, double threshold, int64_t max_steps, hj_
 hj_status hj_optimal_control(hj_grid *g, const double *states, int64_t m, int32_t where, double *controls,
                              double *values);
 
+/* The control query of hj_optimal_control (same arguments, same kernel,
+ * the same results) for callers that cannot allocate device memory: a
+ * safety controller's loop that queries every tick, code under HIP graph
+ * capture, harnesses that forbid allocation.  hj_optimal_control grows a
+ * device staging buffer for host arrays (hipMalloc / hipFree inside the
+ * call); this variant allocates nothing: host arrays pass through one
+ * fixed device array of HJ_NOALLOC_MAX_STATES states (7 doubles each,
+ * 3.5 MiB), which each device holds from its first hj_grid_create until
+ * the process ends, and device arrays are used in place.  m above
+ * HJ_NOALLOC_MAX_STATES is HJ_ERR_INVALID_ARG.  Every call on a device
+ * shares that array (each call writes all of it that it reads), so calls
+ * that overlap on one device -- from several host threads, or on handles
+ * with different streams -- race and must be serialised by the caller. */
+#define HJ_NOALLOC_MAX_STATES 65536
+hj_status hj_optimal_control_noalloc(hj_grid *g, const double *states, int64_t m, int32_t where,
+                                     double *controls, double *values);
+
 /* How the time step runs on this handle.  kernel: 2 = LDS plane kernel, 1 =
  * streaming kernel, 0 = one-thread-per-node kernel (chosen by grid shape,
  * then by hj_autotune).  x_chunks: how many pieces each x sweep is split

@@ -10,8 +10,10 @@
 
 #include <string>
 #include <algorithm>
+#include <atomic>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/hj.h"
@@ -43,6 +45,44 @@ bool bit(uint32_t mask, int d) { return ((mask >> d) & 1u) != 0; }
 
 // Steps the convergence mode enqueues between two looks at the stop flag.
 constexpr int kConvergeChunk = 32;
+
+}  // namespace
+
+// ---- staging of hj_optimal_control_noalloc --------------------------------
+// Host arrays given to hj_optimal_control_noalloc pass through this fixed
+// device array: per state its (x, y, v, theta), its two controls and its
+// value, 7 doubles (HJ_NOALLOC_MAX_STATES states, 3.5 MiB).  Each device
+// holds its own copy until the process ends.  In host code the name is only
+// a stand-in: host code reaches the memory through the address
+// hipGetSymbolAddress gives on each device (noalloc_staging below).
+static __device__ __align__(256) double scratch[(size_t)HJ_NOALLOC_MAX_STATES * 7];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<double *> g_scratch[kMaxDevices];
+
+// The device address of `scratch` on device `dev`, which must be current:
+// looked up once per device (hj_grid_create does it at set-up) and kept.
+hj_status noalloc_staging(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(HJ_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  double *p = g_scratch[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      void *addr = nullptr;
+      hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !addr)
+        return fail(HJ_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      p = static_cast<double *>(addr);
+      g_scratch[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return HJ_OK;
+}
 
 }  // namespace
 
@@ -1015,6 +1055,13 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * G->n_seg, slab_runs, G->kernel == 2);
   }
   hipError_t e = hipGetDevice(&G->device);
+  if (e == hipSuccess) {
+    // set-up of this device's staging for hj_optimal_control_noalloc (a
+    // failure here is reported by that call, which looks again)
+    double *unused = nullptr;
+    (void)noalloc_staging(G->device, &unused);
+    g_last_error.clear();
+  }
   size_t bytes = G->npts * G->elem;
   bool rk2 = scheme->integrator == HJ_TVD_RK2;
   if (e == hipSuccess) e = hipMalloc(&G->v0, bytes);
@@ -1346,14 +1393,22 @@ hj_status hj_solve_converge(hj_grid *G, double threshold, int64_t max_steps, hj_
   return HJ_OK;
 }
 
-hj_status hj_optimal_control(hj_grid *G, const double *states, int64_t m, int32_t where, double *controls,
-                             double *values) {
+namespace {
+
+// The control query of hj_optimal_control and hj_optimal_control_noalloc.
+// Host arrays are staged through `staging` (7 doubles per state) when it is
+// given, else through the handle's own buffer, grown as needed.
+hj_status optimal_control_impl(hj_grid *G, const double *states, int64_t m, int32_t where, double *controls,
+                               double *values, bool noalloc) {
   hj_status st = check_handle(G);
   if (st != HJ_OK) return st;
   if (m < 0 || (m > 0 && (!states || !controls))) return fail(HJ_ERR_INVALID_ARG, "null states or controls");
   if (where != HJ_HOST && where != HJ_DEVICE) return fail(HJ_ERR_INVALID_ARG, "unknown location %d", where);
   if (G->dyn.kind != HJ_DYN_CAR4D && G->dyn.kind != HJ_DYN_CAR4D_STEER)
     return fail(HJ_ERR_UNSUPPORTED, "the optimal control is defined for the car dynamics");
+  if (noalloc && m > HJ_NOALLOC_MAX_STATES)
+    return fail(HJ_ERR_INVALID_ARG, "%lld states: the no-allocation query takes at most %d", (long long)m,
+                HJ_NOALLOC_MAX_STATES);
   if (m == 0) return HJ_OK;
   if ((st = set_device(G)) != HJ_OK) return st;
   const double *z = states;
@@ -1361,14 +1416,19 @@ hj_status hj_optimal_control(hj_grid *G, const double *states, int64_t m, int32_
   if (where == HJ_HOST) {
     for (int64_t i = 0; i < 4 * m; ++i)
       if (!isfinite(states[i])) return fail(HJ_ERR_INVALID_ARG, "state %lld is not finite", (long long)(i / 4));
-    if (m > G->ctl_cap) {
-      if (G->ctl_dev) HJ_HIP(hipFree(G->ctl_dev));
-      G->ctl_dev = nullptr;
-      G->ctl_cap = 0;
-      HJ_HIP(hipMalloc((void **)&G->ctl_dev, (size_t)m * 7 * sizeof(double)));
-      G->ctl_cap = m;
+    double *zd = nullptr;
+    if (noalloc) {
+      if ((st = noalloc_staging(G->device, &zd)) != HJ_OK) return st;
+    } else {
+      if (m > G->ctl_cap) {
+        if (G->ctl_dev) HJ_HIP(hipFree(G->ctl_dev));
+        G->ctl_dev = nullptr;
+        G->ctl_cap = 0;
+        HJ_HIP(hipMalloc((void **)&G->ctl_dev, (size_t)m * 7 * sizeof(double)));
+        G->ctl_cap = m;
+      }
+      zd = G->ctl_dev;
     }
-    double *zd = G->ctl_dev;
     HJ_HIP(hipMemcpyAsync(zd, states, m * 4 * sizeof(double), hipMemcpyHostToDevice, S(G)));
     z = zd;
     u = zd + 4 * m;
@@ -1419,6 +1479,18 @@ hj_status hj_optimal_control(hj_grid *G, const double *states, int64_t m, int32_
     HJ_HIP(hipStreamSynchronize(S(G)));
   }
   return HJ_OK;
+}
+
+}  // namespace
+
+hj_status hj_optimal_control(hj_grid *G, const double *states, int64_t m, int32_t where, double *controls,
+                             double *values) {
+  return optimal_control_impl(G, states, m, where, controls, values, false);
+}
+
+hj_status hj_optimal_control_noalloc(hj_grid *G, const double *states, int64_t m, int32_t where, double *controls,
+                                     double *values) {
+  return optimal_control_impl(G, states, m, where, controls, values, true);
 }
 
 hj_status hj_get_value(hj_grid *G, void *out, int32_t dtype, int32_t where) {

@@ -33,6 +33,7 @@ HJ_NORM_BOX, HJ_NORM_BALL = 0, 1
 HJ_INPUT_MAXIMIZES, HJ_INPUT_MINIMIZES = 0, 1
 HJ_BATCH_LAUNCHES, HJ_BATCH_GRAPH, HJ_BATCH_PERSISTENT, HJ_BATCH_STREAMS = 0, 1, 2, 3
 HJ_ALPHA_STATE, HJ_ALPHA_DERIV_RANGE, HJ_ALPHA_DERIV_RANGE_ONESIDED = 0, 1, 2
+HJ_NOALLOC_MAX_STATES = 65536
 HJ_SERVE_SMALL_FIRST, HJ_SERVE_SHARE = 0, 1
 SERVE_POLICIES = {"small_first": HJ_SERVE_SMALL_FIRST, "share": HJ_SERVE_SHARE}
 BATCH_MODES = {"launches": HJ_BATCH_LAUNCHES, "graph": HJ_BATCH_GRAPH, "persistent": HJ_BATCH_PERSISTENT,
@@ -45,7 +46,7 @@ EXPORTED = [
     "hj_grid_create", "hj_grid_destroy", "hj_set_target", "hj_set_target_cylinders", "hj_solve_brt",
     "hj_step", "hj_get_cfl_dt", "hj_get_alpha_max", "hj_get_value", "hj_get_target", "hj_set_value",
     "hj_get_num_points", "hj_set_profiling", "hj_get_profile", "hj_get_launch_info", "hj_autotune",
-    "hj_set_autotune", "hj_solve_converge", "hj_optimal_control", "hj_batch_create", "hj_batch_destroy", "hj_batch_solve", "hj_batch_set_tile",
+    "hj_set_autotune", "hj_solve_converge", "hj_optimal_control", "hj_optimal_control_noalloc", "hj_batch_create", "hj_batch_destroy", "hj_batch_solve", "hj_batch_set_tile",
     "hj_batch_set_spin_limit", "hj_batch_autotune", "hj_batch_get_info", "hj_server_create", "hj_server_destroy",
     "hj_server_submit", "hj_server_tick", "hj_server_poll", "hj_server_take", "hj_server_get_stats",
     "hj_last_error", "hj_version",
@@ -157,6 +158,7 @@ def load_library(path: str = LIB_PATH):
         "hj_set_autotune": [vp, i32],
         "hj_solve_converge": [vp, dbl, i64, P(hj_converge_info)],
         "hj_optimal_control": [vp, vp, i64, i32, vp, vp],
+        "hj_optimal_control_noalloc": [vp, vp, i64, i32, vp, vp],
         "hj_batch_create": [P(vp), i32, P(vp)],
         "hj_batch_destroy": [vp],
         "hj_batch_solve": [vp, P(dbl), i32, P(hj_solve_info)],
@@ -375,16 +377,17 @@ def hj_solve_converge(h: int, threshold: float, max_steps: int) -> dict:
     return {"steps": i.steps, "converged": bool(i.converged), "dt": i.dt, "eps_last": i.eps_last}
 
 
-def hj_optimal_control(h: int, states, controls=None, values=None):
+def hj_optimal_control(h: int, states, controls=None, values=None, name: str = "hj_optimal_control"):
     """states: (m, 4) float64 numpy array (host) or torch tensor (device).
-    Returns (controls (m, 2), values (m,)) of the same kind."""
+    Returns (controls (m, 2), values (m,)) of the same kind.  name selects
+    the entry point: hj_optimal_control or hj_optimal_control_noalloc."""
+    fn = getattr(_lib, name)
     if isinstance(states, np.ndarray) or not hasattr(states, "data_ptr"):
         z = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(-1, 4))
         m = z.shape[0]
         u = np.empty((m, 2)) if controls is None else controls
         val = np.empty(m) if values is None else values
-        _check(_lib.hj_optimal_control(h, z.ctypes.data, m, HJ_HOST, u.ctypes.data, val.ctypes.data),
-               "hj_optimal_control")
+        _check(fn(h, z.ctypes.data, m, HJ_HOST, u.ctypes.data, val.ctypes.data), name)
         return u, val
     import torch
 
@@ -394,9 +397,14 @@ def hj_optimal_control(h: int, states, controls=None, values=None):
     m = z.shape[0]
     u = torch.empty((m, 2), dtype=torch.float64, device=z.device) if controls is None else controls
     val = torch.empty(m, dtype=torch.float64, device=z.device) if values is None else values
-    _check(_lib.hj_optimal_control(h, z.data_ptr(), m, HJ_DEVICE, u.data_ptr(), val.data_ptr()),
-           "hj_optimal_control")
+    _check(fn(h, z.data_ptr(), m, HJ_DEVICE, u.data_ptr(), val.data_ptr()), name)
     return u, val
+
+
+def hj_optimal_control_noalloc(h: int, states, controls=None, values=None):
+    """hj_optimal_control through the entry point that allocates no device
+    memory (at most HJ_NOALLOC_MAX_STATES states)."""
+    return hj_optimal_control(h, states, controls, values, "hj_optimal_control_noalloc")
 
 
 def hj_batch_create(handles) -> int:
@@ -585,6 +593,9 @@ class Grid:
 
     def optimal_control(self, states):
         return hj_optimal_control(self.handle, states)
+
+    def optimal_control_noalloc(self, states):
+        return hj_optimal_control_noalloc(self.handle, states)
 
     def autotune(self):
         hj_autotune(self.handle)
