@@ -37,13 +37,34 @@ _LIB = os.path.join(_HERE, "libhjoracle.so")
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
 
 
-def build(force: bool = True) -> str:
-    """Compile ``hj_oracle.c`` into ``libhjoracle.so`` with gcc."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+# HJ_SANITIZE=1: the same source built with AddressSanitizer and
+# UndefinedBehaviorSanitizer by clang (the runtime the sanitized HIP library
+# uses, so that one runtime serves both in an interpreter that preloads it),
+# into libhjoracle_san.so, which is then the one loaded.
+_LIB_SAN = os.path.join(_HERE, "libhjoracle_san.so")
+SAN_CC = "/opt/rocm/llvm/bin/clang"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-shared-libsan",
+             "-fno-omit-frame-pointer", "-g"]
+
+
+def _sanitize() -> bool:
+    return os.environ.get("HJ_SANITIZE") == "1"
+
+
+def build(force: bool = True, sanitize: bool | None = None) -> str:
+    """Compile ``hj_oracle.c`` into ``libhjoracle.so`` with gcc (or, sanitized,
+    into ``libhjoracle_san.so`` with clang)."""
+    sanitize = _sanitize() if sanitize is None else sanitize
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        if sanitize:
+            flags = [f for f in CFLAGS if f != "-fopenmp"] + SAN_FLAGS
+            subprocess.check_call([SAN_CC, *flags, "-o", tmp, _SRC, "-lm"])
+        else:
+            subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Grid(ctypes.Structure):
@@ -87,9 +108,10 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _LIB_SAN if _sanitize() else _LIB
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
         g, dy, sc = P(_Grid), P(_Dyn), P(_Scheme)

@@ -121,10 +121,14 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load ``libhj.so`` (raises if it has not been built)."""
+    """Load ``libhj.so`` (raises if it has not been built).  With
+    HJ_SANITIZE=1 the sanitizer build ``libhj_san.so`` is loaded instead
+    (its runtime must be preloaded; see build.py)."""
     global _lib
     if _lib is not None:
         return _lib
+    if os.environ.get("HJ_SANITIZE") == "1" and path == LIB_PATH:
+        path = os.path.join(os.path.dirname(LIB_PATH), "libhj_san.so")
     if not os.path.exists(path):
         raise ImportError(f"HIP library {path} is not built; run `python -m paper_2012_04011_amd.build` "
                           "(or __graft_entry__.build())")
