@@ -284,12 +284,19 @@ hj_status hj_optimal_control_noalloc(hj_grid *g, const double *states, int64_t m
  * theta nodes); 0 with the other kernels.  solve_graph: 1 if hj_solve_brt
  * replays its time loop as a captured HIP graph (grids of at most 64 MiB per
  * array, or as HJ_SOLVE_GRAPH=0/1 forces; bitwise the same result).
+ * theta_run: theta nodes per thread of the stage kernel (4, 3, 2 or 1; the
+ * plane kernel takes runs of 3 in FP32 where they pack a whole plane into
+ * fuller waves, by an estimate or by hj_autotune).  span_blocks: 0 when
+ * the plane kernel cuts each y row's x sweep into x_chunks pieces; else the
+ * number of blocks that share all rows' x planes equally in row-major order
+ * (so that every compute unit gets the same work; chosen by hj_autotune).
  * bytes_per_point_step: algorithmic
  * HBM bytes one full step moves per grid node in this mode (each array read
  * once and written once per stage). */
 typedef struct {
   int32_t kernel, x_chunks, target_xy, autotuned;
   int32_t plane_segments, solve_graph;
+  int32_t theta_run, span_blocks;
   double bytes_per_point_step;
 } hj_launch_info;
 
@@ -305,7 +312,9 @@ hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
  * Environment (for tests and measurements; read when a handle is created,
  * HJ_AUTOTUNE_VERBOSE when it autotunes):
  * HJ_STAGE_KERNEL=stream|generic forces a stage kernel; HJ_X_CHUNKS=n fixes
- * the x chunks; HJ_PLANE_VSEG=r splits the plane kernel's (v, theta) plane
+ * the x chunks; HJ_PLANE_RUN=3 or =the default run fixes the plane kernel's
+ * theta run (where it fits); HJ_PLANE_SPAN=b shares all row-planes among b
+ * plane-kernel blocks; HJ_PLANE_VSEG=r splits the plane kernel's (v, theta) plane
  * into segments of at most r v rows (r >= 4) even when it fits one block;
  * HJ_AUTOTUNE_VERBOSE prints each candidate's time to stderr. */
 hj_status hj_autotune(hj_grid *g);
@@ -388,7 +397,9 @@ hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);
  *     fill the device alone) first, least remaining work (nodes times steps
  *     left) first, then the larger ones in the order they were submitted;
  *     requests are taken in that order until they hold 4 Mi nodes, the
- *     others wait for a later tick;
+ *     others wait for a later tick; a request left waiting 6 ticks in a row
+ *     goes first at the next (in submission order), so no request waits
+ *     without bound;
  *   HJ_SERVE_SHARE: every running request, every tick.
  * Among the requests of a tick, grids of fewer than 4 Mi nodes share one
  * launch per stage and step (each at its own step), larger ones fill the

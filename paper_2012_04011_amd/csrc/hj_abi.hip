@@ -107,6 +107,12 @@ struct hj_grid {
   int kernel = 0;
   int x_chunks = 1;
   int v_seg = 0, n_seg = 1;  // plane kernel: v rows per block, v segments
+  // plane kernel's theta run length (runs of 3 hold whole planes only), and
+  // a second one the autotuner times (0: none)
+  int plane_run = 1, plane_run_alt = 0;
+  // plane kernel: 0 = chunk mode (x_chunks), else the number of blocks that
+  // share all row-planes (span mode, whole planes only)
+  int span_blocks = 0;
   bool plane_ok = false, stream_ok = false;
   bool launch_fixed = false;   // kernel / chunks forced by the environment
   bool autotune_on = true, autotuned = false;
@@ -162,7 +168,7 @@ struct hj_grid {
     int64_t n;
     double dt, dt_last;
     void *v_in, *w2_in, *v_out, *w2_out;
-    int kernel, x_chunks;
+    int kernel, x_chunks, plane_run, span_blocks;
     bool target_xy;
     const int32_t *skip;
     hipGraphExec_t exec;
@@ -578,12 +584,16 @@ hj::StageArgs<T> stage_args(hj_grid *G) {
   return a;
 }
 
+// The streaming description of the handle's grid for its own stage kernel
+// (plane = the LDS plane kernel runs it, with the handle's plane run length)
+// or for the streaming tiles of the batched launches (plane = false).
 template <typename T>
-hj::StreamArgs<T> stream_args(hj_grid *G) {
+hj::StreamArgs<T> stream_args(hj_grid *G, bool plane) {
   hj::StreamArgs<T> a;
   memset(&a, 0, sizeof a);
   const hj_grid_desc &g = G->g;
-  const int run = hj::run_length((int)sizeof(T), g.n[3]);
+  const int run = plane ? G->plane_run : hj::run_length((int)sizeof(T), g.n[3]);
+  const int nseg = plane && run == 3 ? 1 : G->n_seg;  // runs of 3: whole planes
   for (int d = 0; d < 4; ++d) a.n[d] = g.n[d];
   a.periodic_mask = g.periodic_mask;
   a.plane = g.n[1] * g.n[2] * g.n[3];
@@ -591,10 +601,10 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   a.run = run;
   a.runs_per_row = g.n[3] / run;
   a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
-  a.blocks_per_chunk =
-      G->kernel == 2 ? g.n[1] * G->n_seg : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
-  a.v_seg = G->v_seg;
-  a.n_seg = G->n_seg;
+  a.blocks_per_chunk = plane ? g.n[1] * nseg : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  a.v_seg = plane && run == 3 ? g.n[2] : G->v_seg;
+  a.n_seg = nseg;
+  a.span = plane && nseg == 1 ? G->span_blocks : 0;
   a.n_chunks = G->x_chunks;
   a.chunk_len = (g.n[0] + a.n_chunks - 1) / a.n_chunks;
   a.n_chunks = (g.n[0] + a.chunk_len - 1) / a.chunk_len;
@@ -612,6 +622,11 @@ hj::StreamArgs<T> stream_args(hj_grid *G) {
   a.sig_ball = (T)G->sig_ball;
   a.ball_mask = G->ball_mask;
   return a;
+}
+
+template <typename T>
+hj::StreamArgs<T> stream_args(hj_grid *G) {
+  return stream_args<T>(G, G->kernel == 2);
 }
 
 template <typename T>
@@ -698,7 +713,9 @@ hj_status solve_graph(hj_grid *G, int64_t n, double dt, double dt_last, int64_t 
   for (size_t i = 0; i < G->graphs.size(); ++i) {
     hj_grid::SolveGraph e = G->graphs[i];
     if (e.n == n && e.dt == dt && e.dt_last == dt_last && e.v_in == G->v && e.w2_in == G->w2 &&
-        e.kernel == G->kernel && e.x_chunks == G->x_chunks && e.target_xy == G->target_xy && e.skip == G->skip) {
+        e.kernel == G->kernel && e.x_chunks == G->x_chunks && e.plane_run == G->plane_run &&
+        e.span_blocks == G->span_blocks &&
+        e.target_xy == G->target_xy && e.skip == G->skip) {
       HJ_HIP(hipGraphLaunch(e.exec, S(G)));
       G->v = e.v_out;
       G->w2 = e.w2_out;
@@ -717,6 +734,8 @@ hj_status solve_graph(hj_grid *G, int64_t n, double dt, double dt_last, int64_t 
   e.w2_in = G->w2;
   e.kernel = G->kernel;
   e.x_chunks = G->x_chunks;
+  e.plane_run = G->plane_run;
+  e.span_blocks = G->span_blocks;
   e.target_xy = G->target_xy;
   e.skip = G->skip;
   e.exec = nullptr;
@@ -948,6 +967,19 @@ hj_status time_config(hj_grid *G, int reps, hipEvent_t e0, hipEvent_t e1, float 
   return HJ_OK;
 }
 
+// Compute units of a device (0 if unknown), looked up once per device.
+int device_cus(int dev) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+  cache[dev] = n;
+  return n;
+}
+
 hj_status autotune(hj_grid *G) {
   hj_status st;
   if ((st = ensure_dt(G)) != HJ_OK) return st;
@@ -958,25 +990,39 @@ hj_status autotune(hj_grid *G) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HJ_HIP(hipEventCreate(&e0));
   HJ_HIP(hipEventCreate(&e1));
-  int best_k = G->kernel, best_c = G->x_chunks;
+  int best_k = G->kernel, best_c = G->x_chunks, best_r = G->plane_run, best_s = G->span_blocks;
+  const int cus = device_cus(G->device);
   float best = INFINITY;
-  int kernels[2] = {2, 1};
+  // (kernel, plane run) candidates: the plane kernel with its run length and
+  // the alternative, then the streaming kernel
+  int kernels[3] = {2, 2, 1}, runs[3] = {G->plane_run, G->plane_run_alt, G->plane_run};
   int cap = G->g.n[0] / 4 > 1 ? G->g.n[0] / 4 : 1;
-  for (int kk = 0; kk < 2 && st == HJ_OK; ++kk) {
+  for (int kk = 0; kk < 3 && st == HJ_OK; ++kk) {
     int k = kernels[kk];
-    if ((k == 2 && !G->plane_ok) || (k == 1 && !G->stream_ok)) continue;
-    for (int c = 1; c <= 8 && c <= cap; ++c) {
+    if ((k == 2 && !G->plane_ok) || (k == 1 && !G->stream_ok) || runs[kk] == 0) continue;
+    // chunk modes 1 .. 8, then (plane kernel, whole planes) blocks that
+    // share all row-planes: one or two per CU
+    const bool whole = runs[kk] == 3 || G->n_seg == 1;
+    const int nspan = k == 2 && whole && cus > 0 ? 2 : 0;
+    for (int c = 1; c <= 8 + nspan; ++c) {
+      const bool span = c > 8;
+      if (!span && c > cap) continue;
       G->kernel = k;
-      G->x_chunks = c;
+      G->x_chunks = span ? G->x_chunks : c;
+      G->span_blocks = span ? (c - 8) * cus : 0;
+      G->plane_run = runs[kk];
       float ms = 0;
       st = G->elem == 4 ? time_config<float>(G, 5, e0, e1, &ms) : time_config<double>(G, 5, e0, e1, &ms);
       if (st != HJ_OK) break;
       if (getenv("HJ_AUTOTUNE_VERBOSE"))
-        fprintf(stderr, "hj_autotune: kernel %d chunks %d: %.1f us per step\n", k, c, ms * 1e3);
+        fprintf(stderr, "hj_autotune: kernel %d run %d chunks %d span %d: %.1f us per step\n", k, runs[kk],
+                G->x_chunks, G->span_blocks, ms * 1e3);
       if (ms < best) {
         best = ms;
         best_k = k;
-        best_c = c;
+        best_c = G->x_chunks;
+        best_r = runs[kk];
+        best_s = G->span_blocks;
       }
     }
   }
@@ -984,6 +1030,8 @@ hj_status autotune(hj_grid *G) {
   (void)hipEventDestroy(e1);
   G->kernel = best_k;
   G->x_chunks = best_c;
+  G->plane_run = best_r;
+  G->span_blocks = best_s;
   if (st == HJ_OK) G->autotuned = true;
   return st;
 }
@@ -1038,9 +1086,42 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     const int64_t lds_rows = n_seg > 1 ? v_seg + 4 : nv;
     bool plane_ok = stream_ok && max_rows > 0 && (n_seg == 1 || v_seg >= hj::kPlaneMinSegRows) &&
                     2 * lds_rows * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
-    (void)plane_runs;
     G->v_seg = v_seg;
     G->n_seg = plane_ok ? n_seg : 1;
+    G->plane_run = run;
+    // Runs of 3 theta nodes (FP32): a whole plane in one block of up to
+    // kPlaneMaxThreads3 runs, each run in a 4-element LDS slot.  Taken where
+    // it costs less SIMD time per plane: a thread's plane costs about
+    // 51 R + 15 instructions (R nodes' four axes and update, its run's theta
+    // halo, per-thread overhead), idle lanes of the last wave cost the same,
+    // and a block of 8 or more waves (alone on its CU) takes as long as its
+    // busiest SIMD (waves / 4, rounded up), since a barrier ends each plane.
+    const int64_t runs3 = (int64_t)nv * (grid->n[3] / 3);
+    const bool fit3 = G->elem == 4 && grid->n[3] % 3 == 0 && stream_ok && !vseg_env &&
+                      runs3 <= hj::kPlaneMaxThreads3 && 2 * runs3 * 4 * 4 <= hj::kPlaneMaxLdsBytes;
+    const bool plane_ok_default = plane_ok;
+    if (fit3) {
+      auto cost = [&](int r, int64_t runs_r) {
+        const int64_t waves = (runs_r + 63) / 64;
+        return (double)(waves >= 8 ? 4 * ((waves + 3) / 4) : waves) * (51.0 * r + 15.0);
+      };
+      const bool three_better = !plane_ok || n_seg > 1 || cost(3, runs3) < cost(run, plane_runs);
+      if (!plane_ok) {  // runs of 3 make a whole plane fit
+        plane_ok = true;
+        G->n_seg = 1;
+        G->v_seg = nv;
+      }
+      G->plane_run = three_better ? 3 : run;
+      G->plane_run_alt = three_better ? (plane_ok_default ? run : 0) : 3;
+    }
+    const char *prun = getenv("HJ_PLANE_RUN");
+    if (prun && fit3 && atoi(prun) == 3) {
+      G->plane_run = 3;
+      G->plane_run_alt = 0;
+    } else if (prun && atoi(prun) == run && plane_ok_default) {
+      G->plane_run = run;
+      G->plane_run_alt = 0;
+    }
     G->plane_ok = plane_ok;
     G->stream_ok = stream_ok;
     G->kernel = plane_ok ? 2 : (stream_ok ? 1 : 0);
@@ -1051,8 +1132,14 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
       G->launch_fixed = true;
     }
     if (getenv("HJ_X_CHUNKS")) G->launch_fixed = true;
+    const char *span_env = getenv("HJ_PLANE_SPAN");  // blocks sharing all row-planes (plane kernel, whole planes)
+    if (span_env && atoi(span_env) > 0) {
+      G->span_blocks = atoi(span_env);
+      G->launch_fixed = true;
+    }
     int64_t slab_runs = (int64_t)grid->n[1] * plane_runs;
-    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * G->n_seg, slab_runs, G->kernel == 2);
+    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * (G->plane_run == 3 ? 1 : G->n_seg), slab_runs,
+                                  G->kernel == 2);
   }
   hipError_t e = hipGetDevice(&G->device);
   if (e == hipSuccess) {
@@ -1531,7 +1618,9 @@ hj_status hj_get_launch_info(hj_grid *G, hj_launch_info *out) {
   out->x_chunks = G->x_chunks;
   out->target_xy = G->target_xy && G->kernel > 0;
   out->autotuned = G->autotuned;
-  out->plane_segments = G->kernel == 2 ? G->n_seg : 0;
+  out->plane_segments = G->kernel == 2 ? (G->plane_run == 3 ? 1 : G->n_seg) : 0;
+  out->theta_run = G->kernel == 2 ? G->plane_run : hj::run_length((int)G->elem, G->g.n[3]);
+  out->span_blocks = G->kernel == 2 && (G->plane_run == 3 || G->n_seg == 1) ? G->span_blocks : 0;
   out->solve_graph = G->sch.alpha_mode == HJ_ALPHA_STATE && use_solve_graph(G, 2) ? 1 : 0;
   // arrays per stage: read the stencil input, write the output; stage 2 of
   // TVD-RK2 also reads V^n; the clamp reads V0 unless it is the xy table
@@ -1660,6 +1749,7 @@ constexpr int32_t kBatchDefaultXPlanes = 16;
 constexpr int64_t kServerBlocks = 1024;
 constexpr int64_t kServerAlonePoints = (int64_t)4 << 20;  // grids this large step on their own kernel
 constexpr int64_t kServerFillPoints = kServerAlonePoints;  // small-first: nodes that fill the device
+constexpr int kServerMaxSkips = 6;  // small-first: ticks a running request may be left waiting in a row
 
 int32_t batch_x_planes(const hj_batch *b) { return b->x_planes > 0 ? b->x_planes : kBatchDefaultXPlanes; }
 
@@ -1671,7 +1761,7 @@ int batch_chunks(const hj_batch *b, const hj_grid *G) {
 
 template <typename T>
 hj::StreamArgs<T> batch_stream_args(hj_grid *G, int n_chunks) {
-  hj::StreamArgs<T> a = stream_args<T>(G);
+  hj::StreamArgs<T> a = stream_args<T>(G, false);
   a.skip = nullptr;
   a.blocks_per_chunk = (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
   int nx = G->g.n[0];
@@ -2123,6 +2213,7 @@ struct hj_server {
     int slot = -1;
     int64_t n = 0, k = 0;
     double dt = 0, dt_last = 0;
+    int skipped = 0;  // consecutive ticks left waiting by the small-first order
     hipEvent_t ev = nullptr;
   };
   std::map<int64_t, Req> reqs;
@@ -2282,20 +2373,26 @@ hj_status server_step(hj_server *S) {
   HJ_HIP(hipEventSynchronize(S->ring_ev[r]));  // this ring slot's previous launches are done
   // the requests that step this tick: all of them (sharing), or, in the
   // order small ones (least remaining work first) then large ones (first
-  // submitted first), as many as it takes to fill the device
+  // submitted first), as many as it takes to fill the device -- except that
+  // a request left waiting kServerMaxSkips ticks in a row goes first (in
+  // submission order), so that a stream of small requests cannot hold a
+  // large one back without bound
   std::vector<int64_t> sel(S->running), wait;
   if (S->d.policy == HJ_SERVE_SMALL_FIRST) {
     auto npts = [&](int64_t id) { return S->slots[S->reqs[id].slot].g->npts; };
     auto key = [&](int64_t id) {
       const hj_server::Req &q = S->reqs[id];
+      if (q.skipped >= kServerMaxSkips) return std::make_pair(0, id);
       const bool large = npts(id) >= kServerFillPoints;
-      return std::make_pair(large ? 1 : 0, large ? id : npts(id) * (q.n - q.k));
+      return std::make_pair(large ? 2 : 1, large ? id : npts(id) * (q.n - q.k));
     };
     std::stable_sort(sel.begin(), sel.end(), [&](int64_t x, int64_t y) { return key(x) < key(y); });
     size_t take = 0;
     for (int64_t pts = 0; take < sel.size() && pts < kServerFillPoints; ++take) pts += npts(sel[take]);
     wait.assign(sel.begin() + take, sel.end());
     sel.resize(take);
+    for (int64_t id : sel) S->reqs[id].skipped = 0;
+    for (int64_t id : wait) S->reqs[id].skipped += 1;
   }
   const int m = (int)sel.size();
   // longest remaining first, so the requests still stepping at step s of

@@ -97,6 +97,10 @@ struct StreamArgs {
   // derivatives when range_onesided is set
   unsigned long long *range;
   int32_t range_onesided;
+  // Plane kernel: 0 = chunk mode (one block per (x chunk, v segment, y row));
+  // else this many blocks share the ny * nx row-planes of a whole-plane grid
+  // equally in row-major order (blocks may span two or more rows)
+  int32_t span;
 };
 
 constexpr int kStreamBlock = 256;
@@ -120,6 +124,9 @@ hipError_t launch_stream(const StreamArgs<T> &a, int deriv, bool ball, hipStream
 // holding its segment and two halo rows per side: 2 (v_seg + 4) n[3] values.
 // blocks_per_chunk = n[1] * n_seg (segment-major, y fastest).
 constexpr int kPlaneMaxThreads = 768;
+// Runs of 3 theta nodes (FP32, whole planes only): each run takes a 4-element
+// LDS slot, and a block may hold up to 1024 runs (16 waves).
+constexpr int kPlaneMaxThreads3 = 1024;
 constexpr int kPlaneMaxLdsBytes = 64 * 1024;
 constexpr int kPlaneMinSegRows = 4;  // a split plane keeps at least this many rows per block
 

@@ -58,9 +58,6 @@ __device__ inline T axis_value(const T *__restrict__ v, int64_t p, int i, int o,
   return e + T(q - (n - 1)) * (e - nx);
 }
 
-// Second difference Q_j = V_{j+1} - 2 V_j + V_{j-1}, evaluated as
-// (V_{j+1} - 2 V_j) + V_{j-1}: the doubling is exact, so fused or not this is
-// two roundings, and equal inputs give equal Q (and equal ENO choices).
 // A block-uniform element of a table that no thread writes during the
 // launch, read through the scalar data cache: its latency is then counted
 // apart from the vector loads in flight.
@@ -199,10 +196,21 @@ template <typename T>
 struct Vec2T {
   typedef T type __attribute__((ext_vector_type(2)));
 };
+// A run in global memory.  Runs of 3 sit at 12-byte strides, so their
+// vector type carries the element's alignment only (a 3-vector is otherwise
+// taken as 16-byte aligned).
+template <typename T, int R>
+struct GVecT {
+  typedef T type __attribute__((ext_vector_type(R)));
+};
+template <>
+struct GVecT<float, 3> {
+  typedef float type __attribute__((ext_vector_type(3), aligned(4)));
+};
 
 template <typename T, int R>
 __device__ inline void load_run(const T *__restrict__ p, T (&r)[R]) {
-  typedef typename VecT<T, R>::type V;
+  typedef typename GVecT<T, R>::type V;
   V x = *reinterpret_cast<const V *>(p);
 #pragma unroll
   for (int i = 0; i < R; ++i) r[i] = x[i];
@@ -210,7 +218,7 @@ __device__ inline void load_run(const T *__restrict__ p, T (&r)[R]) {
 
 template <typename T, int R>
 __device__ inline void load_run_nt(const T *__restrict__ p, T (&r)[R]) {
-  typedef typename VecT<T, R>::type V;
+  typedef typename GVecT<T, R>::type V;
   V x = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
 #pragma unroll
   for (int i = 0; i < R; ++i) r[i] = x[i];
@@ -218,7 +226,7 @@ __device__ inline void load_run_nt(const T *__restrict__ p, T (&r)[R]) {
 
 template <typename T, int R>
 __device__ inline void store_run_nt(T *__restrict__ p, const T (&r)[R]) {
-  typedef typename VecT<T, R>::type V;
+  typedef typename GVecT<T, R>::type V;
   V x;
 #pragma unroll
   for (int i = 0; i < R; ++i) x[i] = r[i];
@@ -309,9 +317,11 @@ constexpr int kCacheStream = 2;  // non-temporal
 
 template <typename T, int R, int AUX = kCacheDefault>
 __device__ inline void bload(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T (&r)[R]) {
-  typedef typename VecT<T, R>::type V;
+  typedef typename GVecT<T, R>::type V;
   V x;
-  if constexpr (sizeof(V) == 16)
+  if constexpr (R == 3 && sizeof(T) == 4)
+    x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b96(rs, voff, soff, AUX));
+  else if constexpr (sizeof(V) == 16)
     x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, AUX));
   else if constexpr (sizeof(V) == 8)
     x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, AUX));
@@ -680,7 +690,8 @@ __global__ __launch_bounds__(kStreamBlock) void stage_stream(StreamArgs<T> a) {
 
 template <typename T, int R>
 __device__ inline void lds_run(const T *p, T (&r)[R]) {
-  typedef typename VecT<T, R>::type V;
+  // a run of 3 sits in a 4-element slot (16-byte aligned)
+  typedef typename VecT<T, R == 3 ? 4 : R>::type V;
   V x = *reinterpret_cast<const V *>(p);
 #pragma unroll
   for (int i = 0; i < R; ++i) r[i] = x[i];
@@ -708,23 +719,39 @@ __device__ inline unsigned long long order_key(double x) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// Stage forms the plane kernel compiles in (see FORM below): Euler or TVD-RK2
+// stage 1 without a clamp, the last stage of an Euler step with the clamp
+// value from the Nx x Ny table, TVD-RK2 stage 2 (the average) with it.
+enum PlaneForm { kFormRuntime = 0, kFormPlain = 1, kFormPlainXY = 2, kFormAverageXY = 3 };
+
 // SEG: the block holds one v segment [va, va + v_seg) of the plane plus two
 // halo rows on each side (copied from global memory by the first 4 * rpr
 // threads, one plane ahead), for planes with more runs than a block has
 // threads.
-template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE>
-__global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
+// FORM: the stage's combine and clamp target fixed at compile time for the
+// forms the solves use (PlaneForm), so that every plane issues the same
+// memory operations and branches on none of them; kFormRuntime reads them,
+// and the eps fold, from the arguments.
+// R = 3 (FP32): runs of three theta nodes, each kept in a 4-element LDS slot
+// (16-byte aligned), blocks of up to kPlaneMaxThreads3 work-items.
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM>
+__global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
   if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   constexpr uint32_t E = sizeof(T);
   const int nx = a.n[0], ny = a.n[1], nv = a.n[2], nth = a.n[3];
   const int rpr = a.runs_per_row;
+  constexpr int SL = R == 3 ? 4 : R;  // LDS elements per run
+  const int rowl = rpr * SL;          // LDS elements per v row
   const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
-  const int chunk = lb / a.blocks_per_chunk;
-  const int rem = lb - chunk * a.blocks_per_chunk;  // segment-major, y fastest
+  // chunk mode (a.span == 0): the block is (x chunk, v segment, y row).
+  // Span mode (whole planes, SEG false): the block takes its equal share of
+  // all rows' x planes in row-major order, as one or more (row, x range)
+  // segments; gridDim.x blocks share the ny * nx row-planes.
+  const int chunk = a.span ? 0 : lb / a.blocks_per_chunk;
+  const int rem = a.span ? 0 : lb - chunk * a.blocks_per_chunk;  // segment-major, y fastest
   const int seg = SEG ? rem / ny : 0;
-  const int y = SEG ? rem - seg * ny : rem;
   const int va = seg * a.v_seg;                            // first v of the segment
   const int nvs = SEG ? min(a.v_seg, nv - va) : nv;        // its rows
   const int vbase = SEG ? va - 2 : 0;                      // v of LDS row 0
@@ -736,28 +763,32 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   const int v = va + r / rpr;
   const int th0 = t * R;
   const int pl = v * nth + th0;             // offset inside the (v, theta) plane
-  const int pll = (v - vbase) * nth + th0;  // the same inside the LDS copy
-  const int offe = y * nv * nth + pl;
-  const uint32_t oc = (uint32_t)offe * E;
-  uint32_t oy[4];
+  const int pll = (v - vbase) * rowl + t * SL;  // the run's slot in the LDS copy
   int lv[4];
   {
     const int o[4] = {-2, -1, 1, 2};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
       // a segment's halo rows hold v - 2 .. v + 2 unwrapped on a periodic v
       const int vk = (SEG && perv) ? v + o[k] : wrap_or_clamp(v + o[k], nv, perv);
-      lv[k] = (vk - vbase) * nth + th0;
+      lv[k] = (vk - vbase) * rowl + t * SL;
     }
   }
   uint32_t lh[4];  // theta halos inside the LDS plane (see the streaming kernel)
-  theta_halo_offsets<R>((v - vbase) * nth, th0, nth, lh);
+  if constexpr (R == 3) {
+    // the last two elements of the previous run's slot, the first two of the next run's
+    const int base = (v - vbase) * rowl;
+    lh[0] = (uint32_t)(base + (t == 0 ? rpr - 1 : t - 1) * SL + 1);
+    lh[1] = lh[0] + 1;
+    lh[2] = (uint32_t)(base + (t == rpr - 1 ? 0 : t + 1) * SL);
+    lh[3] = lh[2] + 1;
+  } else {
+    theta_halo_offsets<R>((v - vbase) * nth, th0, nth, lh);
+  }
   // the v fix-ups run in the waves that hold an edge lane (branching on a
   // wave-uniform flag keeps the selects out of every other wave); y is the
   // block's
   const bool vedge = __ballot(!perv && (v < 2 || v >= nv - 2)) != 0;
-  const bool yedge = !pery && (y < 2 || y >= ny - 2);
   // theta-axis coefficients of this thread's v (see StreamArgs::coef_th)
   const T kpt = a.coef_th[v], kmt = a.coef_th[nv + v], sgt = a.coef_th[2 * nv + v];
   T kpx[R], kmx[R], kpy[R], kmy[R];
@@ -770,70 +801,23 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
   }
   const bool ball_x = (a.ball_mask & 1u) != 0, ball_y = (a.ball_mask & 2u) != 0;
   const bool ball_v = (a.ball_mask & 4u) != 0, ball_t = (a.ball_mask & 8u) != 0;
+  // the stage's form: compile-time constants unless FORM is kFormRuntime
+  constexpr bool kRT = FORM == kFormRuntime;
+  const bool avg = kRT ? a.mode == kAverage : FORM == kFormAverageXY;
+  const bool clamp = kRT ? a.clamp != 0 : FORM != kFormPlain;
+  const bool xy = kRT ? a.v0xy != nullptr : true;  // clamp value from the Nx x Ny table
+  const bool fold_eps = kRT && a.eps != nullptr;
 
   const uint32_t pb = (uint32_t)a.plane * E;
   const uint32_t total = pb * (uint32_t)nx;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vs, total);
-  const __amdgpu_buffer_rsrc_t rvn = make_rsrc(a.vn, a.mode == kAverage ? total : 0u);
-  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, (a.clamp && !a.v0xy) ? total : 0u);
-  const int x0 = chunk * a.chunk_len;
-  const int x1 = min(nx, x0 + a.chunk_len);
+  const __amdgpu_buffer_rsrc_t rnull = make_rsrc(a.vs, 0u);  // loads through it return 0, no memory access
+  const __amdgpu_buffer_rsrc_t rvn = make_rsrc(a.vn, avg ? total : 0u);
+  const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, (clamp && !xy) ? total : 0u);
   constexpr int FR = DERIV == kEno2 ? 2 : 1;
-  const int psz = (SEG ? a.v_seg + 4 : nv) * nth;  // values per LDS buffer
-  // SEG halo rows va-2, va-1, va+nvs, va+nvs+1 (those that exist): thread
-  // h < 4 rpr copies run h % rpr of row h / rpr, loading it one plane ahead
-  bool hcopy = false;
-  uint32_t hoff = 0;
-  int hl = 0;
-  T H[R];
-  if constexpr (SEG) {
-    const int h = (int)threadIdx.x, hk = h / rpr, ht = h - hk * rpr;
-    const int hv = hk < 2 ? va - 2 + hk : va + nvs + (hk - 2);
-    hcopy = h < 4 * rpr && (perv || (hv >= 0 && hv < nv));
-    const int hw = hv < 0 ? hv + nv : (hv >= nv ? hv - nv : hv);
-    hoff = (uint32_t)((y * nv + (hcopy ? hw : 0)) * nth + ht * R) * E;
-    hl = (hv - vbase) * nth + ht * R;
-    if (hcopy) bload<T, R>(rs, hoff, (uint32_t)x0 * pb, H);
-  }
+  const int psz = (SEG ? a.v_seg + 4 : nv) * rowl;  // values per LDS buffer
 
-  // x ring: slot S[(P + k) & 3] holds V(X + k) at phase P = (X - x0) & 3
-  // (k = 0 .. FR, and the front of the next plane loading into the last);
-  // the rotating slots and the difference pairs need no register moves once
-  // the loop is unrolled by four.  D[(P + k) & 3] = V(X + k) - V(X + k - 1)
-  // for k = 0, 1 (and 2 once computed); Q[i], M[i]: the second difference at
-  // X and the ENO choice between X-1 and X, for the current (i = P & 1) and
-  // next plane.
-  T S[4][R], D[4][R], Q[2][R], M[2][R];
-  if (DERIV == kEno2) {
-    T wm2[R], wm1[R];
-    x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
-    x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
-    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, S[0]);
-    x_plane_b<T, R>(rs, x0 + 1, nx, perx, pb, oc, S[1]);
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      D[0][j] = S[0][j] - wm1[j];
-      D[1][j] = S[1][j] - S[0][j];
-      T qm = D[0][j] - (wm1[j] - wm2[j]);
-      Q[0][j] = D[1][j] - D[0][j];
-      M[0][j] = choose(qm, Q[0][j]);
-    }
-  } else {
-    T wm1[R];
-    x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
-    x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, S[0]);
-#pragma unroll
-    for (int j = 0; j < R; ++j) D[0][j] = S[0][j] - wm1[j];
-  }
-  x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, S[FR]);
-  // y neighbours of the current plane (y - 2, y - 1, y + 1, y + 2): loaded
-  // at the end of the previous plane, as soon as that plane has used them
-  T Y[4][R];
-  if (DERIV == kEno2) bload<T, R>(rs, oy[0], (uint32_t)x0 * pb, Y[0]);
-  bload<T, R>(rs, oy[1], (uint32_t)x0 * pb, Y[1]);
-  bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
-  if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
-
+  // the accumulators of the range pass and the eps fold span every segment
   // RANGE: the smallest and largest derivative (unscaled, h p) per axis
   // over this thread's nodes -- of the central one (p- + p+) / 2, or of both
   // one-sided ones; nothing is written but the keys
@@ -852,210 +836,311 @@ __global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane(StreamArgs<T> a)
     rhi[d] = mx > rhi[d] ? mx : rhi[d];
   };
   double em = 0.0;  // largest change of this thread's nodes (when a.eps is set)
-  auto plane = [&](auto phase, const int X) {
-    constexpr int P = decltype(phase)::value;
-    constexpr int I0 = P & 3, I1 = (P + 1) & 3, IF = (P + FR) & 3, IL = (P + FR + 1) & 3;
-    constexpr int DC = P & 1, DN = (P + 1) & 1;
-    const uint32_t sX = (uint32_t)X * pb;
-    T *buf = lds + ((X - x0) & 1) * psz;
-    // ---- global loads of this plane (its y neighbours are in flight), then the next front
-    T(&yn2)[R] = Y[0];
-    T(&yn1)[R] = Y[1];
-    T(&yp1)[R] = Y[2];
-    T(&yp2)[R] = Y[3];
-    // pointwise streams of this plane (V^n, V0): issued now, used at the end
-    T vn[R], t0[R], tv = T(0);
-    if (a.mode == kAverage) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
-    if (a.clamp) {
-      if (a.v0xy)
-        tv = uniform_load(a.v0xy, X * ny + y);  // every run of the block shares (x, y)
-      else
-        bload<T, R, kCacheStream>(rv0, oc, sX, t0);
-    }
-    if (X + 1 < x1) {
-      const int xf = X + 1 + FR;
-      if (xf < nx)
-        bload<T, R>(rs, oc, (uint32_t)xf * pb, S[IL]);
-      else
-        x_plane_b<T, R>(rs, xf, nx, perx, pb, oc, S[IL]);
-    }
-    // ---- publish the centre run; c = V_X
-    const T(&c)[R] = S[I0];
-    if (active) {
-      typedef typename VecT<T, R>::type V;
-      V cv;
-#pragma unroll
-      for (int j = 0; j < R; ++j) cv[j] = c[j];
-      *reinterpret_cast<V *>(buf + pll) = cv;
-    }
-    if constexpr (SEG) {
-      if (hcopy) {
-        typedef typename VecT<T, R>::type V;
-        V hv;
-#pragma unroll
-        for (int j = 0; j < R; ++j) hv[j] = H[j];
-        *reinterpret_cast<V *>(buf + hl) = hv;
-        if (X + 1 < x1) bload<T, R>(rs, hoff, sX + pb, H);
-      }
-    }
-    T L[R], b2[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      L[j] = T(0);
-      b2[j] = T(0);
-    }
-    // ---- x from the ring (registers only, overlaps the barrier wait)
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      T pm, pp;
-      if (DERIV == kEno2) {
-        D[(P + 2) & 3][j] = S[IF][j] - S[I1][j];
-        Q[DN][j] = D[(P + 2) & 3][j] - D[(P + 1) & 3][j];
-        M[DN][j] = choose(Q[DC][j], Q[DN][j]);
-        pm = D[P & 3][j] + T(0.5) * M[DC][j];
-        pp = D[(P + 1) & 3][j] - T(0.5) * M[DN][j];
-      } else {
-        D[(P + 1) & 3][j] = S[IF][j] - S[I0][j];
-        pm = D[P & 3][j];
-        pp = D[(P + 1) & 3][j];
-      }
-      if constexpr (RANGE)
-        rng(0, pm, pp);
-      else
-        accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
-    }
-    __syncthreads();
-    // ---- theta: halos from LDS
+  int pcb = 0;  // planes done in earlier segments (the LDS buffer's parity)
+  int64_t idx = 0, idx_end = 1;  // span mode: this block's row-planes
+  if (a.span) {
+    const int64_t W = (int64_t)ny * nx;
+    idx = (int64_t)lb * W / gridDim.x;
+    idx_end = ((int64_t)lb + 1) * W / gridDim.x;
+  }
+  while (idx < idx_end) {
+    // this segment: row y, planes [x0, x1)
+    const int y = a.span ? (int)(idx / nx) : (SEG ? rem - seg * ny : rem);
+    const int x0 = a.span ? (int)(idx - (int64_t)y * nx) : chunk * a.chunk_len;
+    const int x1 = a.span ? (int)min((int64_t)nx, x0 + (idx_end - idx)) : min(nx, x0 + a.chunk_len);
+    idx = a.span ? idx + (x1 - x0) : idx_end;
+    const int offe = y * nv * nth + pl;
+    const uint32_t oc = (uint32_t)offe * E;
+    uint32_t oy[4];
     {
-      T u[R + 4];
-      if constexpr (R >= 2) {
-        lds_pair<T>(buf + lh[0], u[0], u[1]);
-        lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
-      } else {
-        u[0] = buf[lh[0]];
-        u[1] = buf[lh[1]];
-        u[3] = buf[lh[2]];
-        u[4] = buf[lh[3]];
+      const int o[4] = {-2, -1, 1, 2};
+  #pragma unroll
+      for (int k = 0; k < 4; ++k) oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
+    }
+    const bool yedge = !pery && (y < 2 || y >= ny - 2);
+    // SEG halo rows va-2, va-1, va+nvs, va+nvs+1 (those that exist): thread
+    // h < 4 rpr copies run h % rpr of row h / rpr, loading it one plane ahead
+    bool hcopy = false;
+    uint32_t hoff = 0;
+    int hl = 0;
+    T H[R];
+    if constexpr (SEG) {
+      const int h = (int)threadIdx.x, hk = h / rpr, ht = h - hk * rpr;
+      const int hv = hk < 2 ? va - 2 + hk : va + nvs + (hk - 2);
+      hcopy = h < 4 * rpr && (perv || (hv >= 0 && hv < nv));
+      const int hw = hv < 0 ? hv + nv : (hv >= nv ? hv - nv : hv);
+      hoff = (uint32_t)((y * nv + (hcopy ? hw : 0)) * nth + ht * R) * E;
+      hl = (hv - vbase) * rowl + ht * SL;
+      if (hcopy) bload<T, R>(rs, hoff, (uint32_t)x0 * pb, H);
+    }
+
+    // x ring: slot S[(P + k) & 3] holds V(X + k) at phase P = (X - x0) & 3
+    // (k = 0 .. FR, and the front of the next plane loading into the last);
+    // the rotating slots and the difference pairs need no register moves once
+    // the loop is unrolled by four.  D[(P + k) & 3] = V(X + k) - V(X + k - 1)
+    // for k = 0, 1 (and 2 once computed); Q[i], M[i]: the second difference at
+    // X and the ENO choice between X-1 and X, for the current (i = P & 1) and
+    // next plane.
+    T S[4][R], D[4][R], Q[2][R], M[2][R];
+    if (DERIV == kEno2) {
+      T wm2[R], wm1[R];
+      x_plane_b<T, R>(rs, x0 - 2, nx, perx, pb, oc, wm2);
+      x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
+      x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, S[0]);
+      x_plane_b<T, R>(rs, x0 + 1, nx, perx, pb, oc, S[1]);
+  #pragma unroll
+      for (int j = 0; j < R; ++j) {
+        D[0][j] = S[0][j] - wm1[j];
+        D[1][j] = S[1][j] - S[0][j];
+        T qm = D[0][j] - (wm1[j] - wm2[j]);
+        Q[0][j] = D[1][j] - D[0][j];
+        M[0][j] = choose(qm, Q[0][j]);
       }
-#pragma unroll
-      for (int j = 0; j < R; ++j) u[j + 2] = c[j];
-      // e[k] = u[k+1] - u[k]; the second difference at u[k] is e[k] - e[k-1]
-      T e[R + 3];
-#pragma unroll
-      for (int k = 0; k < R + 3; ++k)
-        if (DERIV == kEno2 || (k >= 1 && k <= R + 1)) e[k] = u[k + 1] - u[k];  // upwind: no outer halo
-      T mprev = T(0);
-      if (DERIV == kEno2) mprev = choose(e[1] - e[0], e[2] - e[1]);
-#pragma unroll
+    } else {
+      T wm1[R];
+      x_plane_b<T, R>(rs, x0 - 1, nx, perx, pb, oc, wm1);
+      x_plane_b<T, R>(rs, x0, nx, perx, pb, oc, S[0]);
+  #pragma unroll
+      for (int j = 0; j < R; ++j) D[0][j] = S[0][j] - wm1[j];
+    }
+    x_plane_b<T, R>(rs, x0 + FR, nx, perx, pb, oc, S[FR]);
+    // y neighbours of the current plane (y - 2, y - 1, y + 1, y + 2): loaded
+    // at the end of the previous plane, as soon as that plane has used them
+    T Y[4][R];
+    if (DERIV == kEno2) bload<T, R>(rs, oy[0], (uint32_t)x0 * pb, Y[0]);
+    bload<T, R>(rs, oy[1], (uint32_t)x0 * pb, Y[1]);
+    bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
+    if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
+    auto plane = [&](auto phase, const int X) {
+      constexpr int P = decltype(phase)::value;
+      constexpr int I0 = P & 3, I1 = (P + 1) & 3, IF = (P + FR) & 3, IL = (P + FR + 1) & 3;
+      constexpr int DC = P & 1, DN = (P + 1) & 1;
+      const uint32_t sX = (uint32_t)X * pb;
+      T *buf = lds + ((pcb + P) & 1) * psz;  // LDS planes alternate across segments too
+      // ---- the front of this plane (V(X + FR), loaded by the previous plane)
+      // lies beyond the end of an open x axis: its ghost, k layers out, from the
+      // two end planes in the ring (the slot of V(X - 1) is still unwritten)
+      if (X > x0 && !perx && X + FR >= nx) {
+        const int k = X + FR - (nx - 1);
+        if (k == 1) {
+  #pragma unroll
+          for (int j = 0; j < R; ++j)
+            S[IF][j] = S[(P + FR - 1) & 3][j] + T(1) * (S[(P + FR - 1) & 3][j] - S[(P + FR - 2) & 3][j]);
+        } else {
+  #pragma unroll
+          for (int j = 0; j < R; ++j)
+            S[IF][j] = S[(P + FR - 2) & 3][j] + T(2) * (S[(P + FR - 2) & 3][j] - S[(P + FR - 3) & 3][j]);
+        }
+      }
+      // ---- global loads of this plane (its y neighbours are in flight), then the next front
+      T(&yn2)[R] = Y[0];
+      T(&yn1)[R] = Y[1];
+      T(&yp1)[R] = Y[2];
+      T(&yp2)[R] = Y[3];
+      // pointwise streams of this plane (V^n, V0): issued now, used at the end
+      T vn[R], t0[R], tv = T(0);
+      if (avg) bload<T, R, kCacheStream>(rvn, oc, sX, vn);
+      if (clamp) {
+        if (xy)
+          tv = uniform_load(a.v0xy, X * ny + y);  // every run of the block shares (x, y)
+        else
+          bload<T, R, kCacheStream>(rv0, oc, sX, t0);
+      }
+      {
+        // the next front, one load on every plane: none on the chunk's last
+        // plane and none beyond the end of an open x (its ghost is formed at
+        // the top of the plane that uses it) -- both through the empty
+        // resource; a periodic x wraps
+        const int xf = X + 1 + FR;
+        const bool on = X + 1 < x1 && (perx || xf < nx);
+        bload<T, R>(on ? rs : rnull, oc, on ? (uint32_t)(xf < nx ? xf : xf - nx) * pb : 0u, S[IL]);
+      }
+      // ---- publish the centre run; c = V_X
+      const T(&c)[R] = S[I0];
+      if (active) {
+        typedef typename VecT<T, SL>::type V;
+        V cv;
+  #pragma unroll
+        for (int j = 0; j < SL; ++j) cv[j] = j < R ? c[j] : T(0);
+        *reinterpret_cast<V *>(buf + pll) = cv;
+      }
+      if constexpr (SEG) {
+        if (hcopy) {
+          typedef typename VecT<T, R>::type V;
+          V hv;
+  #pragma unroll
+          for (int j = 0; j < R; ++j) hv[j] = H[j];
+          *reinterpret_cast<V *>(buf + hl) = hv;
+          if (X + 1 < x1) bload<T, R>(rs, hoff, sX + pb, H);
+        }
+      }
+      T L[R], b2[R];
+  #pragma unroll
+      for (int j = 0; j < R; ++j) {
+        L[j] = T(0);
+        b2[j] = T(0);
+      }
+      // ---- x from the ring (registers only, overlaps the barrier wait)
+  #pragma unroll
       for (int j = 0; j < R; ++j) {
         T pm, pp;
         if (DERIV == kEno2) {
-          T mnext = choose(e[j + 2] - e[j + 1], e[j + 3] - e[j + 2]);
-          pm = e[j + 1] + T(0.5) * mprev;
-          pp = e[j + 2] - T(0.5) * mnext;
-          mprev = mnext;
+          D[(P + 2) & 3][j] = S[IF][j] - S[I1][j];
+          Q[DN][j] = D[(P + 2) & 3][j] - D[(P + 1) & 3][j];
+          M[DN][j] = choose(Q[DC][j], Q[DN][j]);
+          pm = D[P & 3][j] + T(0.5) * M[DC][j];
+          pp = D[(P + 1) & 3][j] - T(0.5) * M[DN][j];
         } else {
-          pm = e[j + 1];
-          pp = e[j + 2];
+          D[(P + 1) & 3][j] = S[IF][j] - S[I0][j];
+          pm = D[P & 3][j];
+          pp = D[(P + 1) & 3][j];
         }
         if constexpr (RANGE)
-          rng(3, pm, pp);
+          rng(0, pm, pp);
         else
-          accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
+          accumulate<T, SG, BALL>(L[j], b2[j], kpx[j], kmx[j], a.sg[0], pp, pm, ball_x, a.half_inv_h[0]);
       }
-    }
-    // ---- v: neighbours from LDS
-    {
-      T vn2[R], vn1[R], vp1[R], vp2[R];
-      if (DERIV == kEno2) lds_run<T, R>(buf + lv[0], vn2);
-      lds_run<T, R>(buf + lv[1], vn1);
-      lds_run<T, R>(buf + lv[2], vp1);
-      if (DERIV == kEno2) lds_run<T, R>(buf + lv[3], vp2);
-      T pmv[R], ppv[R];
-#pragma unroll
-      for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pmv[j], ppv[j]);
-      if (vedge) {
-        keep_branch();
-#pragma unroll
-        for (int j = 0; j < R; ++j) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pmv[j], ppv[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if constexpr (RANGE)
-          rng(2, pmv[j], ppv[j]);
-        else
-          accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
-      }
-    }
-    // ---- y: neighbours from global memory
-    T pmy[R], ppy[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pmy[j], ppy[j]);
-    if (yedge) {
-      keep_branch();
-#pragma unroll
-      for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pmy[j], ppy[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      if constexpr (RANGE)
-        rng(1, pmy[j], ppy[j]);
-      else
-        accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
-    }
-    if (X + 1 < x1) {
-      if (DERIV == kEno2) bload<T, R>(rs, oy[0], sX + pb, Y[0]);
-      bload<T, R>(rs, oy[1], sX + pb, Y[1]);
-      bload<T, R>(rs, oy[2], sX + pb, Y[2]);
-      if (DERIV == kEno2) bload<T, R>(rs, oy[3], sX + pb, Y[3]);
-    }
-    if constexpr (!RANGE) {
-      // ---- update
-      T res[R];
-  #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        T Lj = L[j];
-        if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
-        res[j] = fma(a.dt, Lj, c[j]);
-      }
-      if (a.mode == kAverage) {
-  #pragma unroll
-        for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
-      }
-      if (a.clamp) {
-        if (a.v0xy) {
-  #pragma unroll
-          for (int j = 0; j < R; ++j) res[j] = tv < res[j] ? tv : res[j];
+      __syncthreads();
+      // ---- theta: halos from LDS
+      {
+        T u[R + 4];
+        if constexpr (R == 3) {
+          u[0] = buf[lh[0]];  // a 4-byte aligned pair
+          u[1] = buf[lh[1]];
+          lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
+        } else if constexpr (R >= 2) {
+          lds_pair<T>(buf + lh[0], u[0], u[1]);
+          lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
         } else {
-  #pragma unroll
-          for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+          u[0] = buf[lh[0]];
+          u[1] = buf[lh[1]];
+          u[3] = buf[lh[2]];
+          u[4] = buf[lh[3]];
         }
-      }
-      if (a.eps) {
+  #pragma unroll
+        for (int j = 0; j < R; ++j) u[j + 2] = c[j];
+        // e[k] = u[k+1] - u[k]; the second difference at u[k] is e[k] - e[k-1]
+        T e[R + 3];
+  #pragma unroll
+        for (int k = 0; k < R + 3; ++k)
+          if (DERIV == kEno2 || (k >= 1 && k <= R + 1)) e[k] = u[k + 1] - u[k];  // upwind: no outer halo
+        T mprev = T(0);
+        if (DERIV == kEno2) mprev = choose(e[1] - e[0], e[2] - e[1]);
   #pragma unroll
         for (int j = 0; j < R; ++j) {
-          double d = fabs((double)res[j] - (double)(a.mode == kAverage ? vn[j] : c[j]));
-          if (d != d) d = INFINITY;
-          em = (active && d > em) ? d : em;
+          T pm, pp;
+          if (DERIV == kEno2) {
+            T mnext = choose(e[j + 2] - e[j + 1], e[j + 3] - e[j + 2]);
+            pm = e[j + 1] + T(0.5) * mprev;
+            pp = e[j + 2] - T(0.5) * mnext;
+            mprev = mnext;
+          } else {
+            pm = e[j + 1];
+            pp = e[j + 2];
+          }
+          if constexpr (RANGE)
+            rng(3, pm, pp);
+          else
+            accumulate<T, true, BALL>(L[j], b2[j], kpt, kmt, sgt, pp, pm, ball_t, a.half_inv_h[3]);
         }
       }
-      if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
-    }
-  };
+      // ---- v: neighbours from LDS
+      {
+        T vn2[R], vn1[R], vp1[R], vp2[R];
+        if (DERIV == kEno2) lds_run<T, R>(buf + lv[0], vn2);
+        lds_run<T, R>(buf + lv[1], vn1);
+        lds_run<T, R>(buf + lv[2], vp1);
+        if (DERIV == kEno2) lds_run<T, R>(buf + lv[3], vp2);
+        T pmv[R], ppv[R];
+  #pragma unroll
+        for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(vn2[j], vn1[j], c[j], vp1[j], vp2[j], pmv[j], ppv[j]);
+        if (vedge) {
+          keep_branch();
+  #pragma unroll
+          for (int j = 0; j < R; ++j) edge_diffs<T>(v, nv, vn1[j], c[j], vp1[j], pmv[j], ppv[j]);
+        }
+  #pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if constexpr (RANGE)
+            rng(2, pmv[j], ppv[j]);
+          else
+            accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
+        }
+      }
+      // ---- y: neighbours from global memory
+      T pmy[R], ppy[R];
+  #pragma unroll
+      for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pmy[j], ppy[j]);
+      if (yedge) {
+        keep_branch();
+  #pragma unroll
+        for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pmy[j], ppy[j]);
+      }
+  #pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if constexpr (RANGE)
+          rng(1, pmy[j], ppy[j]);
+        else
+          accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
+      }
+      {
+        // the next plane's y neighbours (none after the chunk's last plane)
+        const __amdgpu_buffer_rsrc_t ry = X + 1 < x1 ? rs : rnull;
+        if (DERIV == kEno2) bload<T, R>(ry, oy[0], sX + pb, Y[0]);
+        bload<T, R>(ry, oy[1], sX + pb, Y[1]);
+        bload<T, R>(ry, oy[2], sX + pb, Y[2]);
+        if (DERIV == kEno2) bload<T, R>(ry, oy[3], sX + pb, Y[3]);
+      }
+      if constexpr (!RANGE) {
+        // ---- update
+        T res[R];
+    #pragma unroll
+        for (int j = 0; j < R; ++j) {
+          T Lj = L[j];
+          if (BALL) Lj = fma(a.sig_ball, sqrt(b2[j]), Lj);
+          res[j] = fma(a.dt, Lj, c[j]);
+        }
+        if (avg) {
+    #pragma unroll
+          for (int j = 0; j < R; ++j) res[j] = T(0.5) * (vn[j] + res[j]);
+        }
+        if (clamp) {
+          if (xy) {
+    #pragma unroll
+            for (int j = 0; j < R; ++j) res[j] = tv < res[j] ? tv : res[j];
+          } else {
+    #pragma unroll
+            for (int j = 0; j < R; ++j) res[j] = t0[j] < res[j] ? t0[j] : res[j];
+          }
+        }
+        if (fold_eps) {
+    #pragma unroll
+          for (int j = 0; j < R; ++j) {
+            double d = fabs((double)res[j] - (double)(avg ? vn[j] : c[j]));
+            if (d != d) d = INFINITY;
+            em = (active && d > em) ? d : em;
+          }
+        }
+        if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
+      }
+    };
 
-  // four planes per trip: every slot index above is a compile-time constant
-  int X = x0;
-  for (;;) {
-    if (X >= x1) break;
-    plane(std::integral_constant<int, 0>(), X++);
-    if (X >= x1) break;
-    plane(std::integral_constant<int, 1>(), X++);
-    if (X >= x1) break;
-    plane(std::integral_constant<int, 2>(), X++);
-    if (X >= x1) break;
-    plane(std::integral_constant<int, 3>(), X++);
+    // four planes per trip: every slot index above is a compile-time constant
+    int X = x0;
+    for (;;) {
+      if (X >= x1) break;
+      plane(std::integral_constant<int, 0>(), X++);
+      if (X >= x1) break;
+      plane(std::integral_constant<int, 1>(), X++);
+      if (X >= x1) break;
+      plane(std::integral_constant<int, 2>(), X++);
+      if (X >= x1) break;
+      plane(std::integral_constant<int, 3>(), X++);
+    }
+
+    pcb += x1 - x0;
   }
-  if (a.eps) {
+  if (fold_eps) {
     em = wave_max_d(em);
     if ((threadIdx.x & 63) == 0) atomicMax(a.eps, (unsigned long long)__double_as_longlong(em));
   }
@@ -1207,23 +1292,63 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
   return sg ? launch_stream_v<T, DERIV, true, false>(a, s) : launch_stream_v<T, DERIV, false, false>(a, s);
 }
 
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE>
+void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, size_t lds, hipStream_t s) {
+  // the compiled-in forms (not for the ball test dynamics); the eps fold and
+  // the 4D clamp target take the runtime form
+  int form = kFormRuntime;
+  if (RANGE)
+    form = kFormPlain;
+  else if (!BALL && !a.eps) {
+    if (a.mode == kPlain && !a.clamp)
+      form = kFormPlain;
+    else if (a.mode == kPlain && a.clamp && a.v0xy)
+      form = kFormPlainXY;
+    else if (a.mode == kAverage && a.clamp && a.v0xy)
+      form = kFormAverageXY;
+  }
+  if (form == kFormPlain)
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, RANGE, kFormPlain>), dim3(blocks), dim3(threads), lds,
+                       s, a);
+  else if constexpr (!RANGE && !BALL) {
+    if (form == kFormPlainXY)
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormPlainXY>), dim3(blocks), dim3(threads),
+                         lds, s, a);
+    else if (form == kFormAverageXY)
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormAverageXY>), dim3(blocks),
+                         dim3(threads), lds, s, a);
+    else
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormRuntime>), dim3(blocks), dim3(threads),
+                         lds, s, a);
+  } else if constexpr (!RANGE) {
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormRuntime>), dim3(blocks), dim3(threads),
+                       lds, s, a);
+  }
+}
+
 template <typename T, int R, int DERIV, bool SG, bool BALL, bool RANGE = false>
 hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
   const bool seg = a.n_seg > 1;
   const int rows = seg ? a.v_seg : a.n[2];
   const int runs = rows * a.runs_per_row;
-  if (runs > kPlaneMaxThreads || a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1) ||
+  constexpr int SL = R == 3 ? 4 : R;  // LDS elements per run
+  if (runs > (R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) || a.run != R || a.span < 0 || (a.span && seg) ||
+      a.runs_per_row * R != a.n[3] || (R == 3 && seg) || a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1) ||
       (seg && (a.v_seg < kPlaneMinSegRows || (int64_t)a.v_seg * a.n_seg < a.n[2] ||
                (int64_t)a.v_seg * (a.n_seg - 1) >= a.n[2])))
     return hipErrorInvalidValue;
   const int threads = (runs + 63) / 64 * 64;
-  const size_t lds = 2 * (size_t)(seg ? a.v_seg + 4 : a.n[2]) * a.n[3] * sizeof(T);
+  const size_t lds = 2 * (size_t)(seg ? a.v_seg + 4 : a.n[2]) * a.runs_per_row * SL * sizeof(T);
   if (lds > (size_t)kPlaneMaxLdsBytes) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)(a.blocks_per_chunk * a.n_chunks);
-  if (seg)
-    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, true, RANGE>), dim3(blocks), dim3(threads), lds, s, a);
-  else
-    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, false, RANGE>), dim3(blocks), dim3(threads), lds, s, a);
+  const unsigned blocks = a.span ? (unsigned)a.span : (unsigned)(a.blocks_per_chunk * a.n_chunks);
+  if constexpr (R == 3) {
+    launch_plane_form<T, R, DERIV, SG, BALL, false, RANGE>(a, blocks, threads, lds, s);
+  } else {
+    if (seg)
+      launch_plane_form<T, R, DERIV, SG, BALL, true, RANGE>(a, blocks, threads, lds, s);
+    else
+      launch_plane_form<T, R, DERIV, SG, BALL, false, RANGE>(a, blocks, threads, lds, s);
+  }
   return hipGetLastError();
 }
 
@@ -1233,8 +1358,10 @@ template <typename T, int DERIV, bool SG, bool BALL>
 hipError_t launch_plane_v(const StreamArgs<T> &a, hipStream_t s) {
   if (a.run == 1) return launch_plane_r<T, 1, DERIV, SG, BALL>(a, s);
   if (a.run == 2) return launch_plane_r<T, 2, DERIV, SG, BALL>(a, s);
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) == 4) {
     if (a.run == 4) return launch_plane_r<T, 4, DERIV, SG, BALL>(a, s);
+    if (a.run == 3) return launch_plane_r<T, 3, DERIV, SG, BALL>(a, s);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -1878,8 +2005,10 @@ hipError_t launch_plane_range(StreamArgs<T> a, int deriv, hipStream_t s) {
     constexpr int D = decltype(deriv_c)::value;
     if (a.run == 1) return launch_plane_r<T, 1, D, false, false, true>(a, s);
     if (a.run == 2) return launch_plane_r<T, 2, D, false, false, true>(a, s);
-    if constexpr (sizeof(T) == 4)
+    if constexpr (sizeof(T) == 4) {
       if (a.run == 4) return launch_plane_r<T, 4, D, false, false, true>(a, s);
+      if (a.run == 3) return launch_plane_r<T, 3, D, false, false, true>(a, s);
+    }
     return hipErrorInvalidValue;
   };
   if (deriv == kUpwind1) return by_run(std::integral_constant<int, kUpwind1>());

@@ -326,26 +326,38 @@ def rough_input(grid, V0, seed, precision):
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_large_120_one_step_operator(monkeypatch, precision):
     """120x120x40x72, ENO2 + TVD-RK2, cylinder target (its x-y table form),
-    in the launch configuration the benchmark times (plane kernel, 2 x
-    chunks): from a seeded rough input, one full GPU step against the oracle
-    at every node.  FP64: |dV| <= 16 u max(|V|, 1) (same inputs, same
-    second-difference formula, so the same ENO choices).  FP32: within
-    16 u of the oracle's binary32-decision interval (assert_f32_step)."""
+    in the launch configurations the benchmark's autotuner chooses between
+    (plane kernel with 2 x chunks, and in FP32 256 blocks sharing all
+    row-planes):
+    from a seeded rough input, one full GPU step against the oracle at every
+    node.  FP64: |dV| <= 16 u max(|V|, 1) (same inputs, same second-difference
+    formula, so the same ENO choices).  FP32: within 16 u of the oracle's
+    binary32-decision interval (assert_f32_step)."""
     from paper_2012_04011_amd import hj
 
-    monkeypatch.setenv("HJ_X_CHUNKS", "2")
     wl = W.LARGE_120
     cyl = W.cylinders(0, wl.obstacles)
     V0 = oracle.target_cylinders(wl.grid, *cyl)
     Vk = rough_input(wl.grid, V0, 1, precision)
     dt = oracle.cfl_dt(wl.grid, wl.dyn, wl.scheme["cfl"], wl.horizon)
-    with hj.Grid(wl.grid, wl.dyn, wl.scheme, precision) as g:
-        g.set_target_cylinders(*cyl)
-        li = g.launch_info()
-        assert li["kernel"] == "plane" and li["x_chunks"] == 2 and li["target_xy"]
-        g.set_value(Vk)
-        g.step(dt)
-        V1 = g.value()
+    outs = []
+    # span mode covers whole (v, theta) planes; the FP64 plane here is split along v
+    for chunks, span in (("2", None), ("1", "256")) if precision == "f32" else (("2", None),):
+        monkeypatch.setenv("HJ_X_CHUNKS", chunks)
+        if span:
+            monkeypatch.setenv("HJ_PLANE_SPAN", span)
+        else:
+            monkeypatch.delenv("HJ_PLANE_SPAN", raising=False)
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, precision) as g:
+            g.set_target_cylinders(*cyl)
+            li = g.launch_info()
+            assert li["kernel"] == "plane" and li["target_xy"]
+            assert li["span_blocks"] == (int(span) if span else 0) and (span or li["x_chunks"] == 2)
+            g.set_value(Vk)
+            g.step(dt)
+            outs.append(g.value())
+    assert all(np.array_equal(o, outs[0]) for o in outs)
+    V1 = outs[0]
     if precision == "f64":
         ref = oracle.step(wl.grid, wl.dyn, wl.scheme, V0, Vk, dt)
         err = np.abs(V1 - ref)
@@ -450,22 +462,36 @@ def test_each_stage_kernel_one_step(monkeypatch, kernel, shape, deriv, integ, pr
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_kernels_and_target_forms_bitwise_equal(monkeypatch, precision):
-    """The plane and streaming kernels and every x-chunking evaluate each node
-    with the same arithmetic, and the clamp gives the same result from the
-    cylinder target's x-y table as from the full 4D target: all bitwise
-    equal (so the autotuner's choice cannot change a result)."""
+    """The plane and streaming kernels, every x-chunking, span mode (blocks
+    sharing all row-planes) and both theta run lengths of the plane kernel
+    (4 and 3) evaluate each node with the same
+    arithmetic, and the clamp gives the same result from the cylinder
+    target's x-y table as from the full 4D target: all bitwise equal (so the
+    autotuner's choice cannot change a result)."""
     from paper_2012_04011_amd import hj
 
     wl = W.ENO_60_DIST
     cyl = W.cylinders(2, wl.obstacles)
     outs = {}
-    for kernel, chunks, form in [("plane", "3", "xy"), ("plane", "7", "xy"), ("stream", "2", "xy"),
-                                 ("stream", "5", "4d"), ("plane", "4", "4d")]:
+    # (kernel, x chunks, target form, plane run, span blocks): span mode
+    # shares all row-planes among that many blocks (7: each block sweeps parts
+    # of about nine rows; 256: one or two rows)
+    configs = [("plane", "3", "xy", None, None), ("plane", "7", "xy", None, None), ("stream", "2", "xy", None, None),
+               ("stream", "5", "4d", None, None), ("plane", "4", "4d", None, None),
+               ("plane", "1", "xy", None, "7"), ("plane", "1", "4d", None, "256")]
+    if precision == "f32":  # runs of 3 theta nodes beside the default runs of 4
+        configs += [("plane", "2", "xy", "3", None), ("plane", "5", "4d", "3", None), ("plane", "1", "xy", "3", "256")]
+    for kernel, chunks, form, run, span in configs:
         monkeypatch.setenv("HJ_X_CHUNKS", chunks)
         if kernel == "stream":
             monkeypatch.setenv("HJ_STAGE_KERNEL", "stream")
         else:
             monkeypatch.delenv("HJ_STAGE_KERNEL", raising=False)
+        for var, val in (("HJ_PLANE_RUN", run), ("HJ_PLANE_SPAN", span)):
+            if val:
+                monkeypatch.setenv(var, val)
+            else:
+                monkeypatch.delenv(var, raising=False)
         with hj.Grid(wl.grid, wl.dyn, wl.scheme, precision) as g:
             g.set_target_cylinders(*cyl)
             if form == "4d":
@@ -473,9 +499,12 @@ def test_kernels_and_target_forms_bitwise_equal(monkeypatch, precision):
             info = g.launch_info()
             assert info["kernel"] == kernel
             assert info["target_xy"] == (form == "xy")
+            if run:
+                assert info["theta_run"] == int(run)
+            assert info["span_blocks"] == (int(span) if span else 0)
             for _ in range(6):
                 g.step()
-            outs[(kernel, chunks, form)] = g.value()
+            outs[(kernel, chunks, form, run, span)] = g.value()
     ref = next(iter(outs.values()))
     for k, v in outs.items():
         assert np.array_equal(v, ref), k
