@@ -313,7 +313,8 @@ def bench_serve(args) -> int:
 
     def play_server(reqs, policy="small_first"):
         lat, done, idmap = [], 0, {}
-        with hj.Server(sch, "f32", hbm_budget=args.hbm_budget, max_inflight=64, stream=stream, policy=policy) as srv:
+        with hj.Server(sch, "f32", hbm_budget=args.hbm_budget, max_inflight=64, stream=stream, policy=policy,
+                       age_ms=args.age_ms) as srv:
             # warm three slots per class (first-use allocation, table and
             # CFL step: tens of milliseconds once per slot), so that
             # overlapping requests of a class find a resident grid, as the
@@ -400,6 +401,7 @@ def bench_serve(args) -> int:
             "workload": "serving: Poisson 20 req/s, 70/30 mix of 60x60x20x36 (82 steps) and 100x100x24x48 (121 "
                         "steps), 1-3 obstacle changes per request, horizon 1.5 s, ENO2+TVD-RK2 FP32",
             "requests": n_req, "point_steps": point_steps, "hbm_budget": args.hbm_budget,
+            "age_ms": args.age_ms or "library default (5)",
         },
         "latency_ms": {
             "server": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99), "max": float(lat_s.max())},
@@ -722,6 +724,8 @@ def main() -> int:
                     help="large120: arithmetic of the solve (the headline is FP32)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
     ap.add_argument("--hbm-budget", type=int, default=8 << 30, help="serve: slot memory budget in bytes")
+    ap.add_argument("--age-ms", type=float, default=0.0,
+                    help="serve: small-first age limit in ms after which requests go first (0: the library's)")
     ap.add_argument("--summarize-traffic", metavar="DIR")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="large120: skip the precision report (FP32 vs FP64 GPU solves, coarse-grid comparison)")

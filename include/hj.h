@@ -397,9 +397,9 @@ hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);
  *     fill the device alone) first, least remaining work (nodes times steps
  *     left) first, then the larger ones in the order they were submitted;
  *     requests are taken in that order until they hold 4 Mi nodes, the
- *     others wait for a later tick; a request left waiting 6 ticks in a row
- *     goes first at the next (in submission order), so no request waits
- *     without bound;
+ *     others wait for a later tick; requests older than age_ms (since
+ *     submission) go first, oldest first, so past that age the order is
+ *     first come, first served and no request waits without bound;
  *   HJ_SERVE_SHARE: every running request, every tick.
  * Among the requests of a tick, grids of fewer than 4 Mi nodes share one
  * launch per stage and step (each at its own step), larger ones fill the
@@ -417,6 +417,7 @@ typedef struct {
   int32_t steps_per_tick; /* time steps one tick enqueues for the running requests (0 = 4); at most
                            * two ticks are in flight, so new requests wait for <= 2 ticks */
   int32_t policy;        /* HJ_SERVE_SMALL_FIRST or HJ_SERVE_SHARE */
+  double age_ms;         /* small-first: age (ms since submission) after which a request goes first (0 = 5) */
 } hj_server_desc;
 
 typedef struct {

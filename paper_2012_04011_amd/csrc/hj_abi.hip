@@ -11,6 +11,7 @@
 #include <string>
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -1749,7 +1750,11 @@ constexpr int32_t kBatchDefaultXPlanes = 16;
 constexpr int64_t kServerBlocks = 1024;
 constexpr int64_t kServerAlonePoints = (int64_t)4 << 20;  // grids this large step on their own kernel
 constexpr int64_t kServerFillPoints = kServerAlonePoints;  // small-first: nodes that fill the device
-constexpr int kServerMaxSkips = 6;  // small-first: ticks a running request may be left waiting in a row
+constexpr double kServerAgeMs = 5.0;  // small-first: the default age after which a request goes first
+
+double host_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 int32_t batch_x_planes(const hj_batch *b) { return b->x_planes > 0 ? b->x_planes : kBatchDefaultXPlanes; }
 
@@ -2213,7 +2218,7 @@ struct hj_server {
     int slot = -1;
     int64_t n = 0, k = 0;
     double dt = 0, dt_last = 0;
-    int skipped = 0;  // consecutive ticks left waiting by the small-first order
+    double submitted_s = 0;  // host clock at submission (seconds)
     hipEvent_t ev = nullptr;
   };
   std::map<int64_t, Req> reqs;
@@ -2374,15 +2379,17 @@ hj_status server_step(hj_server *S) {
   // the requests that step this tick: all of them (sharing), or, in the
   // order small ones (least remaining work first) then large ones (first
   // submitted first), as many as it takes to fill the device -- except that
-  // a request left waiting kServerMaxSkips ticks in a row goes first (in
-  // submission order), so that a stream of small requests cannot hold a
-  // large one back without bound
+  // requests older than the age limit (since submission) go first, oldest
+  // first, so that a stream of small requests cannot hold a large one back:
+  // past the limit the order is first come, first served
   std::vector<int64_t> sel(S->running), wait;
   if (S->d.policy == HJ_SERVE_SMALL_FIRST) {
+    const double now = host_seconds();
+    const double age_s = (S->d.age_ms > 0 ? S->d.age_ms : kServerAgeMs) * 1e-3;
     auto npts = [&](int64_t id) { return S->slots[S->reqs[id].slot].g->npts; };
     auto key = [&](int64_t id) {
       const hj_server::Req &q = S->reqs[id];
-      if (q.skipped >= kServerMaxSkips) return std::make_pair(0, id);
+      if (now - q.submitted_s >= age_s) return std::make_pair(0, id);
       const bool large = npts(id) >= kServerFillPoints;
       return std::make_pair(large ? 2 : 1, large ? id : npts(id) * (q.n - q.k));
     };
@@ -2391,8 +2398,6 @@ hj_status server_step(hj_server *S) {
     for (int64_t pts = 0; take < sel.size() && pts < kServerFillPoints; ++take) pts += npts(sel[take]);
     wait.assign(sel.begin() + take, sel.end());
     sel.resize(take);
-    for (int64_t id : sel) S->reqs[id].skipped = 0;
-    for (int64_t id : wait) S->reqs[id].skipped += 1;
   }
   const int m = (int)sel.size();
   // longest remaining first, so the requests still stepping at step s of
@@ -2551,7 +2556,7 @@ hj_status hj_server_create(const hj_server_desc *desc, void *hip_stream, hj_serv
   if (!desc) return fail(HJ_ERR_INVALID_ARG, "null server description");
   if (desc->max_inflight < 1 || desc->max_inflight > hj::kMaxBatch)
     return fail(HJ_ERR_INVALID_ARG, "max_inflight must be 1..%d", hj::kMaxBatch);
-  if (desc->hbm_budget < 0 || desc->x_planes < 0 || desc->steps_per_tick < 0)
+  if (desc->hbm_budget < 0 || desc->x_planes < 0 || desc->steps_per_tick < 0 || !(desc->age_ms >= 0.0))
     return fail(HJ_ERR_INVALID_ARG, "negative budget, tile or steps per tick");
   if (desc->policy != HJ_SERVE_SMALL_FIRST && desc->policy != HJ_SERVE_SHARE)
     return fail(HJ_ERR_INVALID_ARG, "unknown server policy %d", desc->policy);
@@ -2618,6 +2623,7 @@ hj_status hj_server_submit(hj_server *S, const hj_grid_desc *grid, const hj_dyna
   q.cy.assign(cy, cy + m);
   q.r.assign(r, r + m);
   q.horizon = horizon;
+  q.submitted_s = host_seconds();
   int64_t nid = S->next_id++;
   S->reqs[nid] = q;
   S->queue.push_back(nid);

@@ -105,7 +105,8 @@ class hj_batch_info(ctypes.Structure):
 
 class hj_server_desc(ctypes.Structure):
     _fields_ = [("scheme", hj_scheme_desc), ("hbm_budget", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("x_planes", ctypes.c_int32), ("steps_per_tick", ctypes.c_int32), ("policy", ctypes.c_int32)]
+                ("x_planes", ctypes.c_int32), ("steps_per_tick", ctypes.c_int32), ("policy", ctypes.c_int32),
+                ("age_ms", ctypes.c_double)]
 
 
 class hj_server_stats(ctypes.Structure):
@@ -457,12 +458,14 @@ def hj_batch_get_info(b: int) -> dict:
 
 
 def hj_server_create(scheme: dict, precision: str = "f32", hbm_budget: int = 0, max_inflight: int = 64,
-                     x_planes: int = 0, stream=None, steps_per_tick: int = 0, policy: str = "small_first") -> int:
+                     x_planes: int = 0, stream=None, steps_per_tick: int = 0, policy: str = "small_first",
+                     age_ms: float = 0.0) -> int:
     d = hj_server_desc()
     d.scheme = scheme_desc(scheme, precision)
     d.hbm_budget, d.max_inflight, d.x_planes = int(hbm_budget), int(max_inflight), int(x_planes)
     d.steps_per_tick = int(steps_per_tick)
     d.policy = SERVE_POLICIES[policy] if isinstance(policy, str) else int(policy)
+    d.age_ms = float(age_ms)
     out = ctypes.c_void_p()
     _check(_lib.hj_server_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(out)), "hj_server_create")
     return out.value
@@ -653,9 +656,10 @@ class Server:
     """Continuous-batching re-solve server (see hj_server_create)."""
 
     def __init__(self, scheme: dict, precision: str = "f32", hbm_budget: int = 0, max_inflight: int = 64,
-                 x_planes: int = 0, stream=None, steps_per_tick: int = 0, policy: str = "small_first"):
+                 x_planes: int = 0, stream=None, steps_per_tick: int = 0, policy: str = "small_first",
+                 age_ms: float = 0.0):
         self.handle = hj_server_create(scheme, precision, hbm_budget, max_inflight, x_planes, stream, steps_per_tick,
-                                       policy)
+                                       policy, age_ms)
 
     def close(self):
         if getattr(self, "handle", None):

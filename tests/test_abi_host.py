@@ -174,5 +174,5 @@ def test_server_null_and_range_arguments(lib):
 
 
 def test_server_struct_layouts():
-    assert ctypes.sizeof(hj.hj_server_desc) == 56
+    assert ctypes.sizeof(hj.hj_server_desc) == 64
     assert ctypes.sizeof(hj.hj_server_stats) == 56

@@ -180,14 +180,17 @@ def test_served_mix_of_large_and_small_equals_alone():
         assert np.array_equal(results[rid], r), rid
 
 
-@pytest.mark.parametrize("policy", ["small_first", "share"])
-def test_policy_order_of_completion(policy):
+@pytest.mark.parametrize("policy,age_ms", [("small_first", 1e9), ("small_first", 1e-6), ("share", 0.0)],
+                         ids=["small_first", "small_first_aged", "share"])
+def test_policy_order_of_completion(policy, age_ms):
     """Two 60x60x20x36 requests with a long horizon (less work each than the
     100x100x24x48 request beside them, but more steps) and the large one,
-    submitted together.  Small-first steps the two small ones (together they
-    fill the device) and holds the large one, so both small ones finish
-    first; sharing steps all three and the large one, with fewer steps,
-    finishes first.  Every result equals its solve alone."""
+    submitted together.  Small-first (no request reaching the age limit)
+    steps the two small ones (together they fill the device) and holds the
+    large one, so both small ones finish first; past the age limit (here at
+    once) the order is first come, first served and the large one, submitted
+    first, finishes first; sharing steps all three and the large one, with
+    fewer steps, finishes first.  Every result equals its solve alone."""
     from paper_2012_04011_amd import hj
 
     small, large = W.SERVE_GRIDS
@@ -197,7 +200,8 @@ def test_policy_order_of_completion(policy):
     ref = [alone(hj, r) for r in reqs]
     work = [int(np.prod(r.grid["n"])) * info["steps"] for r, (_, info) in zip(reqs, ref)]
     assert work[1] < work[0] and work[2] < work[0] and ref[1][1]["steps"] > ref[0][1]["steps"]
-    with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=8, steps_per_tick=4, policy=policy) as srv:
+    with hj.Server(W.scheme("eno2", "rk2"), "f32", max_inflight=8, steps_per_tick=4, policy=policy,
+                   age_ms=age_ms) as srv:
         ids = [srv.submit(r.grid, r.dyn, r.cylinders, r.horizon) for r in reqs]
         shapes = {rid: tuple(r.grid["n"]) for rid, r in zip(ids, reqs)}
         order, results = [], {}
@@ -210,7 +214,7 @@ def test_policy_order_of_completion(policy):
                 srv.take(rid, out)
                 results[rid] = out
                 order.append(rid)
-    if policy == "small_first":
+    if policy == "small_first" and age_ms > 1e3:
         assert order[-1] == ids[0], order
     else:
         assert order[0] == ids[0], order
