@@ -206,9 +206,11 @@ def summarize_traffic(root: str, last: int = 200) -> int:
 def bench_batch(args) -> int:
     """The uneven 64-instance batch: every mode of hj_batch_solve beside the
     same solves run one grid at a time, fixed 16-plane tiles beside the
-    autotuned tile length.  One JSON line; throughput is whole-batch
-    point-steps over the solve time of the faster of the autotuned graph mode
-    and the concurrent-streams mode."""
+    autotuned tile length, and the launches on the streaming tiles alone
+    beside the default mix of batched plane-kernel classes and streaming
+    tiles.  One JSON line; throughput is whole-batch point-steps over the
+    solve time of the faster of the autotuned graph mode and the
+    concurrent-streams mode."""
     import numpy as np
     import torch
 
@@ -251,8 +253,17 @@ def bench_batch(args) -> int:
     tuned = b.autotune(H, "graph")
     res["graph_tuned"] = timed(lambda: b.solve(H, "graph"), args.steps)
     res["streams"] = timed(lambda: b.solve(H, "streams"), args.steps)
+    b.solve(H, "graph")
     info = b.info()
     b.close()
+    os.environ["HJ_BATCH_KERNEL"] = "stream"  # read when a batch is created
+    try:
+        bs = hj.Batch(grids)
+    finally:
+        del os.environ["HJ_BATCH_KERNEL"]
+    bs.set_tile(16)
+    res["graph_tiles_only"] = timed(lambda: bs.solve(H, "graph"), max(1, args.steps // 3))
+    bs.close()
     for g in grids:
         g.close()
     best = min(("graph_tuned", "streams"), key=lambda k: float(np.median(res[k])))
@@ -270,7 +281,7 @@ def bench_batch(args) -> int:
             "points": info["points"], "point_steps": point_steps,
             "mode": "graph" if best == "graph_tuned" else "streams",
             "x_planes_autotuned": tuned, "tiles_per_sweep": info["tiles_per_sweep"],
-            "graph_nodes": info["graph_nodes"],
+            "graph_nodes": info["graph_nodes"], "launch_classes": info["classes"],
         },
         "modes_ms": {
             "one_grid_at_a_time": float(np.median(one)),
@@ -278,11 +289,12 @@ def bench_batch(args) -> int:
             "graph_fixed16": float(np.median(res["graph"])),
             "persistent_fixed16": float(np.median(res["persistent"])),
             "graph_autotuned": float(np.median(res["graph_tuned"])),
+            "graph_streaming_tiles_only_fixed16": float(np.median(res["graph_tiles_only"])),
             "streams": float(np.median(res["streams"])),
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("batched stage kernel" if best == "graph_tuned" else
+                     "kernel": ("batched plane-kernel classes and streaming tiles" if best == "graph_tuned" else
                                 "single-grid stage kernels on four concurrent streams") +
                                " (whole solve, both stages)", "bytes_per_point_step": bpps},
     }

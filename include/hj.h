@@ -337,12 +337,17 @@ enum {
 
 typedef struct {
   int32_t m;                  /* instances */
-  int32_t x_planes;           /* x planes per tile (tile = 256 runs of theta nodes x x_planes) */
+  int32_t x_planes;           /* x planes per tile (streaming tile = 256 runs of theta nodes x x_planes;
+                                 plane block = one y row's (v, theta) plane x x_planes), for the kernel
+                                 of the last solve */
   int32_t persistent_blocks;  /* blocks of the last persistent launch */
   int32_t graph_nodes;        /* kernel nodes of the cached graph (0: none) */
   int64_t tiles_per_sweep;    /* tiles of one stage over all instances */
   int64_t work_items;         /* tiles over all stages of the last solve (0 after a streams-mode solve) */
   int64_t points;             /* grid nodes over all instances */
+  int32_t plane_kernel;       /* 1: the last solve's launches ran the batched plane kernel */
+  int32_t classes;            /* launch classes of the last solve (plane-kernel block sizes and the
+                                 streaming tiles), each class's launches on a lane of its own */
 } hj_batch_info;
 
 /* Group m (1..256) grid handles.  They must share precision, derivative
@@ -353,6 +358,16 @@ typedef struct {
  * handle, m out of range), HJ_ERR_UNSUPPORTED (mixed schemes, streams or a
  * non-periodic theta). */
 hj_status hj_batch_create(hj_grid *const *grids, int32_t m, hj_batch **out);
+/* Launch- and graph-mode solves run the batched plane kernel (each
+ * instance's blocks hold a y row's (v, theta) plane in LDS, as the
+ * single-grid plane kernel) for the instances whose plane fits one of its
+ * blocks of at most 768 work-items with runs of two or more theta nodes, and
+ * the streaming tiles for the others; the persistent mode always runs
+ * streaming tiles.  Launches are grouped into classes: plane blocks of 1-2,
+ * 3-4 and 5-12 waves, and the streaming tiles; with more than one class,
+ * each runs on a private stream forked from the batch stream and joined back
+ * into it.  HJ_BATCH_KERNEL=stream (read at create) keeps every instance on
+ * the streaming tiles. */
 hj_status hj_batch_destroy(hj_batch *b);
 
 /* Solve instance j over horizons[j] (finite, >= 0; m entries) from its
@@ -369,7 +384,8 @@ hj_status hj_batch_destroy(hj_batch *b);
  * if a persistent tile waited past the spin limit (values then undefined). */
 hj_status hj_batch_solve(hj_batch *b, const double *horizons, int32_t mode, hj_solve_info *infos);
 
-/* Tile shape: x planes per tile for every instance (0 = the default, 16). */
+/* Tile shape: x planes per tile for every instance (0 = the default: 16 for
+ * streaming tiles, 32 for the batched plane kernel). */
 hj_status hj_batch_set_tile(hj_batch *b, int32_t x_planes);
 
 /* Polls a persistent tile makes of its dependency counter before it gives up

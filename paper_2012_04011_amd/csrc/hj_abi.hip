@@ -586,14 +586,15 @@ hj::StageArgs<T> stage_args(hj_grid *G) {
 }
 
 // The streaming description of the handle's grid for its own stage kernel
-// (plane = the LDS plane kernel runs it, with the handle's plane run length)
-// or for the streaming tiles of the batched launches (plane = false).
+// (plane = the LDS plane kernel runs it, with the handle's plane run length
+// or with plane_run, one of the handle's two) or for the streaming tiles of
+// the batched launches (plane = false).
 template <typename T>
-hj::StreamArgs<T> stream_args(hj_grid *G, bool plane) {
+hj::StreamArgs<T> stream_args(hj_grid *G, bool plane, int plane_run = 0) {
   hj::StreamArgs<T> a;
   memset(&a, 0, sizeof a);
   const hj_grid_desc &g = G->g;
-  const int run = plane ? G->plane_run : hj::run_length((int)sizeof(T), g.n[3]);
+  const int run = plane ? (plane_run ? plane_run : G->plane_run) : hj::run_length((int)sizeof(T), g.n[3]);
   const int nseg = plane && run == 3 ? 1 : G->n_seg;  // runs of 3: whole planes
   for (int d = 0; d < 4; ++d) a.n[d] = g.n[d];
   a.periodic_mask = g.periodic_mask;
@@ -1700,6 +1701,7 @@ struct hj_batch {
   int deriv = 0;
   bool rk2 = false, sg = false, ball = false;
   int32_t x_planes = 0;  // 0: automatic
+  bool plane_allowed = true;  // launch and graph modes may run the batched plane kernel (HJ_BATCH_KERNEL)
   int64_t spin_limit = (int64_t)1 << 21;
   int cus = 0;
 
@@ -1747,6 +1749,7 @@ void batch_free(hj_batch *b) {
 }
 
 constexpr int32_t kBatchDefaultXPlanes = 16;
+constexpr int32_t kBatchPlaneDefaultXPlanes = 32;  // the batched plane kernel's x planes per block
 constexpr int64_t kServerBlocks = 1024;
 constexpr int64_t kServerAlonePoints = (int64_t)4 << 20;  // grids this large step on their own kernel
 constexpr int64_t kServerFillPoints = kServerAlonePoints;  // small-first: nodes that fill the device
@@ -1756,12 +1759,38 @@ double host_seconds() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-int32_t batch_x_planes(const hj_batch *b) { return b->x_planes > 0 ? b->x_planes : kBatchDefaultXPlanes; }
+int32_t batch_x_planes(const hj_batch *b, bool plane = false) {
+  return b->x_planes > 0 ? b->x_planes : (plane ? kBatchPlaneDefaultXPlanes : kBatchDefaultXPlanes);
+}
 
 // x chunks of a grid in a batch: ceil(N_x / x planes per tile)
 int batch_chunks(const hj_batch *b, const hj_grid *G) {
   int xp = batch_x_planes(b);
   return (G->g.n[0] + xp - 1) / xp;
+}
+
+// The batched plane kernel's description of instance G, x_planes x planes
+// per block: the handle's plane run length and v split (runs of 3 with more
+// runs than that kernel's blocks hold take the handle's other run length),
+// or false where its planes fit no batched plane block.
+template <typename T>
+bool batch_plane_args(hj_grid *G, int32_t x_planes, hj::StreamArgs<T> *out, int *threads, size_t *lds) {
+  if (!G->plane_ok) return false;
+  const int runs[2] = {G->plane_run, G->plane_run_alt};
+  for (int r : runs) {
+    if (r == 0) continue;
+    hj::StreamArgs<T> a = stream_args<T>(G, true, r);
+    a.skip = nullptr;
+    a.span = 0;
+    const int nx = G->g.n[0];
+    a.chunk_len = x_planes < nx ? x_planes : nx;
+    a.n_chunks = (nx + a.chunk_len - 1) / a.chunk_len;
+    if (hj::plane_multi_fits<T>(a, threads, lds)) {
+      *out = a;
+      return true;
+    }
+  }
+  return false;
 }
 
 template <typename T>
@@ -1783,11 +1812,35 @@ struct BatchPlan {
   std::vector<int32_t> tiles;  // per sorted position
   std::vector<int32_t> tile_end, start, active;
   int nphase = 0, pps = 1;
+  // launch classes: class c holds sorted positions cls_begin[c] ..
+  // cls_begin[c+1]-1 (tile_end restarts at each class) and runs the batched
+  // plane kernel (cls_plane[c]) or the streaming tiles; work-items and LDS
+  // bytes per plane block over the class's positions up to i
+  bool plane = false;  // some class runs the plane kernel
+  std::vector<int> cls_begin;
+  std::vector<uint8_t> cls_plane;
+  std::vector<int32_t> threads;
+  std::vector<int64_t> lds;
 };
 
-// Step schedules, the sorted order and the host tables of one batch solve.
+// Launch classes of the batched plane kernel, by the waves of an instance's
+// blocks: 1-2, 3-4 and 5-12; the instances it does not take (among them
+// those with runs of one theta node) form the streaming class.  A workgroup is dispatched only where all its waves'
+// registers fit, so a block sized for a larger instance would hold a small
+// instance's CU share idle; each class runs its own launches, on its own
+// lane beside the others.
+constexpr int kStreamClass = 3;
+int plane_class(int threads) {
+  const int w = (threads + 63) / 64;
+  return w <= 2 ? 0 : (w <= 4 ? 1 : 2);
+}
+static_assert(kStreamClass + 1 <= kBatchLanes, "a lane per class");
+
+// Step schedules, the sorted order and the host tables of one batch solve
+// (plane_mode: the launches may run the batched plane kernel, which they do
+// when it takes every instance).
 template <typename T>
-hj_status batch_plan(hj_batch *b, const double *horizons, BatchPlan *P) {
+hj_status batch_plan(hj_batch *b, const double *horizons, BatchPlan *P, bool plane_mode) {
   hj_status st;
   const int m = b->m;
   P->steps.resize(m);
@@ -1801,22 +1854,54 @@ hj_status batch_plan(hj_batch *b, const double *horizons, BatchPlan *P) {
     if (P->steps[j] > ((int64_t)1 << 24)) return fail(HJ_ERR_INVALID_ARG, "instance %d: %lld steps", j, (long long)P->steps[j]);
     points += G->npts;
   }
+  // the batched plane kernel's description of the instances it takes
+  const bool try_plane = plane_mode && b->plane_allowed;
+  std::vector<hj::StreamArgs<T>> pa(try_plane ? m : 0);
+  std::vector<int> thr(m, 0), cls(m, kStreamClass);
+  std::vector<size_t> bytes(m, 0);
+  for (int j = 0; j < m && try_plane; ++j)
+    if (batch_plane_args<T>(b->g[j], batch_x_planes(b, true), &pa[j], &thr[j], &bytes[j]))
+      cls[j] = plane_class(thr[j]);
   P->order.resize(m);
   for (int j = 0; j < m; ++j) P->order[j] = j;
-  std::stable_sort(P->order.begin(), P->order.end(), [&](int x, int y) { return P->steps[x] > P->steps[y]; });
+  std::stable_sort(P->order.begin(), P->order.end(), [&](int x, int y) {
+    return cls[x] != cls[y] ? cls[x] < cls[y] : P->steps[x] > P->steps[y];
+  });
+  P->cls_begin.assign(1, 0);
+  P->cls_plane.assign(1, cls[P->order[0]] != kStreamClass);
+  for (int i = 1; i < m; ++i)
+    if (cls[P->order[i]] != cls[P->order[i - 1]]) {
+      P->cls_begin.push_back(i);
+      P->cls_plane.push_back(cls[P->order[i]] != kStreamClass);
+    }
+  P->cls_begin.push_back(m);
+  P->plane = std::find(P->cls_plane.begin(), P->cls_plane.end(), 1) != P->cls_plane.end();
+  b->info.classes = (int32_t)P->cls_plane.size();
   P->pps = b->rk2 ? 2 : 1;
-  int64_t maxn = P->steps[P->order[0]];
+  int64_t maxn = 0;
+  for (int j = 0; j < m; ++j) maxn = std::max(maxn, P->steps[j]);
   P->nphase = (int)(maxn * P->pps);
   hj::BatchInst<T> *inst = static_cast<hj::BatchInst<T> *>(b->inst_host);
   P->tiles.resize(m);
   P->tile_end.resize(m);
+  P->threads.assign(m, 0);
+  P->lds.assign(m, 0);
+  b->info.plane_kernel = P->plane ? 1 : 0;
   int64_t acc = 0;
   for (int i = 0; i < m; ++i) {
     const int j = P->order[i];
     hj_grid *G = b->g[j];
     hj::BatchInst<T> &in = inst[i];
     memset(&in, 0, sizeof in);
-    in.a = batch_stream_args<T>(G, batch_chunks(b, G));
+    const bool first = std::find(P->cls_begin.begin(), P->cls_begin.end(), i) != P->cls_begin.end();
+    if (first) acc = 0;  // each class's tile prefix starts at 0
+    if (cls[j] != kStreamClass) {
+      in.a = pa[j];
+      P->threads[i] = std::max(thr[j], first ? 0 : P->threads[i - 1]);
+      P->lds[i] = std::max((int64_t)bytes[j], first ? (int64_t)0 : P->lds[i - 1]);
+    } else {
+      in.a = batch_stream_args<T>(G, batch_chunks(b, G));
+    }
     in.v0 = buf<const T>(G->v0);
     in.va = buf<T>(G->v);
     in.vb = buf<T>(G->w2);
@@ -1826,26 +1911,36 @@ hj_status batch_plan(hj_batch *b, const double *horizons, BatchPlan *P) {
     in.steps = (int32_t)P->steps[j];
     in.rk2 = b->rk2 ? 1 : 0;
     in.clamp = G->sch.clamp == HJ_CLAMP_MIN_V0 ? 1 : 0;
-    in.tiles = in.a.blocks_per_chunk * in.a.n_chunks;
+    const int64_t tiles = (int64_t)in.a.blocks_per_chunk * in.a.n_chunks;
+    if (tiles >= ((int64_t)1 << 30)) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
+    in.tiles = (int32_t)tiles;
     P->tiles[i] = in.tiles;
     acc += in.tiles;
     if (acc >= ((int64_t)1 << 30)) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
     P->tile_end[i] = (int32_t)acc;
   }
+  // active[p]: instances of the first class still running in phase p (the
+  // one class of the streaming tiles and the persistent kernel's work list)
   P->active.resize(P->nphase);
   P->start.resize(P->nphase + 1);
-  int64_t items = 0;
-  int act = m;
-  for (int p = 0; p < P->nphase; ++p) {
-    int64_t k = p / P->pps;
-    while (act > 0 && P->steps[P->order[act - 1]] <= k) --act;
-    P->active[p] = act;
-    P->start[p] = (int32_t)items;
-    items += P->tile_end[act - 1];
-    if (items >= ((int64_t)1 << 31) - 1) return fail(HJ_ERR_UNSUPPORTED, "batch work list too long");
+  int64_t items = 0, sweep = 0;
+  for (size_t c = 0; c + 1 < P->cls_begin.size(); ++c) {
+    const int c0 = P->cls_begin[c];
+    int act = P->cls_begin[c + 1] - c0;
+    sweep += P->tile_end[c0 + act - 1];
+    for (int p = 0; p < P->nphase; ++p) {
+      int64_t k = p / P->pps;
+      while (act > 0 && P->steps[P->order[c0 + act - 1]] <= k) --act;
+      if (c == 0) {
+        P->active[p] = act;
+        P->start[p] = (int32_t)items;
+      }
+      if (act > 0) items += P->tile_end[c0 + act - 1];
+      if (items >= ((int64_t)1 << 31) - 1) return fail(HJ_ERR_UNSUPPORTED, "batch work list too long");
+    }
   }
   P->start[P->nphase] = (int32_t)items;
-  b->info.tiles_per_sweep = acc;
+  b->info.tiles_per_sweep = sweep;
   b->info.work_items = items;
   b->info.points = points;
   return HJ_OK;
@@ -1879,18 +1974,60 @@ hj_status batch_upload(hj_batch *b, const BatchPlan &P) {
   return HJ_OK;
 }
 
-// One launch per (step, stage), each over the instances still running.
+hj_status batch_lanes(hj_batch *b) {
+  for (int k = 0; k < kBatchLanes; ++k) {
+    if (!b->lanes[k]) HJ_HIP(hipStreamCreateWithFlags(&b->lanes[k], hipStreamNonBlocking));
+    if (!b->join[k]) HJ_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+  }
+  if (!b->fork) HJ_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  return HJ_OK;
+}
+
+// The launches of class c on stream s: one per (step, stage) over the
+// class's instances still running.
 template <typename T>
-hj_status batch_enqueue_launches(hj_batch *b, const BatchPlan &P, hipStream_t s, int32_t *nodes) {
-  const hj::BatchInst<T> *inst = static_cast<const hj::BatchInst<T> *>(b->inst_dev);
-  *nodes = 0;
+hj_status batch_enqueue_class(hj_batch *b, const BatchPlan &P, int c, hipStream_t s, int32_t *nodes) {
+  const int c0 = P.cls_begin[c], c1 = P.cls_begin[c + 1];
+  const hj::BatchInst<T> *inst = static_cast<const hj::BatchInst<T> *>(b->inst_dev) + c0;
+  const int32_t *tile_end = b->ints_dev + c0;
+  int act = c1 - c0;
   for (int p = 0; p < P.nphase; ++p) {
-    int act = P.active[p];
-    HJ_HIP(hj::launch_multi<T>(inst, b->ints_dev, act, P.tile_end[act - 1], p / P.pps, p % P.pps, b->deriv, b->sg,
-                               b->ball, s));
+    const int64_t k = p / P.pps;
+    while (act > 0 && P.steps[P.order[c0 + act - 1]] <= k) --act;
+    if (act == 0) break;
+    const int last = c0 + act - 1;
+    if (P.cls_plane[c])
+      HJ_HIP(hj::launch_plane_multi<T>(inst, tile_end, act, P.tile_end[last], P.threads[last], (size_t)P.lds[last],
+                                       (int)k, p % P.pps, b->deriv, b->sg, b->ball, s));
+    else
+      HJ_HIP(hj::launch_multi<T>(inst, tile_end, act, P.tile_end[last], (int)k, p % P.pps, b->deriv, b->sg, b->ball,
+                                 s));
     *nodes += 1;
   }
   return HJ_OK;
+}
+
+// One launch per (step, stage) and class, each over the class's instances
+// still running; with several classes, class c runs on lane c, forked from
+// s and joined back into it (also while s is being captured into a graph).
+template <typename T>
+hj_status batch_enqueue_launches(hj_batch *b, const BatchPlan &P, hipStream_t s, int32_t *nodes) {
+  *nodes = 0;
+  const int ncls = (int)P.cls_begin.size() - 1;
+  if (ncls == 1) return batch_enqueue_class<T>(b, P, 0, s, nodes);
+  hj_status st;
+  if ((st = batch_lanes(b)) != HJ_OK) return st;
+  HJ_HIP(hipEventRecord(b->fork, s));
+  for (int c = 0; c < ncls; ++c) HJ_HIP(hipStreamWaitEvent(b->lanes[c], b->fork, 0));
+  st = HJ_OK;
+  for (int c = 0; c < ncls && st == HJ_OK; ++c)
+    st = batch_enqueue_class<T>(b, P, c, b->lanes[c], nodes);
+  // join every forked lane, also after a failed launch
+  for (int c = 0; c < ncls; ++c) {
+    HJ_HIP(hipEventRecord(b->join[c], b->lanes[c]));
+    HJ_HIP(hipStreamWaitEvent(s, b->join[c], 0));
+  }
+  return st;
 }
 
 template <typename T>
@@ -1898,7 +2035,7 @@ hj_status batch_solve_t(hj_batch *b, const double *horizons, int32_t mode, hj_so
   hj_status st;
   HJ_HIP(hipEventSynchronize(b->staged));  // the pinned tables are free again
   BatchPlan P;
-  if ((st = batch_plan<T>(b, horizons, &P)) != HJ_OK) return st;
+  if ((st = batch_plan<T>(b, horizons, &P, mode != HJ_BATCH_PERSISTENT)) != HJ_OK) return st;
   if (P.nphase > 0) {
     if ((st = batch_upload<T>(b, P)) != HJ_OK) return st;
     if (mode == HJ_BATCH_LAUNCHES) {
@@ -1907,9 +2044,14 @@ hj_status batch_solve_t(hj_batch *b, const double *horizons, int32_t mode, hj_so
     } else if (mode == HJ_BATCH_GRAPH) {
       std::vector<int64_t> key;
       key.push_back(P.pps);
+      key.push_back(P.plane ? 1 : 0);
+      for (int c : P.cls_begin) key.push_back(c);
+      for (uint8_t c : P.cls_plane) key.push_back(c);
       for (int i = 0; i < b->m; ++i) {
         key.push_back(P.steps[P.order[i]]);
         key.push_back(P.tiles[i]);
+        key.push_back(P.threads[i]);
+        key.push_back(P.lds[i]);
       }
       if (!b->gexec || key != b->gkey) {
         if (b->gexec) HJ_HIP(hipGraphExecDestroy(b->gexec));
@@ -1992,11 +2134,7 @@ hj_status check_batch(hj_batch *b) {
 // to the least-loaded lane in decreasing order of work (nodes x steps).
 hj_status batch_solve_streams(hj_batch *b, const double *horizons, hj_solve_info *infos) {
   hj_status st;
-  for (int k = 0; k < kBatchLanes; ++k) {
-    if (!b->lanes[k]) HJ_HIP(hipStreamCreateWithFlags(&b->lanes[k], hipStreamNonBlocking));
-    if (!b->join[k]) HJ_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
-  }
-  if (!b->fork) HJ_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  if ((st = batch_lanes(b)) != HJ_OK) return st;
   std::vector<std::pair<double, int>> work((size_t)b->m);
   b->info.points = 0;
   b->info.work_items = 0;  // no tiles: every instance runs its own solve
@@ -2099,6 +2237,8 @@ hj_status hj_batch_create(hj_grid *const *grids, int32_t m, hj_batch **out) {
                 hipGetErrorString(e));
   }
   b->info.m = m;
+  const char *kern = getenv("HJ_BATCH_KERNEL");
+  b->plane_allowed = !(kern && !strcmp(kern, "stream"));
   *out = b;
   return HJ_OK;
 }
@@ -2183,7 +2323,7 @@ hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out) {
   hj_status st = check_batch(b);
   if (st != HJ_OK) return st;
   if (!out) return fail(HJ_ERR_INVALID_ARG, "null output");
-  b->info.x_planes = batch_x_planes(b);
+  b->info.x_planes = batch_x_planes(b, b->info.plane_kernel != 0);
   *out = b->info;
   return HJ_OK;
 }

@@ -187,6 +187,23 @@ template <typename T>
 hipError_t launch_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int k, int stage,
                         int deriv, bool sg, bool ball, hipStream_t s);
 
+// The batched plane kernel: the same launches with each instance's blocks
+// running the plane kernel on its grid (inst[j].a a plane description:
+// whole planes, or v segments, with chunk_len x planes per block), in
+// blocks of `threads` work-items (a multiple of 64, at least the largest
+// instance's runs) with `lds` bytes of LDS (at least the largest instance's).
+template <typename T>
+hipError_t launch_plane_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int threads,
+                              size_t lds, int k, int stage, int deriv, bool sg, bool ball, hipStream_t s);
+
+// Whether the plane description `a` runs in the batched plane kernel (run
+// lengths 2 and, FP32, 3 and 4 -- a plane step of one theta node per
+// work-item costs about as much as one of four, so runs of one are left to
+// the streaming tiles; at most kPlaneMaxThreads runs per block; chunk mode),
+// and the work-items and LDS bytes of its blocks.
+template <typename T>
+bool plane_multi_fits(const StreamArgs<T> &a, int *threads, size_t *lds);
+
 // The whole batch in one launch of `blocks` persistent blocks.
 template <typename T>
 hipError_t launch_persistent(const PersistArgs<T> &p, int blocks, int deriv, bool sg, bool ball, hipStream_t s);

@@ -734,9 +734,10 @@ enum PlaneForm { kFormRuntime = 0, kFormPlain = 1, kFormPlainXY = 2, kFormAverag
 // and the eps fold, from the arguments.
 // R = 3 (FP32): runs of three theta nodes, each kept in a 4-element LDS slot
 // (16-byte aligned), blocks of up to kPlaneMaxThreads3 work-items.
+// One block of the plane kernel: logical block lb of the nblk blocks of the
+// grid's launch (a single-grid launch, or the grid's share of a batched one).
 template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM>
-__global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
-  if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
+__device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb, const int nblk) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   constexpr uint32_t E = sizeof(T);
@@ -744,7 +745,6 @@ __global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void
   const int rpr = a.runs_per_row;
   constexpr int SL = R == 3 ? 4 : R;  // LDS elements per run
   const int rowl = rpr * SL;          // LDS elements per v row
-  const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
   // chunk mode (a.span == 0): the block is (x chunk, v segment, y row).
   // Span mode (whole planes, SEG false): the block takes its equal share of
   // all rows' x planes in row-major order, as one or more (row, x range)
@@ -840,8 +840,8 @@ __global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void
   int64_t idx = 0, idx_end = 1;  // span mode: this block's row-planes
   if (a.span) {
     const int64_t W = (int64_t)ny * nx;
-    idx = (int64_t)lb * W / gridDim.x;
-    idx_end = ((int64_t)lb + 1) * W / gridDim.x;
+    idx = (int64_t)lb * W / nblk;
+    idx_end = ((int64_t)lb + 1) * W / nblk;
   }
   while (idx < idx_end) {
     // this segment: row y, planes [x0, x1)
@@ -1166,6 +1166,13 @@ __global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void
   }
 }
 
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM>
+__global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
+  if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
+  plane_block<T, R, DERIV, SG, BALL, SEG, RANGE, FORM>(a, (int)xcd_logical_block(blockIdx.x, gridDim.x),
+                                                       (int)gridDim.x);
+}
+
 // Target: one block per (x, y) pair computes the distance once and writes
 // it over the whole (v, theta) plane.
 template <typename T>
@@ -1440,6 +1447,39 @@ __global__ __launch_bounds__(kStreamBlock) void stage_multi(const BatchInst<T> *
   StreamArgs<T> a = inst[j].a;
   phase_args(a, inst[j], k >= 0 ? k : inst[j].k + (-1 - k), stage);
   tile_any_run<T, DERIV, SG, BALL>(a, lb - (j > 0 ? tile_end[j - 1] : 0));
+}
+
+// The batched plane kernel: instance j's blocks run the plane kernel on its
+// grid, at its own run length and with its own plane split, in the stage's
+// runtime form.  A launch's blocks have as many work-items as its largest
+// instance needs; the waves an instance leaves empty end at once, before
+// any barrier (a workgroup barrier waits only for the waves that have not
+// ended), so they hold no registers while the block sweeps its planes.
+template <typename T, int DERIV, bool SG, bool BALL>
+__global__ __launch_bounds__(kPlaneMaxThreads) void stage_plane_multi(const BatchInst<T> *__restrict__ inst,
+                                                                      const int32_t *__restrict__ tile_end,
+                                                                      int ninst, int k, int stage) {
+  const int lb = (int)xcd_logical_block(blockIdx.x, gridDim.x);
+  const int j = find_end(tile_end, ninst, lb);
+  StreamArgs<T> a = inst[j].a;
+  phase_args(a, inst[j], k >= 0 ? k : inst[j].k + (-1 - k), stage);
+  const bool seg = a.n_seg > 1;
+  // the block's runs: those of a whole plane, or of a full v segment (the
+  // segment kernel's halo copy needs the work-items of 4 rows)
+  const int runs = __builtin_amdgcn_readfirstlane((seg ? a.v_seg : a.n[2]) * a.runs_per_row);
+  if (__builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) * 64 >= runs) return;  // wave-uniform
+  const int local = lb - (j > 0 ? tile_end[j - 1] : 0);
+  const int nblk = inst[j].tiles;
+  if (seg) {
+    if (a.run == 2) plane_block<T, 2, DERIV, SG, BALL, true, false, kFormRuntime>(a, local, nblk);
+  } else if (a.run == 2) {
+    plane_block<T, 2, DERIV, SG, BALL, false, false, kFormRuntime>(a, local, nblk);
+  } else if constexpr (sizeof(T) == 4) {
+    if (a.run == 3)
+      plane_block<T, 3, DERIV, SG, BALL, false, false, kFormRuntime>(a, local, nblk);
+    else if (a.run == 4)
+      plane_block<T, 4, DERIV, SG, BALL, false, false, kFormRuntime>(a, local, nblk);
+  }
 }
 
 // The persistent batch kernel.  Each block takes work items in order from a
@@ -1836,6 +1876,59 @@ static hipError_t launch_multi_v(const BatchInst<T> *inst, const int32_t *tile_e
 }
 
 template <typename T>
+bool plane_multi_fits(const StreamArgs<T> &a, int *threads, size_t *lds) {
+  const int R = a.run;
+  const bool seg = a.n_seg > 1;
+  const bool run_ok = R == 2 || (sizeof(T) == 4 && (R == 3 || R == 4) && !seg);
+  if (!run_ok || a.runs_per_row < 1 || a.runs_per_row * R != a.n[3] || a.span != 0 || a.n_chunks < 1 ||
+      a.chunk_len < 1 || (int64_t)a.chunk_len * a.n_chunks < a.n[0] ||
+      (int64_t)a.chunk_len * (a.n_chunks - 1) >= a.n[0] || a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1))
+    return false;
+  if (seg && (a.v_seg < kPlaneMinSegRows || (int64_t)a.v_seg * a.n_seg < a.n[2] ||
+              (int64_t)a.v_seg * (a.n_seg - 1) >= a.n[2]))
+    return false;
+  const int64_t runs = (int64_t)(seg ? a.v_seg : a.n[2]) * a.runs_per_row;
+  const int64_t bytes = 2 * (int64_t)(seg ? a.v_seg + 4 : a.n[2]) * a.runs_per_row * (R == 3 ? 4 : R) * sizeof(T);
+  if (runs > kPlaneMaxThreads || bytes > kPlaneMaxLdsBytes) return false;
+  *threads = (int)((runs + 63) / 64 * 64);
+  *lds = (size_t)bytes;
+  return true;
+}
+
+template <typename T, int DERIV, bool SG, bool BALL>
+static hipError_t launch_plane_multi_v(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks,
+                                       int threads, size_t lds, int k, int stage, hipStream_t s) {
+  hipLaunchKernelGGL((stage_plane_multi<T, DERIV, SG, BALL>), dim3(blocks), dim3(threads), lds, s, inst, tile_end,
+                     ninst, k, stage);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_plane_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int threads,
+                              size_t lds, int k, int stage, int deriv, bool sg, bool ball, hipStream_t s) {
+  if (blocks < 1 || ninst < 1 || threads < 64 || threads > kPlaneMaxThreads || threads % 64 != 0 ||
+      lds > (size_t)kPlaneMaxLdsBytes)
+    return hipErrorInvalidValue;
+#define HJ_PMULTI(D, G, B) \
+  return launch_plane_multi_v<T, D, G, B>(inst, tile_end, ninst, blocks, threads, lds, k, stage, s)
+  if (deriv == kUpwind1) {
+    if (ball) {
+      if (sg) HJ_PMULTI(kUpwind1, true, true);
+      HJ_PMULTI(kUpwind1, false, true);
+    }
+    if (sg) HJ_PMULTI(kUpwind1, true, false);
+    HJ_PMULTI(kUpwind1, false, false);
+  }
+  if (ball) {
+    if (sg) HJ_PMULTI(kEno2, true, true);
+    HJ_PMULTI(kEno2, false, true);
+  }
+  if (sg) HJ_PMULTI(kEno2, true, false);
+  HJ_PMULTI(kEno2, false, false);
+#undef HJ_PMULTI
+}
+
+template <typename T>
 hipError_t launch_multi(const BatchInst<T> *inst, const int32_t *tile_end, int ninst, int blocks, int k, int stage,
                         int deriv, bool sg, bool ball, hipStream_t s) {
 #define HJ_MULTI(D, G, B) return launch_multi_v<T, D, G, B>(inst, tile_end, ninst, blocks, k, stage, s)
@@ -1920,6 +2013,12 @@ template hipError_t launch_multi<float>(const BatchInst<float> *, const int32_t 
                                         hipStream_t);
 template hipError_t launch_multi<double>(const BatchInst<double> *, const int32_t *, int, int, int, int, int, bool,
                                          bool, hipStream_t);
+template hipError_t launch_plane_multi<float>(const BatchInst<float> *, const int32_t *, int, int, int, size_t, int,
+                                              int, int, bool, bool, hipStream_t);
+template hipError_t launch_plane_multi<double>(const BatchInst<double> *, const int32_t *, int, int, int, size_t, int,
+                                               int, int, bool, bool, hipStream_t);
+template bool plane_multi_fits<float>(const StreamArgs<float> &, int *, size_t *);
+template bool plane_multi_fits<double>(const StreamArgs<double> &, int *, size_t *);
 template hipError_t launch_persistent<float>(const PersistArgs<float> &, int, int, bool, bool, hipStream_t);
 template hipError_t launch_persistent<double>(const PersistArgs<double> &, int, int, bool, bool, hipStream_t);
 template int persistent_blocks_per_cu<float>(int, bool, bool);

@@ -100,7 +100,8 @@ class hj_converge_info(ctypes.Structure):
 class hj_batch_info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("x_planes", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
                 ("graph_nodes", ctypes.c_int32), ("tiles_per_sweep", ctypes.c_int64),
-                ("work_items", ctypes.c_int64), ("points", ctypes.c_int64)]
+                ("work_items", ctypes.c_int64), ("points", ctypes.c_int64), ("plane_kernel", ctypes.c_int32),
+                ("classes", ctypes.c_int32)]
 
 
 class hj_server_desc(ctypes.Structure):

@@ -142,7 +142,7 @@ def test_batch_null_and_range_arguments(lib):
 
 
 def test_batch_info_layout():
-    assert ctypes.sizeof(hj.hj_batch_info) == 40
+    assert ctypes.sizeof(hj.hj_batch_info) == 48
 
 
 def test_server_null_and_range_arguments(lib):

@@ -83,10 +83,91 @@ def test_batch_equals_single_solves(mode, precision):
         info = b.info()
         assert info["m"] == len(insts) and info["x_planes"] == 5
         assert info["points"] == sum(i.points for i in insts)
+        assert info["plane_kernel"] == (1 if mode in ("launches", "graph") else 0)
         if mode == "graph":
-            assert info["graph_nodes"] == 2 * max(r["steps"] for r in ref_infos)
+            # a node per (step, stage) of each launch class
+            nmax = max(r["steps"] for r in ref_infos)
+            assert 2 * nmax <= info["graph_nodes"] <= 2 * nmax * info["classes"]
         if mode == "persistent":
             assert info["persistent_blocks"] >= 1
+    for g in grids:
+        g.close()
+
+
+def plane_batch(precision: str):
+    """Instances that take every path of the batched launches: plane blocks
+    with theta runs of 4, 3 and 2, planes split into v segments (runs of 2
+    with more runs per plane than a block has work-items), one whose runs of
+    3 would not fit a batched block, streaming tiles for runs of one (prime
+    N_theta), and horizons of 0, 1 and many steps."""
+    shapes = [(14, 12, 6, 16), (11, 13, 9, 21), (9, 10, 7, 18), (10, 9, 20, 43), (12, 8, 40, 60),
+              (13, 11, 5, 19), (9, 9, 4, 3), (8, 8, 80, 30)]
+    horizons = [0.6, 0.35, 0.0, 0.3, 0.2, 0.5, 0.01, 0.2]
+    out = []
+    for i, (n, T) in enumerate(zip(shapes, horizons)):
+        dyn = W.car_dynamics(d_max=0.1 if (precision == "f64" and i % 2) else 0.0)
+        out.append(W.Instance(W.car_grid(*n), dyn, W.scheme("eno2", "rk2"), W.cylinders(60 + i, 1 + i % 4), T))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["launches", "graph"])
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_plane_kernel_equals_single_solves(monkeypatch, mode, precision):
+    """The batched plane kernel (an instance's blocks hold a y row's
+    (v, theta) plane in LDS; launch classes by block size, each on its own
+    lane, beside a class of streaming tiles) on instances covering its run
+    lengths and split planes, at three block lengths (the second and third
+    re-plan), bitwise equal to the single-grid solves; the streaming tiles
+    alone (HJ_BATCH_KERNEL=stream) give the same."""
+    from paper_2012_04011_amd import hj
+
+    insts = plane_batch(precision)
+    ref, ref_infos = single_solutions(hj, insts, precision)
+    for kernel in ("plane", "stream"):
+        if kernel == "stream":
+            monkeypatch.setenv("HJ_BATCH_KERNEL", "stream")
+        else:
+            monkeypatch.delenv("HJ_BATCH_KERNEL", raising=False)
+        grids = make_grids(hj, insts, precision)
+        with hj.Batch(grids) as b:
+            for tile in (0, 7, 100):
+                for g, ins in zip(grids, insts):
+                    g.set_target_cylinders(*ins.cylinders)
+                b.set_tile(tile)
+                infos = b.solve([i.horizon for i in insts], mode)
+                info = b.info()
+                assert info["plane_kernel"] == (1 if kernel == "plane" else 0), (kernel, tile)
+                assert (info["classes"] >= 3) if kernel == "plane" else (info["classes"] == 1)
+                assert info["x_planes"] == (tile if tile else (32 if kernel == "plane" else 16))
+                for j, g in enumerate(grids):
+                    assert infos[j]["steps"] == ref_infos[j]["steps"]
+                    assert np.array_equal(g.value(np.float64), ref[j]), (kernel, tile, j)
+        for g in grids:
+            g.close()
+
+
+def test_batch_plane_kernel_beside_streaming_tiles():
+    """A plane with more theta nodes than a block holds work-items, on a
+    prime N_theta (runs of one), beside a grid with runs of four: the one
+    runs on the streaming tiles, the other on the plane kernel, in two
+    classes, bitwise equal to the single solves; with runs of one alone the
+    batch is one class of streaming tiles."""
+    from paper_2012_04011_amd import hj
+
+    insts = [W.Instance(W.car_grid(8, 7, 4, 769), W.car_dynamics(), W.scheme("eno2", "rk2"), W.cylinders(5, 2), 0.05),
+             W.Instance(W.car_grid(12, 10, 6, 16), W.car_dynamics(), W.scheme("eno2", "rk2"), W.cylinders(6, 2), 0.3)]
+    ref, _ = single_solutions(hj, insts, "f32")
+    grids = make_grids(hj, insts, "f32")
+    with hj.Batch(grids) as b:
+        b.solve([i.horizon for i in insts], "launches")
+        assert b.info()["plane_kernel"] == 1 and b.info()["classes"] == 2
+        for j, g in enumerate(grids):
+            assert np.array_equal(g.value(np.float64), ref[j]), j
+    with hj.Batch(grids[:1]) as b:
+        grids[0].set_target_cylinders(*insts[0].cylinders)
+        b.solve([insts[0].horizon], "graph")
+        assert b.info()["plane_kernel"] == 0 and b.info()["classes"] == 1
+        assert np.array_equal(grids[0].value(np.float64), ref[0])
     for g in grids:
         g.close()
 
@@ -177,12 +258,14 @@ def test_batch_autotune_picks_a_candidate():
         g.close()
 
 
-@pytest.mark.parametrize("mode", ["persistent", "streams"])
+@pytest.mark.parametrize("mode", ["graph", "persistent", "streams"])
 def test_batch_64_uneven_sampled(mode):
     """The 64-instance uneven batch (30x30x12x18 .. 80x80x24x48, 1-8
-    cylinders, horizons 0.5-2 s) in one persistent launch and on concurrent
-    streams: four instances (the largest, the smallest, the longest and the
-    shortest horizon) equal their single-grid solves bit for bit."""
+    cylinders, horizons 0.5-2 s) through the batched plane kernel's graph,
+    in one persistent launch and on concurrent streams: five instances (the
+    largest, the smallest, the longest and the shortest horizon, and one
+    with a prime N_theta, which runs on the streaming tiles) equal their
+    single-grid solves bit for bit."""
     from paper_2012_04011_amd import hj
 
     insts = W.batch_instances(**W.BATCH_64)
@@ -190,8 +273,10 @@ def test_batch_64_uneven_sampled(mode):
     with hj.Batch(grids) as b:
         infos = b.solve([i.horizon for i in insts], mode)
         assert b.info()["points"] == sum(i.points for i in insts)
+        assert b.info()["plane_kernel"] == (1 if mode == "graph" else 0)
     pick = {int(np.argmax([i.points for i in insts])), int(np.argmin([i.points for i in insts])),
-            int(np.argmax([i.horizon for i in insts])), int(np.argmin([i.horizon for i in insts]))}
+            int(np.argmax([i.horizon for i in insts])), int(np.argmin([i.horizon for i in insts])),
+            next(j for j, i in enumerate(insts) if i.grid["n"][2] * i.grid["n"][3] > 768 and i.grid["n"][3] == 43)}
     sub = [insts[j] for j in sorted(pick)]
     ref, ref_infos = single_solutions(hj, sub, "f32")
     for r, ri, j in zip(ref, ref_infos, sorted(pick)):
