@@ -303,8 +303,9 @@ typedef struct {
 hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
 
 /* Time the candidate launch configurations (stage kernel that fits the
- * shape, x-chunk counts 1..8) on the handle's current buffers and keep the
- * fastest; a few milliseconds, synchronises.  The result of a solve does
+ * shape, x-chunk counts 1..8) on the handle's current buffers, time the three
+ * fastest again in three alternating rounds and keep the fastest of those; a
+ * few tens of milliseconds, synchronises.  The result of a solve does
  * not depend on the choice (every candidate evaluates each node with the
  * same arithmetic).  hj_solve_brt calls it on first use unless disabled by
  * hj_set_autotune(g, 0) or fixed by the HJ_X_CHUNKS / HJ_STAGE_KERNEL

@@ -994,7 +994,11 @@ hj_status autotune(hj_grid *G) {
   HJ_HIP(hipEventCreate(&e1));
   int best_k = G->kernel, best_c = G->x_chunks, best_r = G->plane_run, best_s = G->span_blocks;
   const int cus = device_cus(G->device);
-  float best = INFINITY;
+  struct Cand {
+    int k, c, r, s;
+    float ms;
+  };
+  std::vector<Cand> cands;
   // (kernel, plane run) candidates: the plane kernel with its run length and
   // the alternative, then the streaming kernel
   int kernels[3] = {2, 2, 1}, runs[3] = {G->plane_run, G->plane_run_alt, G->plane_run};
@@ -1019,14 +1023,35 @@ hj_status autotune(hj_grid *G) {
       if (getenv("HJ_AUTOTUNE_VERBOSE"))
         fprintf(stderr, "hj_autotune: kernel %d run %d chunks %d span %d: %.1f us per step\n", k, runs[kk],
                 G->x_chunks, G->span_blocks, ms * 1e3);
-      if (ms < best) {
-        best = ms;
-        best_k = k;
-        best_c = G->x_chunks;
-        best_r = runs[kk];
-        best_s = G->span_blocks;
-      }
+      cands.push_back({k, G->x_chunks, runs[kk], G->span_blocks, ms});
     }
+  }
+  // the three fastest again, in three alternating rounds: one short timing
+  // can rank candidates a few per cent apart by the noise of its launches
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+  if (cands.size() > 3) cands.resize(3);
+  std::vector<float> total(cands.size(), 0.0f);
+  for (int round = 0; round < 3 && st == HJ_OK && cands.size() > 1; ++round)
+    for (size_t i = 0; i < cands.size() && st == HJ_OK; ++i) {
+      G->kernel = cands[i].k;
+      G->x_chunks = cands[i].c;
+      G->plane_run = cands[i].r;
+      G->span_blocks = cands[i].s;
+      float ms = 0;
+      st = G->elem == 4 ? time_config<float>(G, 5, e0, e1, &ms) : time_config<double>(G, 5, e0, e1, &ms);
+      total[i] += ms;
+    }
+  if (!cands.empty()) {
+    size_t b = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+      if (total[i] < total[b]) b = i;
+    if (getenv("HJ_AUTOTUNE_VERBOSE") && cands.size() > 1)
+      fprintf(stderr, "hj_autotune: kept kernel %d run %d chunks %d span %d (%.1f us per step over 3 rounds)\n",
+              cands[b].k, cands[b].r, cands[b].c, cands[b].s, total[b] / 3 * 1e3);
+    best_k = cands[b].k;
+    best_c = cands[b].c;
+    best_r = cands[b].r;
+    best_s = cands[b].s;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

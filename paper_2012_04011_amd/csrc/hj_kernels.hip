@@ -871,7 +871,9 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
       const int hw = hv < 0 ? hv + nv : (hv >= nv ? hv - nv : hv);
       hoff = (uint32_t)((y * nv + (hcopy ? hw : 0)) * nth + ht * R) * E;
       hl = (hv - vbase) * rowl + ht * SL;
-      if (hcopy) bload<T, R>(rs, hoff, (uint32_t)x0 * pb, H);
+      // every lane loads (the others a run of row v = 0 of their own y, in
+      // bounds), so that each plane issues a fixed set of loads
+      bload<T, R>(rs, hoff, (uint32_t)x0 * pb, H);
     }
 
     // x ring: slot S[(P + k) & 3] holds V(X + k) at phase P = (X - x0) & 3
@@ -971,8 +973,8 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   #pragma unroll
           for (int j = 0; j < R; ++j) hv[j] = H[j];
           *reinterpret_cast<V *>(buf + hl) = hv;
-          if (X + 1 < x1) bload<T, R>(rs, hoff, sX + pb, H);
         }
+        bload<T, R>(X + 1 < x1 ? rs : rnull, hoff, X + 1 < x1 ? sX + pb : 0u, H);
       }
       T L[R], b2[R];
   #pragma unroll
@@ -1121,7 +1123,10 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
             em = (active && d > em) ? d : em;
           }
         }
-        if (active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
+        // idle lanes shadow the last run and would store the same values to
+        // the same address: in FP32 the store takes no branch (measured
+        // faster), in FP64 it keeps it (measured faster that way)
+        if (sizeof(T) == 4 || active) store_run_nt<T, R>(a.out + (size_t)X * a.plane + offe, res);
       }
     };
 
