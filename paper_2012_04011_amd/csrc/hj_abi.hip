@@ -341,20 +341,27 @@ void build_coef(hj_grid *G, const std::vector<double> &tab, std::vector<double> 
 // measured best among 1..10).  Plane kernel (one block per y row and chunk):
 // about two blocks per CU.  Either way at least 8 planes per chunk (each
 // chunk re-reads up to 4 planes to start its ring).
-int choose_x_chunks(int nx, int ny, int64_t slab_runs, bool plane) {
+// x chunks of a handle without autotuning.  The plane kernel: about 3072
+// waves in all (twelve per CU of 256), from ny blocks per chunk of
+// block_waves waves each, at least 5 planes per chunk; the streaming kernel:
+// about 1000 blocks, at least 8 planes per chunk.
+int choose_x_chunks(int nx, int ny, int64_t slab_runs, bool plane, int block_waves) {
   const char *env = getenv("HJ_X_CHUNKS");
   if (env && atoi(env) > 0) {
     int c = atoi(env);
     return c > nx ? nx : c;
   }
-  int64_t want;
+  int64_t want, cap;
   if (plane) {
-    want = (512 + ny / 2) / ny;
+    const int64_t w = (int64_t)ny * (block_waves > 0 ? block_waves : 1);
+    want = (3072 + w / 2) / w;
+    cap = nx / 5;
   } else {
     int64_t bpc = (slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
     want = (1000 + bpc - 1) / bpc;
+    cap = nx / 8;
   }
-  int64_t cap = nx / 8 > 1 ? nx / 8 : 1;
+  if (cap < 1) cap = 1;
   int64_t c = want < cap ? want : cap;
   return c < 1 ? 1 : (int)c;
 }
@@ -1006,16 +1013,19 @@ hj_status autotune(hj_grid *G) {
   for (int kk = 0; kk < 3 && st == HJ_OK; ++kk) {
     int k = kernels[kk];
     if ((k == 2 && !G->plane_ok) || (k == 1 && !G->stream_ok) || runs[kk] == 0) continue;
-    // chunk modes 1 .. 8, then (plane kernel, whole planes) blocks that
-    // share all row-planes: one or two per CU
+    // chunk modes 1 .. 8, 10, 12, 16 (at least 4 planes each), then (plane
+    // kernel, whole planes) blocks that share all row-planes: one or two per CU
     const bool whole = runs[kk] == 3 || G->n_seg == 1;
     const int nspan = k == 2 && whole && cus > 0 ? 2 : 0;
-    for (int c = 1; c <= 8 + nspan; ++c) {
-      const bool span = c > 8;
+    static const int kChunks[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
+    const int nchunk = (int)(sizeof kChunks / sizeof kChunks[0]);
+    for (int ci = 0; ci < nchunk + nspan; ++ci) {
+      const bool span = ci >= nchunk;
+      const int c = span ? 0 : kChunks[ci];
       if (!span && c > cap) continue;
       G->kernel = k;
       G->x_chunks = span ? G->x_chunks : c;
-      G->span_blocks = span ? (c - 8) * cus : 0;
+      G->span_blocks = span ? (ci - nchunk + 1) * cus : 0;
       G->plane_run = runs[kk];
       float ms = 0;
       st = G->elem == 4 ? time_config<float>(G, 5, e0, e1, &ms) : time_config<double>(G, 5, e0, e1, &ms);
@@ -1165,8 +1175,10 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
       G->launch_fixed = true;
     }
     int64_t slab_runs = (int64_t)grid->n[1] * plane_runs;
-    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * (G->plane_run == 3 ? 1 : G->n_seg), slab_runs,
-                                  G->kernel == 2);
+    const int bseg = G->plane_run == 3 ? 1 : G->n_seg;
+    const int64_t block_runs = (int64_t)(bseg > 1 ? G->v_seg : nv) * (grid->n[3] / G->plane_run);
+    G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * bseg, slab_runs, G->kernel == 2,
+                                  (int)((block_runs + 63) / 64));
   }
   hipError_t e = hipGetDevice(&G->device);
   if (e == hipSuccess) {

@@ -561,6 +561,7 @@ def test_autotune_and_launch_info():
         assert not before["autotuned"] and before["bytes_per_point_step"] == 20.0
         g.solve_brt(0.1)
         after = g.launch_info()
-        assert after["autotuned"] and after["kernel"] in ("plane", "stream") and 1 <= after["x_chunks"] <= 8
+        assert after["autotuned"] and after["kernel"] in ("plane", "stream")
+        assert after["x_chunks"] in (1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16)
         g.set_target(g.target())
         assert g.launch_info()["bytes_per_point_step"] == 24.0
