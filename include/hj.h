@@ -420,7 +420,8 @@ hj_status hj_batch_get_info(hj_batch *b, hj_batch_info *out);
  *   HJ_SERVE_SHARE: every running request, every tick.
  * Among the requests of a tick, grids of fewer than 4 Mi nodes share one
  * launch per stage and step (each at its own step), larger ones fill the
- * device alone and step with their own tuned stage kernel.  Every request
+ * device alone and step with their own stage kernel, and so does a small
+ * one that is alone in its tick.  Every request
  * restarts from its own V0 and gets exactly the V of hj_solve_brt on a fresh
  * handle (bitwise), whatever the policy. */
 enum { HJ_SERVE_SMALL_FIRST = 0, HJ_SERVE_SHARE = 1 };

@@ -2585,11 +2585,17 @@ hj_status server_step(hj_server *S) {
   });
   const int64_t spt = S->d.steps_per_tick > 0 ? S->d.steps_per_tick : 4;
   // large grids fill the device alone and step on their own handle's
-  // kernel; the others share one launch per stage and step
+  // kernel; the others share one launch per stage and step -- unless a
+  // small one is alone in the tick, when its own handle's kernel (the plane
+  // kernel with its own chunking, where it fits) serves it better
   std::vector<int> big, small;
   for (int i = 0; i < m; ++i) {
     const hj_grid *G = S->slots[S->reqs[sel[i]].slot].g;
     (G->npts >= kServerAlonePoints ? big : small).push_back(i);
+  }
+  if (small.size() == 1) {
+    big.push_back(small[0]);
+    small.clear();
   }
   hj::BatchInst<T> *inst = static_cast<hj::BatchInst<T> *>(S->inst_host[r]);
   int32_t *tile_end = S->tile_host[r];
