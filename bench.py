@@ -205,7 +205,8 @@ def summarize_traffic(root: str, last: int = 200) -> int:
 
 
 def bench_batch(args) -> int:
-    """The uneven 64-instance batch: every mode of hj_batch_solve beside the
+    """The uneven 64-instance batch (each grid's launch configuration
+    autotuned alone first): every mode of hj_batch_solve beside the
     same solves run one grid at a time, fixed 16-plane tiles beside the
     autotuned tile length, and the launches on the streaming tiles alone
     beside the default mix of batched plane-kernel classes and streaming
@@ -227,7 +228,7 @@ def bench_batch(args) -> int:
     for ins in insts:
         g = hj.Grid(ins.grid, ins.dyn, ins.scheme, "f32", stream)
         g.set_target_cylinders(*ins.cylinders)
-        g.set_autotune(False)
+        g.autotune()  # each grid's own launch configuration, timed alone before the batch
         grids.append(g)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
