@@ -608,7 +608,7 @@ hj::StreamArgs<T> stream_args(hj_grid *G, bool plane, int plane_run = 0) {
   a.plane = g.n[1] * g.n[2] * g.n[3];
   a.row = g.n[2] * g.n[3];
   a.run = run;
-  a.runs_per_row = g.n[3] / run;
+  a.runs_per_row = (g.n[3] + run - 1) / run;  // the plane kernel's last run may overlap (ragged)
   a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
   a.blocks_per_chunk = plane ? g.n[1] * nseg : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
   a.v_seg = plane && run == 3 ? g.n[2] : G->v_seg;
@@ -1106,13 +1106,25 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     // theta periodic; 32-bit byte offsets (buffer addressing) need each
     // array below 4 GiB
     bool stream_ok = bit(grid->periodic_mask, 3) && G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
-    const int rpr = grid->n[3] / run, nv = grid->n[2];
+    const int nv = grid->n[2], nth = grid->n[3];
+    const char *vseg_env = getenv("HJ_PLANE_VSEG");
+    // An odd N_theta gives runs of one theta node; the plane kernel takes
+    // runs of 4 (FP32; 2 in FP64) instead, the last run of a row shifted
+    // back to end at the row's end (it repeats nodes of the run before it),
+    // where the whole plane fits one block
+    {
+      const int rr = G->elem == 4 ? 4 : 2;
+      const int64_t rruns = (int64_t)nv * ((nth + rr - 1) / rr);
+      if (run == 1 && nth >= 2 * rr && !vseg_env && rruns <= hj::kPlaneMaxThreads &&
+          2 * rruns * rr * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes)
+        run = rr;
+    }
+    const int rpr = (nth + run - 1) / run;
     int64_t plane_runs = (int64_t)nv * rpr;
     // The plane kernel holds the whole (v, theta) plane in one block when it
     // has at most kPlaneMaxThreads runs, else the fewest v segments that fit
     // (HJ_PLANE_VSEG caps the rows per block, to exercise the split).
     int max_rows = hj::kPlaneMaxThreads / rpr;
-    const char *vseg_env = getenv("HJ_PLANE_VSEG");
     if (vseg_env && atoi(vseg_env) > 0 && atoi(vseg_env) < max_rows) max_rows = atoi(vseg_env);
     int n_seg = 1, v_seg = nv;
     if (max_rows > 0 && nv > max_rows) {
@@ -1122,7 +1134,7 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     }
     const int64_t lds_rows = n_seg > 1 ? v_seg + 4 : nv;
     bool plane_ok = stream_ok && max_rows > 0 && (n_seg == 1 || v_seg >= hj::kPlaneMinSegRows) &&
-                    2 * lds_rows * grid->n[3] * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
+                    2 * lds_rows * rpr * run * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
     G->v_seg = v_seg;
     G->n_seg = plane_ok ? n_seg : 1;
     G->plane_run = run;
@@ -1176,7 +1188,8 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     }
     int64_t slab_runs = (int64_t)grid->n[1] * plane_runs;
     const int bseg = G->plane_run == 3 ? 1 : G->n_seg;
-    const int64_t block_runs = (int64_t)(bseg > 1 ? G->v_seg : nv) * (grid->n[3] / G->plane_run);
+    const int64_t block_runs =
+        (int64_t)(bseg > 1 ? G->v_seg : nv) * ((grid->n[3] + G->plane_run - 1) / G->plane_run);
     G->x_chunks = choose_x_chunks(grid->n[0], grid->n[1] * bseg, slab_runs, G->kernel == 2,
                                   (int)((block_runs + 63) / 64));
   }

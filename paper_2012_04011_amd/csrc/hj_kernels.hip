@@ -196,16 +196,13 @@ template <typename T>
 struct Vec2T {
   typedef T type __attribute__((ext_vector_type(2)));
 };
-// A run in global memory.  Runs of 3 sit at 12-byte strides, so their
-// vector type carries the element's alignment only (a 3-vector is otherwise
-// taken as 16-byte aligned).
+// A run in global memory.  Runs of 3 sit at 12-byte strides and the last
+// run of a ragged row starts at any element, so the vector type carries the
+// element's alignment only (gfx950 takes 16-byte loads and stores at 4-byte
+// alignment; the instructions are the same).
 template <typename T, int R>
 struct GVecT {
-  typedef T type __attribute__((ext_vector_type(R)));
-};
-template <>
-struct GVecT<float, 3> {
-  typedef float type __attribute__((ext_vector_type(3), aligned(4)));
+  typedef T type __attribute__((ext_vector_type(R), aligned(sizeof(T))));
 };
 
 template <typename T, int R>
@@ -761,7 +758,11 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   const bool perx = a.periodic_mask & 1u, pery = (a.periodic_mask >> 1) & 1u, perv = (a.periodic_mask >> 2) & 1u;
   const int t = r % rpr;
   const int v = va + r / rpr;
-  const int th0 = t * R;
+  // ragged rows (runs of 2 or 4 that do not divide N_theta, whole planes):
+  // the last run of a row starts at N_theta - R, repeating the last nodes of
+  // the run before it (both compute them alike and store the same values)
+  const bool ragged = (R == 2 || R == 4) && rpr * R != nth;
+  const int th0 = (ragged && t == rpr - 1) ? nth - R : t * R;
   const int pl = v * nth + th0;             // offset inside the (v, theta) plane
   const int pll = (v - vbase) * rowl + t * SL;  // the run's slot in the LDS copy
   int lv[4];
@@ -782,6 +783,17 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
     lh[1] = lh[0] + 1;
     lh[2] = (uint32_t)(base + (t == rpr - 1 ? 0 : t + 1) * SL);
     lh[3] = lh[2] + 1;
+  } else if (ragged) {
+    // the LDS row holds theta 0 .. (rpr - 1) R - 1 in place and the last
+    // run's R nodes after them
+    const int base = (v - vbase) * rowl, lim = (rpr - 1) * R, shift = rpr * R - nth;
+    const int o[4] = {-2, -1, R, R + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int q = th0 + o[k];
+      q = q < 0 ? q + nth : (q >= nth ? q - nth : q);
+      lh[k] = (uint32_t)(base + (q < lim ? q : q + shift));
+    }
   } else {
     theta_halo_offsets<R>((v - vbase) * nth, th0, nth, lh);
   }
@@ -1011,8 +1023,15 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
           u[1] = buf[lh[1]];
           lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
         } else if constexpr (R >= 2) {
-          lds_pair<T>(buf + lh[0], u[0], u[1]);
-          lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
+          if (ragged) {  // the halo pairs may straddle the last run's slot
+            u[0] = buf[lh[0]];
+            u[1] = buf[lh[1]];
+            u[R + 2] = buf[lh[2]];
+            u[R + 3] = buf[lh[3]];
+          } else {
+            lds_pair<T>(buf + lh[0], u[0], u[1]);
+            lds_pair<T>(buf + lh[2], u[R + 2], u[R + 3]);
+          }
         } else {
           u[0] = buf[lh[0]];
           u[1] = buf[lh[1]];
@@ -1344,8 +1363,11 @@ hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
   const int rows = seg ? a.v_seg : a.n[2];
   const int runs = rows * a.runs_per_row;
   constexpr int SL = R == 3 ? 4 : R;  // LDS elements per run
+  // ragged rows (runs of 2 or 4, whole planes): ceil(N_theta / R) runs, N_theta >= 2 R
+  const bool ragged_ok = (R == 2 || R == 4) && !seg && a.n[3] >= 2 * R && a.runs_per_row == (a.n[3] + R - 1) / R;
   if (runs > (R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) || a.run != R || a.span < 0 || (a.span && seg) ||
-      a.runs_per_row * R != a.n[3] || (R == 3 && seg) || a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1) ||
+      (a.runs_per_row * R != a.n[3] && !ragged_ok) || (R == 3 && seg) ||
+      a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1) ||
       (seg && (a.v_seg < kPlaneMinSegRows || (int64_t)a.v_seg * a.n_seg < a.n[2] ||
                (int64_t)a.v_seg * (a.n_seg - 1) >= a.n[2])))
     return hipErrorInvalidValue;
@@ -1885,7 +1907,9 @@ bool plane_multi_fits(const StreamArgs<T> &a, int *threads, size_t *lds) {
   const int R = a.run;
   const bool seg = a.n_seg > 1;
   const bool run_ok = R == 2 || (sizeof(T) == 4 && (R == 3 || R == 4) && !seg);
-  if (!run_ok || a.runs_per_row < 1 || a.runs_per_row * R != a.n[3] || a.span != 0 || a.n_chunks < 1 ||
+  const bool ragged_ok = (R == 2 || R == 4) && !seg && a.n[3] >= 2 * R && a.runs_per_row == (a.n[3] + R - 1) / R;
+  if (!run_ok || a.runs_per_row < 1 || (a.runs_per_row * R != a.n[3] && !ragged_ok) || a.span != 0 ||
+      a.n_chunks < 1 ||
       a.chunk_len < 1 || (int64_t)a.chunk_len * a.n_chunks < a.n[0] ||
       (int64_t)a.chunk_len * (a.n_chunks - 1) >= a.n[0] || a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1))
     return false;

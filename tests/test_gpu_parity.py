@@ -511,15 +511,21 @@ def test_kernels_and_target_forms_bitwise_equal(monkeypatch, precision):
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-@pytest.mark.parametrize("nth", [18, 19, 21])
+@pytest.mark.parametrize("nth", [5, 7, 11, 13, 18, 19, 21, 43])
 def test_short_runs_kernels_bitwise_and_solve(monkeypatch, precision, nth):
-    """Grids whose N_theta is not a multiple of 4 run the plane and streaming
-    kernels with runs of 2 or 1 theta nodes: bitwise equal across kernels and
-    x-chunkings, and a short ENO2 + TVD-RK2 solve with a disturbance matches
-    the oracle."""
+    """Grids whose N_theta is not a multiple of 4 run the streaming kernel
+    with runs of 2 or 1 theta nodes and the plane kernel with runs of 2, 3
+    or, for an odd N_theta of at least 2 R, ragged runs of 4 (FP32) or 2
+    (FP64) whose last run of a row is shifted back to end at the row's end:
+    bitwise equal across kernels and x-chunkings, and a short ENO2 +
+    TVD-RK2 solve with a disturbance matches the oracle."""
     from paper_2012_04011_amd import hj
 
     grid = W.car_grid(22, 20, 8, nth)
+    rr = 4 if precision == "f32" else 2
+    if nth % 2 and nth >= 2 * rr and not (precision == "f32" and nth % 3 == 0):
+        with hj.Grid(grid, W.car_dynamics(), W.scheme("eno2", "rk2"), precision) as g:
+            assert g.launch_info()["theta_run"] == rr  # ragged rows
     dyn = W.car_dynamics(d_max=0.1)
     sch = W.scheme("eno2", "rk2")
     cyl = W.cylinders(11, 4)
