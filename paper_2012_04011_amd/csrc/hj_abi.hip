@@ -1108,15 +1108,22 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
     bool stream_ok = bit(grid->periodic_mask, 3) && G->npts * (int64_t)G->elem < ((int64_t)1 << 32);
     const int nv = grid->n[2], nth = grid->n[3];
     const char *vseg_env = getenv("HJ_PLANE_VSEG");
-    // An odd N_theta gives runs of one theta node; the plane kernel takes
-    // runs of 4 (FP32; 2 in FP64) instead, the last run of a row shifted
-    // back to end at the row's end (it repeats nodes of the run before it),
-    // where the whole plane fits one block
+    // SIMD time per plane of a run length (see the runs-of-3 choice below)
+    auto cost = [&](int r, int64_t runs_r) {
+      const int64_t waves = (runs_r + 63) / 64;
+      return (double)(waves >= 8 ? 4 * ((waves + 3) / 4) : waves) * (51.0 * r + 15.0);
+    };
+    // An odd N_theta gives runs of one theta node, an even one not divisible
+    // by 4 runs of two in FP32; the plane kernel takes runs of 4 (FP32; 2 in
+    // FP64) instead -- for runs of two where they cost less -- the last run
+    // of a row shifted back to end at the row's end (it repeats nodes of the
+    // run before it), where the whole plane fits one block
     {
       const int rr = G->elem == 4 ? 4 : 2;
       const int64_t rruns = (int64_t)nv * ((nth + rr - 1) / rr);
-      if (run == 1 && nth >= 2 * rr && !vseg_env && rruns <= hj::kPlaneMaxThreads &&
-          2 * rruns * rr * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes)
+      const bool fits = nth >= 2 * rr && !vseg_env && rruns <= hj::kPlaneMaxThreads &&
+                        2 * rruns * rr * (int64_t)G->elem <= hj::kPlaneMaxLdsBytes;
+      if (fits && (run == 1 || (run == 2 && rr == 4 && cost(4, rruns) < cost(2, (int64_t)nv * (nth / 2)))))
         run = rr;
     }
     const int rpr = (nth + run - 1) / run;
@@ -1150,10 +1157,6 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
                       runs3 <= hj::kPlaneMaxThreads3 && 2 * runs3 * 4 * 4 <= hj::kPlaneMaxLdsBytes;
     const bool plane_ok_default = plane_ok;
     if (fit3) {
-      auto cost = [&](int r, int64_t runs_r) {
-        const int64_t waves = (runs_r + 63) / 64;
-        return (double)(waves >= 8 ? 4 * ((waves + 3) / 4) : waves) * (51.0 * r + 15.0);
-      };
       const bool three_better = !plane_ok || n_seg > 1 || cost(3, runs3) < cost(run, plane_runs);
       if (!plane_ok) {  // runs of 3 make a whole plane fit
         plane_ok = true;
