@@ -761,7 +761,7 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   // ragged rows (runs of 2 or 4 that do not divide N_theta, whole planes):
   // the last run of a row starts at N_theta - R, repeating the last nodes of
   // the run before it (both compute them alike and store the same values)
-  const bool ragged = (R == 2 || R == 4) && rpr * R != nth;
+  const bool ragged = !SEG && (R == 2 || R == 4) && rpr * R != nth;  // whole planes only
   const int th0 = (ragged && t == rpr - 1) ? nth - R : t * R;
   const int pl = v * nth + th0;             // offset inside the (v, theta) plane
   const int pll = (v - vbase) * rowl + t * SL;  // the run's slot in the LDS copy
