@@ -64,17 +64,18 @@ def algorithmic_bytes_per_launch(npts: int, info: dict, integrator: str) -> floa
     return info["bytes_per_point_step"] * npts / launches
 
 
-def measured_traffic(npts_expected: int, x_chunks: int):
+def measured_traffic(npts_expected: int, x_chunks: int, plane_rows: int = 1):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     committed under profiles/, if they were taken on the current kernels in
-    the same launch configuration (x chunks: each adds halo planes)."""
+    the same launch configuration (x chunks: each adds halo planes; y rows
+    per plane-kernel block: two-row blocks split the plane along v)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if (t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("points") != npts_expected or
-            t.get("x_chunks") != x_chunks):
+            t.get("x_chunks") != x_chunks or t.get("plane_rows", 1) != plane_rows):
         return None
     return t.get("bytes_per_launch")
 
@@ -158,12 +159,15 @@ def summarize_traffic(root: str, last: int = 200) -> int:
             with open(os.path.join(root, f"stage_{key}.log")) as fh:
                 for line in fh:
                     if line.startswith("{"):
-                        chunks.add(json.loads(line)["config"]["x_chunks"])
+                        cfg = json.loads(line)["config"]
+                        chunks.add((cfg["x_chunks"], cfg.get("plane_rows", 1)))
         except (OSError, ValueError, KeyError):
             pass
     if len(chunks) != 1:
-        print(f"summarize-traffic: the stage runs' x chunks are not one known value: {sorted(chunks)}", file=sys.stderr)
+        print(f"summarize-traffic: the stage runs' launch configurations are not one known value: {sorted(chunks)}",
+              file=sys.stderr)
         return 1
+    x_chunks, plane_rows = chunks.pop()
     res = {}
     for counter, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         stage = [r for r in _counter_rows(os.path.join(root, "stage_" + key), counter) if "stage_" in r[1]]
@@ -184,7 +188,8 @@ def summarize_traffic(root: str, last: int = 200) -> int:
     out = {
         "kernel_source_sha256_16": kernel_source_hash(),
         "points": W.LARGE_120.points,
-        "x_chunks": chunks.pop(),
+        "x_chunks": x_chunks,
+        "plane_rows": plane_rows,
         "bytes_per_launch": (s1 + s2) / 2.0,
         "stage1_bytes": s1,
         "stage2_bytes": s2,
@@ -838,7 +843,7 @@ def main() -> int:
     bpl = algorithmic_bytes_per_launch(npts, launch, wl.scheme["integrator"])
     avg_launch_s = prof["loop_ms"] / 1e3 / prof["step_launches"]
     achieved = bpl / avg_launch_s / 1e9
-    traffic = measured_traffic(npts, launch["x_chunks"]) if prec == "f32" else None
+    traffic = measured_traffic(npts, launch["x_chunks"], launch["plane_rows"]) if prec == "f32" else None
     copy_gbs = copy_bandwidth_gbs(stream)
     out = {
         "metric": METRIC,
@@ -867,6 +872,7 @@ def main() -> int:
             "obstacles": wl.obstacles,
             "stage_kernel": launch["kernel"],
             "x_chunks": launch["x_chunks"],
+            "plane_rows": launch["plane_rows"],
             "target": "xy table (cylinders)" if launch["target_xy"] else "4D V0",
         },
         "roofline": {

@@ -290,6 +290,10 @@ hj_status hj_optimal_control_noalloc(hj_grid *g, const double *states, int64_t m
  * the plane kernel cuts each y row's x sweep into x_chunks pieces; else the
  * number of blocks that share all rows' x planes equally in row-major order
  * (so that every compute unit gets the same work; chosen by hj_autotune).
+ * plane_rows: y rows per plane-kernel block, 1, or 2 where two neighbouring
+ * rows share a block (each row's threads then load only their outer y
+ * neighbours and read the inner ones from LDS; chosen by hj_autotune or
+ * HJ_PLANE_ROWS=2); 0 with the other kernels.  reserved: 0.
  * bytes_per_point_step: algorithmic
  * HBM bytes one full step moves per grid node in this mode (each array read
  * once and written once per stage). */
@@ -297,6 +301,7 @@ typedef struct {
   int32_t kernel, x_chunks, target_xy, autotuned;
   int32_t plane_segments, solve_graph;
   int32_t theta_run, span_blocks;
+  int32_t plane_rows, reserved;
   double bytes_per_point_step;
 } hj_launch_info;
 
@@ -315,7 +320,9 @@ hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
  * HJ_STAGE_KERNEL=stream|generic forces a stage kernel; HJ_X_CHUNKS=n fixes
  * the x chunks; HJ_PLANE_RUN=3 or =the default run fixes the plane kernel's
  * theta run (where it fits); HJ_PLANE_SPAN=b shares all row-planes among b
- * plane-kernel blocks; HJ_PLANE_VSEG=r splits the plane kernel's (v, theta) plane
+ * plane-kernel blocks; HJ_PLANE_ROWS=1|2 keeps one-row or two-row plane
+ * blocks (two-row blocks where a layout fits; the autotuner then times only
+ * those); HJ_PLANE_VSEG=r splits the plane kernel's (v, theta) plane
  * into segments of at most r v rows (r >= 4) even when it fits one block;
  * HJ_AUTOTUNE_VERBOSE prints each candidate's time to stderr. */
 hj_status hj_autotune(hj_grid *g);

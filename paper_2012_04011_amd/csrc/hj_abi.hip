@@ -114,6 +114,9 @@ struct hj_grid {
   // plane kernel: 0 = chunk mode (x_chunks), else the number of blocks that
   // share all row-planes (span mode, whole planes only)
   int span_blocks = 0;
+  // plane kernel, chunk mode: y rows per block (2: two-row blocks, where
+  // rows2_layout finds a layout for the run length)
+  int plane_rows = 1;
   bool plane_ok = false, stream_ok = false;
   bool launch_fixed = false;   // kernel / chunks forced by the environment
   bool autotune_on = true, autotuned = false;
@@ -169,7 +172,7 @@ struct hj_grid {
     int64_t n;
     double dt, dt_last;
     void *v_in, *w2_in, *v_out, *w2_out;
-    int kernel, x_chunks, plane_run, span_blocks;
+    int kernel, x_chunks, plane_run, span_blocks, plane_rows;
     bool target_xy;
     const int32_t *skip;
     hipGraphExec_t exec;
@@ -592,17 +595,48 @@ hj::StageArgs<T> stage_args(hj_grid *G) {
   return a;
 }
 
+// Two-row plane blocks (StreamArgs::rows = 2) for theta run `run`: each row's
+// runs fill at most half a block in whole waves, so a row takes the whole
+// (v, theta) plane or v segments of at least kPlaneMinSegRows rows (not with
+// runs of 3 or ragged rows), and the LDS holds four plane buffers and four
+// of the published neighbours.  False where no such layout exists.
+bool rows2_layout(const hj_grid *G, int run, int *v_seg, int *n_seg) {
+  const int ny = G->g.n[1], nv = G->g.n[2], nth = G->g.n[3];
+  if (!G->plane_ok || run < 1 || ny < 2 || ny % 2 != 0 || G->ball_mask != 0) return false;
+  const int rpr = (nth + run - 1) / run, sl = run == 3 ? 4 : run;
+  const int per_row = (run == 3 ? hj::kPlaneMaxThreads3 : hj::kPlaneMaxThreads) / 2;  // a multiple of 64
+  const int max_rows = per_row / rpr;
+  if (max_rows < 1) return false;
+  int ns = 1, vs = nv;
+  if (nv > max_rows) {
+    if (run == 3 || rpr * run != nth) return false;
+    ns = (nv + max_rows - 1) / max_rows;
+    vs = (nv + ns - 1) / ns;
+    ns = (nv + vs - 1) / vs;
+    if (vs < hj::kPlaneMinSegRows) return false;
+  }
+  const int64_t lrows = ns > 1 ? vs + 4 : nv;
+  const int64_t lds = (4 * lrows + 4 * (int64_t)vs) * rpr * sl * G->elem;
+  if (lds > hj::kPlaneMaxLdsBytes) return false;
+  *v_seg = vs;
+  *n_seg = ns;
+  return true;
+}
+
 // The streaming description of the handle's grid for its own stage kernel
 // (plane = the LDS plane kernel runs it, with the handle's plane run length
-// or with plane_run, one of the handle's two) or for the streaming tiles of
-// the batched launches (plane = false).
+// or with plane_run, one of the handle's two; rows = 2: two-row blocks where
+// they fit) or for the streaming tiles of the batched launches (plane =
+// false).
 template <typename T>
-hj::StreamArgs<T> stream_args(hj_grid *G, bool plane, int plane_run = 0) {
+hj::StreamArgs<T> stream_args(hj_grid *G, bool plane, int plane_run = 0, int rows = 1) {
   hj::StreamArgs<T> a;
   memset(&a, 0, sizeof a);
   const hj_grid_desc &g = G->g;
   const int run = plane ? (plane_run ? plane_run : G->plane_run) : hj::run_length((int)sizeof(T), g.n[3]);
-  const int nseg = plane && run == 3 ? 1 : G->n_seg;  // runs of 3: whole planes
+  int nseg = plane && run == 3 ? 1 : G->n_seg;  // runs of 3: whole planes
+  int vseg = plane && run == 3 ? g.n[2] : G->v_seg;
+  const bool two = plane && rows == 2 && rows2_layout(G, run, &vseg, &nseg);
   for (int d = 0; d < 4; ++d) a.n[d] = g.n[d];
   a.periodic_mask = g.periodic_mask;
   a.plane = g.n[1] * g.n[2] * g.n[3];
@@ -610,10 +644,11 @@ hj::StreamArgs<T> stream_args(hj_grid *G, bool plane, int plane_run = 0) {
   a.run = run;
   a.runs_per_row = (g.n[3] + run - 1) / run;  // the plane kernel's last run may overlap (ragged)
   a.slab_runs = g.n[1] * g.n[2] * a.runs_per_row;
-  a.blocks_per_chunk = plane ? g.n[1] * nseg : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
-  a.v_seg = plane && run == 3 ? g.n[2] : G->v_seg;
+  a.blocks_per_chunk = plane ? g.n[1] / (two ? 2 : 1) * nseg : (a.slab_runs + hj::kStreamBlock - 1) / hj::kStreamBlock;
+  a.v_seg = vseg;
   a.n_seg = nseg;
-  a.span = plane && nseg == 1 ? G->span_blocks : 0;
+  a.span = plane && nseg == 1 && !two ? G->span_blocks : 0;
+  a.rows = two ? 2 : 1;
   a.n_chunks = G->x_chunks;
   a.chunk_len = (g.n[0] + a.n_chunks - 1) / a.n_chunks;
   a.n_chunks = (g.n[0] + a.chunk_len - 1) / a.chunk_len;
@@ -635,7 +670,7 @@ hj::StreamArgs<T> stream_args(hj_grid *G, bool plane, int plane_run = 0) {
 
 template <typename T>
 hj::StreamArgs<T> stream_args(hj_grid *G) {
-  return stream_args<T>(G, G->kernel == 2);
+  return stream_args<T>(G, G->kernel == 2, 0, G->plane_rows);
 }
 
 template <typename T>
@@ -723,7 +758,7 @@ hj_status solve_graph(hj_grid *G, int64_t n, double dt, double dt_last, int64_t 
     hj_grid::SolveGraph e = G->graphs[i];
     if (e.n == n && e.dt == dt && e.dt_last == dt_last && e.v_in == G->v && e.w2_in == G->w2 &&
         e.kernel == G->kernel && e.x_chunks == G->x_chunks && e.plane_run == G->plane_run &&
-        e.span_blocks == G->span_blocks &&
+        e.span_blocks == G->span_blocks && e.plane_rows == G->plane_rows &&
         e.target_xy == G->target_xy && e.skip == G->skip) {
       HJ_HIP(hipGraphLaunch(e.exec, S(G)));
       G->v = e.v_out;
@@ -745,6 +780,7 @@ hj_status solve_graph(hj_grid *G, int64_t n, double dt, double dt_last, int64_t 
   e.x_chunks = G->x_chunks;
   e.plane_run = G->plane_run;
   e.span_blocks = G->span_blocks;
+  e.plane_rows = G->plane_rows;
   e.target_xy = G->target_xy;
   e.skip = G->skip;
   e.exec = nullptr;
@@ -848,13 +884,13 @@ hj_status range_alpha_update(hj_grid *G, double *dt_allowed) {
   // one-thread-per-column pass
   const int32_t onesided = G->sch.alpha_mode == HJ_ALPHA_DERIV_RANGE_ONESIDED ? 1 : 0;
   if (G->kernel == 2 && G->elem == 4) {
-    hj::StreamArgs<float> a = stream_args<float>(G);
+    hj::StreamArgs<float> a = stream_args<float>(G, true, 0, 1);  // the range pass takes one-row blocks
     a.vs = buf<const float>(G->v);
     a.range = G->range_keys;
     a.range_onesided = onesided;
     HJ_HIP(hj::launch_plane_range(a, G->sch.deriv, S(G)));
   } else if (G->kernel == 2) {
-    hj::StreamArgs<double> a = stream_args<double>(G);
+    hj::StreamArgs<double> a = stream_args<double>(G, true, 0, 1);
     a.vs = buf<const double>(G->v);
     a.range = G->range_keys;
     a.range_onesided = onesided;
@@ -1000,23 +1036,32 @@ hj_status autotune(hj_grid *G) {
   HJ_HIP(hipEventCreate(&e0));
   HJ_HIP(hipEventCreate(&e1));
   int best_k = G->kernel, best_c = G->x_chunks, best_r = G->plane_run, best_s = G->span_blocks;
+  int best_w = G->plane_rows;
   const int cus = device_cus(G->device);
   struct Cand {
-    int k, c, r, s;
+    int k, c, r, s, w;
     float ms;
   };
   std::vector<Cand> cands;
-  // (kernel, plane run) candidates: the plane kernel with its run length and
-  // the alternative, then the streaming kernel
-  int kernels[3] = {2, 2, 1}, runs[3] = {G->plane_run, G->plane_run_alt, G->plane_run};
+  // (kernel, plane run, rows per block) candidates: the plane kernel with its
+  // run length and the alternative, each with one-row and (where they fit)
+  // two-row blocks, then the streaming kernel; HJ_PLANE_ROWS=1|2 keeps one
+  const char *rows_env = getenv("HJ_PLANE_ROWS");
+  const int rows_only = rows_env ? atoi(rows_env) : 0;
+  int kernels[5] = {2, 2, 2, 2, 1}, runs[5] = {G->plane_run, G->plane_run, G->plane_run_alt, G->plane_run_alt, G->plane_run};
+  int rowsv[5] = {1, 2, 1, 2, 1};
   int cap = G->g.n[0] / 4 > 1 ? G->g.n[0] / 4 : 1;
-  for (int kk = 0; kk < 3 && st == HJ_OK; ++kk) {
+  for (int kk = 0; kk < 5 && st == HJ_OK; ++kk) {
     int k = kernels[kk];
     if ((k == 2 && !G->plane_ok) || (k == 1 && !G->stream_ok) || runs[kk] == 0) continue;
+    int vs_unused, ns_unused;
+    if (k == 2 && rowsv[kk] == 2 && !rows2_layout(G, runs[kk], &vs_unused, &ns_unused)) continue;
+    if (k == 2 && rows_only && rowsv[kk] != rows_only) continue;
     // chunk modes 1 .. 8, 10, 12, 16 (at least 4 planes each), then (plane
-    // kernel, whole planes) blocks that share all row-planes: one or two per CU
+    // kernel, whole planes, one-row blocks) blocks that share all row-planes:
+    // one or two per CU
     const bool whole = runs[kk] == 3 || G->n_seg == 1;
-    const int nspan = k == 2 && whole && cus > 0 ? 2 : 0;
+    const int nspan = k == 2 && whole && rowsv[kk] == 1 && cus > 0 ? 2 : 0;
     static const int kChunks[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
     const int nchunk = (int)(sizeof kChunks / sizeof kChunks[0]);
     for (int ci = 0; ci < nchunk + nspan; ++ci) {
@@ -1027,13 +1072,14 @@ hj_status autotune(hj_grid *G) {
       G->x_chunks = span ? G->x_chunks : c;
       G->span_blocks = span ? (ci - nchunk + 1) * cus : 0;
       G->plane_run = runs[kk];
+      G->plane_rows = rowsv[kk];
       float ms = 0;
       st = G->elem == 4 ? time_config<float>(G, 5, e0, e1, &ms) : time_config<double>(G, 5, e0, e1, &ms);
       if (st != HJ_OK) break;
       if (getenv("HJ_AUTOTUNE_VERBOSE"))
-        fprintf(stderr, "hj_autotune: kernel %d run %d chunks %d span %d: %.1f us per step\n", k, runs[kk],
-                G->x_chunks, G->span_blocks, ms * 1e3);
-      cands.push_back({k, G->x_chunks, runs[kk], G->span_blocks, ms});
+        fprintf(stderr, "hj_autotune: kernel %d run %d rows %d chunks %d span %d: %.1f us per step\n", k, runs[kk],
+                rowsv[kk], G->x_chunks, G->span_blocks, ms * 1e3);
+      cands.push_back({k, G->x_chunks, runs[kk], G->span_blocks, rowsv[kk], ms});
     }
   }
   // the three fastest again, in three alternating rounds: one short timing
@@ -1047,6 +1093,7 @@ hj_status autotune(hj_grid *G) {
       G->x_chunks = cands[i].c;
       G->plane_run = cands[i].r;
       G->span_blocks = cands[i].s;
+      G->plane_rows = cands[i].w;
       float ms = 0;
       st = G->elem == 4 ? time_config<float>(G, 5, e0, e1, &ms) : time_config<double>(G, 5, e0, e1, &ms);
       total[i] += ms;
@@ -1056,12 +1103,13 @@ hj_status autotune(hj_grid *G) {
     for (size_t i = 1; i < cands.size(); ++i)
       if (total[i] < total[b]) b = i;
     if (getenv("HJ_AUTOTUNE_VERBOSE") && cands.size() > 1)
-      fprintf(stderr, "hj_autotune: kept kernel %d run %d chunks %d span %d (%.1f us per step over 3 rounds)\n",
-              cands[b].k, cands[b].r, cands[b].c, cands[b].s, total[b] / 3 * 1e3);
+      fprintf(stderr, "hj_autotune: kept kernel %d run %d rows %d chunks %d span %d (%.1f us per step over 3 rounds)\n",
+              cands[b].k, cands[b].r, cands[b].w, cands[b].c, cands[b].s, total[b] / 3 * 1e3);
     best_k = cands[b].k;
     best_c = cands[b].c;
     best_r = cands[b].r;
     best_s = cands[b].s;
+    best_w = cands[b].w;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1069,6 +1117,7 @@ hj_status autotune(hj_grid *G) {
   G->x_chunks = best_c;
   G->plane_run = best_r;
   G->span_blocks = best_s;
+  G->plane_rows = best_w;
   if (st == HJ_OK) G->autotuned = true;
   return st;
 }
@@ -1184,6 +1233,12 @@ hj_status hj_grid_create(const hj_grid_desc *grid, const hj_dynamics_desc *dyn, 
       G->launch_fixed = true;
     }
     if (getenv("HJ_X_CHUNKS")) G->launch_fixed = true;
+    // two-row plane blocks where they fit (HJ_PLANE_ROWS=2; else the
+    // autotuner's choice)
+    const char *rows_env = getenv("HJ_PLANE_ROWS");
+    int vs2 = 0, ns2 = 0;
+    if (rows_env && atoi(rows_env) == 2 && G->kernel == 2 && rows2_layout(G, G->plane_run, &vs2, &ns2))
+      G->plane_rows = 2;
     const char *span_env = getenv("HJ_PLANE_SPAN");  // blocks sharing all row-planes (plane kernel, whole planes)
     if (span_env && atoi(span_env) > 0) {
       G->span_blocks = atoi(span_env);
@@ -1673,9 +1728,13 @@ hj_status hj_get_launch_info(hj_grid *G, hj_launch_info *out) {
   out->x_chunks = G->x_chunks;
   out->target_xy = G->target_xy && G->kernel > 0;
   out->autotuned = G->autotuned;
-  out->plane_segments = G->kernel == 2 ? (G->plane_run == 3 ? 1 : G->n_seg) : 0;
+  int vs2 = 0, ns2 = 0;
+  const bool two = G->kernel == 2 && G->plane_rows == 2 && rows2_layout(G, G->plane_run, &vs2, &ns2);
+  out->plane_segments = G->kernel == 2 ? (two ? ns2 : (G->plane_run == 3 ? 1 : G->n_seg)) : 0;
   out->theta_run = G->kernel == 2 ? G->plane_run : hj::run_length((int)G->elem, G->g.n[3]);
-  out->span_blocks = G->kernel == 2 && (G->plane_run == 3 || G->n_seg == 1) ? G->span_blocks : 0;
+  out->span_blocks = G->kernel == 2 && !two && (G->plane_run == 3 || G->n_seg == 1) ? G->span_blocks : 0;
+  out->plane_rows = G->kernel == 2 ? (two ? 2 : 1) : 0;
+  out->reserved = 0;
   out->solve_graph = G->sch.alpha_mode == HJ_ALPHA_STATE && use_solve_graph(G, 2) ? 1 : 0;
   // arrays per stage: read the stencil input, write the output; stage 2 of
   // TVD-RK2 also reads V^n; the clamp reads V0 unless it is the xy table

@@ -101,6 +101,10 @@ struct StreamArgs {
   // else this many blocks share the ny * nx row-planes of a whole-plane grid
   // equally in row-major order (blocks may span two or more rows)
   int32_t span;
+  // Plane kernel, chunk mode: y rows per block, 1 or 2 (2: the block holds
+  // rows 2u and 2u + 1 of its v segment, n[1] even; blocks_per_chunk is
+  // then n[1] / 2 * n_seg)
+  int32_t rows;
 };
 
 constexpr int kStreamBlock = 256;

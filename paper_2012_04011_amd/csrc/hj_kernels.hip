@@ -733,8 +733,17 @@ enum PlaneForm { kFormRuntime = 0, kFormPlain = 1, kFormPlainXY = 2, kFormAverag
 // (16-byte aligned), blocks of up to kPlaneMaxThreads3 work-items.
 // One block of the plane kernel: logical block lb of the nblk blocks of the
 // grid's launch (a single-grid launch, or the grid's share of a batched one).
-template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM>
+// ROWS2 (chunk mode): the block holds two neighbouring y rows, y0 = 2u and
+// y0 + 1, of one v segment (or of the whole plane); the threads of row q
+// start at q * tpr, a whole number of waves.  Along y each thread loads only
+// its two outer neighbours from memory -- y0 - 2 and y0 - 1 for row 0,
+// y0 + 2 and y0 + 3 for row 1 -- two planes ahead.  The inner ones come from
+// LDS: the other row's centre (its plane buffer) and the neighbour the other
+// row loaded (row 0 publishes y0 - 1, row 1 publishes y0 + 2).  Every node
+// sees the values of the one-row block, so the results are the same.
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM, bool ROWS2 = false>
 __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb, const int nblk) {
+  static_assert(!(ROWS2 && RANGE), "two-row blocks run the stage only");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   constexpr uint32_t E = sizeof(T);
@@ -742,19 +751,25 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   const int rpr = a.runs_per_row;
   constexpr int SL = R == 3 ? 4 : R;  // LDS elements per run
   const int rowl = rpr * SL;          // LDS elements per v row
-  // chunk mode (a.span == 0): the block is (x chunk, v segment, y row).
+  // ROWS2: threads per row (whole waves) and this thread's row, uniform over
+  // the wave
+  const int tpr = ROWS2 ? ((SEG ? a.v_seg : nv) * rpr + 63) / 64 * 64 : 0;
+  const int row2 = ROWS2 ? (int)__builtin_amdgcn_readfirstlane((int)threadIdx.x >= tpr ? 1 : 0) : 0;
+  const int tl = (int)threadIdx.x - row2 * tpr;  // the thread's index inside its row
+  const int nyu = ROWS2 ? ny / 2 : ny;            // y units (rows, or row pairs) per segment
+  // chunk mode (a.span == 0): the block is (x chunk, v segment, y unit).
   // Span mode (whole planes, SEG false): the block takes its equal share of
   // all rows' x planes in row-major order, as one or more (row, x range)
   // segments; gridDim.x blocks share the ny * nx row-planes.
   const int chunk = a.span ? 0 : lb / a.blocks_per_chunk;
   const int rem = a.span ? 0 : lb - chunk * a.blocks_per_chunk;  // segment-major, y fastest
-  const int seg = SEG ? rem / ny : 0;
+  const int seg = SEG ? rem / nyu : 0;
   const int va = seg * a.v_seg;                            // first v of the segment
   const int nvs = SEG ? min(a.v_seg, nv - va) : nv;        // its rows
   const int vbase = SEG ? va - 2 : 0;                      // v of LDS row 0
-  const int runs = nvs * rpr;                              // runs of the block
-  const bool active = (int)threadIdx.x < runs;
-  const int r = active ? (int)threadIdx.x : runs - 1;  // idle lanes shadow the last run
+  const int runs = nvs * rpr;                              // runs of the block (of each row)
+  const bool active = tl < runs;
+  const int r = active ? tl : runs - 1;  // idle lanes shadow the last run
   const bool perx = a.periodic_mask & 1u, pery = (a.periodic_mask >> 1) & 1u, perv = (a.periodic_mask >> 2) & 1u;
   const int t = r % rpr;
   const int v = va + r / rpr;
@@ -828,6 +843,10 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   const __amdgpu_buffer_rsrc_t rv0 = make_rsrc(a.v0, (clamp && !xy) ? total : 0u);
   constexpr int FR = DERIV == kEno2 ? 2 : 1;
   const int psz = (SEG ? a.v_seg + 4 : nv) * rowl;  // values per LDS buffer
+  // ROWS2: after the four plane buffers (row 0, row 1; two phases each), four
+  // buffers of the published y neighbours, and this run's slot in them
+  const int xsz = ROWS2 ? (SEG ? a.v_seg : nv) * rowl : 0;
+  const int xsl = ROWS2 ? (v - va) * rowl + t * SL : 0;
 
   // the accumulators of the range pass and the eps fold span every segment
   // RANGE: the smallest and largest derivative (unscaled, h p) per axis
@@ -857,7 +876,8 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   }
   while (idx < idx_end) {
     // this segment: row y, planes [x0, x1)
-    const int y = a.span ? (int)(idx / nx) : (SEG ? rem - seg * ny : rem);
+    const int yu = SEG ? rem - seg * nyu : rem;
+    const int y = a.span ? (int)(idx / nx) : (ROWS2 ? 2 * yu + row2 : yu);
     const int x0 = a.span ? (int)(idx - (int64_t)y * nx) : chunk * a.chunk_len;
     const int x1 = a.span ? (int)min((int64_t)nx, x0 + (idx_end - idx)) : min(nx, x0 + a.chunk_len);
     idx = a.span ? idx + (x1 - x0) : idx_end;
@@ -869,6 +889,10 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   #pragma unroll
       for (int k = 0; k < 4; ++k) oy[k] = (uint32_t)((wrap_or_clamp(y + o[k], ny, pery) * nv + v) * nth + th0) * E;
     }
+    // ROWS2: the neighbours this thread loads (ENO2: y - 2, y - 1 in row 0,
+    // y + 1, y + 2 in row 1; first order: y - 1, y + 1)
+    const uint32_t og0 = DERIV == kEno2 ? (row2 == 0 ? oy[0] : oy[2]) : (row2 == 0 ? oy[1] : oy[2]);
+    const uint32_t og1 = row2 == 0 ? oy[1] : oy[3];
     const bool yedge = !pery && (y < 2 || y >= ny - 2);
     // SEG halo rows va-2, va-1, va+nvs, va+nvs+1 (those that exist): thread
     // h < 4 rpr copies run h % rpr of row h / rpr, loading it one plane ahead
@@ -877,7 +901,7 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
     int hl = 0;
     T H[R];
     if constexpr (SEG) {
-      const int h = (int)threadIdx.x, hk = h / rpr, ht = h - hk * rpr;
+      const int h = tl, hk = h / rpr, ht = h - hk * rpr;
       const int hv = hk < 2 ? va - 2 + hk : va + nvs + (hk - 2);
       hcopy = h < 4 * rpr && (perv || (hv >= 0 && hv < nv));
       const int hw = hv < 0 ? hv + nv : (hv >= nv ? hv - nv : hv);
@@ -921,16 +945,30 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
     // y neighbours of the current plane (y - 2, y - 1, y + 1, y + 2): loaded
     // at the end of the previous plane, as soon as that plane has used them
     T Y[4][R];
-    if (DERIV == kEno2) bload<T, R>(rs, oy[0], (uint32_t)x0 * pb, Y[0]);
-    bload<T, R>(rs, oy[1], (uint32_t)x0 * pb, Y[1]);
-    bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
-    if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
+    // ROWS2: this thread's y neighbours of planes x0 and x0 + 1, slot
+    // (X - x0) & 1; each plane loads those of X + 2 into its own slot
+    T YG[2][2][R];
+    if constexpr (ROWS2) {
+      const bool on1 = x0 + 1 < x1;
+      bload<T, R>(rs, og0, (uint32_t)x0 * pb, YG[0][0]);
+      if (DERIV == kEno2) bload<T, R>(rs, og1, (uint32_t)x0 * pb, YG[0][1]);
+      bload<T, R>(on1 ? rs : rnull, og0, on1 ? (uint32_t)(x0 + 1) * pb : 0u, YG[1][0]);
+      if (DERIV == kEno2) bload<T, R>(on1 ? rs : rnull, og1, on1 ? (uint32_t)(x0 + 1) * pb : 0u, YG[1][1]);
+    } else {
+      if (DERIV == kEno2) bload<T, R>(rs, oy[0], (uint32_t)x0 * pb, Y[0]);
+      bload<T, R>(rs, oy[1], (uint32_t)x0 * pb, Y[1]);
+      bload<T, R>(rs, oy[2], (uint32_t)x0 * pb, Y[2]);
+      if (DERIV == kEno2) bload<T, R>(rs, oy[3], (uint32_t)x0 * pb, Y[3]);
+    }
     auto plane = [&](auto phase, const int X) {
       constexpr int P = decltype(phase)::value;
       constexpr int I0 = P & 3, I1 = (P + 1) & 3, IF = (P + FR) & 3, IL = (P + FR + 1) & 3;
       constexpr int DC = P & 1, DN = (P + 1) & 1;
       const uint32_t sX = (uint32_t)X * pb;
-      T *buf = lds + ((pcb + P) & 1) * psz;  // LDS planes alternate across segments too
+      // LDS planes alternate across segments too; ROWS2: this row's pair of
+      // buffers, the other row's beside it
+      const int par = (pcb + P) & 1;
+      T *buf = lds + (row2 * 2 + par) * psz;
       // ---- the front of this plane (V(X + FR), loaded by the previous plane)
       // lies beyond the end of an open x axis: its ghost, k layers out, from the
       // two end planes in the ring (the slot of V(X - 1) is still unwritten)
@@ -977,6 +1015,13 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   #pragma unroll
         for (int j = 0; j < SL; ++j) cv[j] = j < R ? c[j] : T(0);
         *reinterpret_cast<V *>(buf + pll) = cv;
+        if constexpr (ROWS2 && DERIV == kEno2) {
+          // the outer neighbour the other row needs: y0 - 1 (row 0), y0 + 2 (row 1)
+          V xv;
+  #pragma unroll
+          for (int j = 0; j < SL; ++j) xv[j] = j < R ? (row2 == 0 ? YG[P & 1][1][j] : YG[P & 1][0][j]) : T(0);
+          *reinterpret_cast<V *>(lds + 4 * psz + (row2 * 2 + par) * xsz + xsl) = xv;
+        }
       }
       if constexpr (SEG) {
         if (hcopy) {
@@ -1088,14 +1133,39 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
             accumulate<T, true, BALL>(L[j], b2[j], a.kp_v, a.km_v, a.sg[2], ppv[j], pmv[j], ball_v, a.half_inv_h[2]);
         }
       }
-      // ---- y: neighbours from global memory
+      // ---- y: neighbours from global memory (ROWS2: the inner ones from LDS)
       T pmy[R], ppy[R];
+      auto ywin = [&](const T(&w0)[R], const T(&w1)[R], const T(&w3)[R], const T(&w4)[R]) {
   #pragma unroll
-      for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(yn2[j], yn1[j], c[j], yp1[j], yp2[j], pmy[j], ppy[j]);
-      if (yedge) {
-        keep_branch();
+        for (int j = 0; j < R; ++j) window_diffs<T, DERIV>(w0[j], w1[j], c[j], w3[j], w4[j], pmy[j], ppy[j]);
+        if (yedge) {
+          keep_branch();
   #pragma unroll
-        for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, yn1[j], c[j], yp1[j], pmy[j], ppy[j]);
+          for (int j = 0; j < R; ++j) edge_diffs<T>(y, ny, w1[j], c[j], w3[j], pmy[j], ppy[j]);
+        }
+      };
+      if constexpr (ROWS2) {
+        // the other row's centre, and (ENO2) the neighbour it published
+        T oc2[R], ox2[R];
+        lds_run<T, R>(lds + ((1 - row2) * 2 + par) * psz + pll, oc2);
+        if (DERIV == kEno2) lds_run<T, R>(lds + 4 * psz + ((1 - row2) * 2 + par) * xsz + xsl, ox2);
+        const T(&g0)[R] = YG[P & 1][0];
+        const T(&g1)[R] = YG[P & 1][1];
+        if (row2 == 0) {  // uniform over the wave
+          keep_branch();
+          if (DERIV == kEno2)
+            ywin(g0, g1, oc2, ox2);  // y - 2, y - 1 | y + 1, y + 2
+          else
+            ywin(g0, g0, oc2, oc2);  // y - 1 | y + 1
+        } else {
+          keep_branch();
+          if (DERIV == kEno2)
+            ywin(ox2, oc2, g0, g1);
+          else
+            ywin(oc2, oc2, g0, g0);
+        }
+      } else {
+        ywin(yn2, yn1, yp1, yp2);
       }
   #pragma unroll
       for (int j = 0; j < R; ++j) {
@@ -1104,7 +1174,14 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
         else
           accumulate<T, SG, BALL>(L[j], b2[j], kpy[j], kmy[j], a.sg[1], ppy[j], pmy[j], ball_y, a.half_inv_h[1]);
       }
-      {
+      if constexpr (ROWS2) {
+        // this thread's y neighbours of plane X + 2 (none beyond the chunk)
+        const bool on2 = X + 2 < x1;
+        const __amdgpu_buffer_rsrc_t ry = on2 ? rs : rnull;
+        const uint32_t s2 = on2 ? sX + 2 * pb : 0u;
+        bload<T, R>(ry, og0, s2, YG[P & 1][0]);
+        if (DERIV == kEno2) bload<T, R>(ry, og1, s2, YG[P & 1][1]);
+      } else {
         // the next plane's y neighbours (none after the chunk's last plane)
         const __amdgpu_buffer_rsrc_t ry = X + 1 < x1 ? rs : rnull;
         if (DERIV == kEno2) bload<T, R>(ry, oy[0], sX + pb, Y[0]);
@@ -1190,11 +1267,11 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   }
 }
 
-template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM>
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, int FORM, bool ROWS2 = false>
 __global__ __launch_bounds__(R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) void stage_plane(StreamArgs<T> a) {
   if (a.skip && *a.skip) return;  // uniform over the block: no barrier is skipped by part of it
-  plane_block<T, R, DERIV, SG, BALL, SEG, RANGE, FORM>(a, (int)xcd_logical_block(blockIdx.x, gridDim.x),
-                                                       (int)gridDim.x);
+  plane_block<T, R, DERIV, SG, BALL, SEG, RANGE, FORM, ROWS2>(a, (int)xcd_logical_block(blockIdx.x, gridDim.x),
+                                                              (int)gridDim.x);
 }
 
 // Target: one block per (x, y) pair computes the distance once and writes
@@ -1323,7 +1400,7 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
   return sg ? launch_stream_v<T, DERIV, true, false>(a, s) : launch_stream_v<T, DERIV, false, false>(a, s);
 }
 
-template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE>
+template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, bool ROWS2 = false>
 void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, size_t lds, hipStream_t s) {
   // the compiled-in forms (not for the ball test dynamics); the eps fold and
   // the 4D clamp target take the runtime form
@@ -1339,18 +1416,18 @@ void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, siz
       form = kFormAverageXY;
   }
   if (form == kFormPlain)
-    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, RANGE, kFormPlain>), dim3(blocks), dim3(threads), lds,
-                       s, a);
+    hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, RANGE, kFormPlain, ROWS2>), dim3(blocks),
+                       dim3(threads), lds, s, a);
   else if constexpr (!RANGE && !BALL) {
     if (form == kFormPlainXY)
-      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormPlainXY>), dim3(blocks), dim3(threads),
-                         lds, s, a);
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormPlainXY, ROWS2>), dim3(blocks),
+                         dim3(threads), lds, s, a);
     else if (form == kFormAverageXY)
-      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormAverageXY>), dim3(blocks),
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormAverageXY, ROWS2>), dim3(blocks),
                          dim3(threads), lds, s, a);
     else
-      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormRuntime>), dim3(blocks), dim3(threads),
-                         lds, s, a);
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormRuntime, ROWS2>), dim3(blocks),
+                         dim3(threads), lds, s, a);
   } else if constexpr (!RANGE) {
     hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormRuntime>), dim3(blocks), dim3(threads),
                        lds, s, a);
@@ -1360,21 +1437,38 @@ void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, siz
 template <typename T, int R, int DERIV, bool SG, bool BALL, bool RANGE = false>
 hipError_t launch_plane_r(const StreamArgs<T> &a, hipStream_t s) {
   const bool seg = a.n_seg > 1;
+  const bool rows2 = a.rows == 2;
   const int rows = seg ? a.v_seg : a.n[2];
   const int runs = rows * a.runs_per_row;
   constexpr int SL = R == 3 ? 4 : R;  // LDS elements per run
   // ragged rows (runs of 2 or 4, whole planes): ceil(N_theta / R) runs, N_theta >= 2 R
   const bool ragged_ok = (R == 2 || R == 4) && !seg && a.n[3] >= 2 * R && a.runs_per_row == (a.n[3] + R - 1) / R;
-  if (runs > (R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) || a.run != R || a.span < 0 || (a.span && seg) ||
+  // two-row blocks: each row's runs in whole waves, an even number of rows,
+  // chunk mode, the stage only
+  const int threads = rows2 ? 2 * ((runs + 63) / 64 * 64) : (runs + 63) / 64 * 64;
+  if (threads > (R == 3 ? kPlaneMaxThreads3 : kPlaneMaxThreads) || a.run != R || a.span < 0 || (a.span && seg) ||
       (a.runs_per_row * R != a.n[3] && !ragged_ok) || (R == 3 && seg) ||
-      a.blocks_per_chunk != a.n[1] * (seg ? a.n_seg : 1) ||
+      (a.rows != 0 && a.rows != 1 && !rows2) ||
+      (rows2 && (RANGE || BALL || a.span || a.n[1] % 2 != 0)) ||
+      a.blocks_per_chunk != a.n[1] / (rows2 ? 2 : 1) * (seg ? a.n_seg : 1) ||
       (seg && (a.v_seg < kPlaneMinSegRows || (int64_t)a.v_seg * a.n_seg < a.n[2] ||
                (int64_t)a.v_seg * (a.n_seg - 1) >= a.n[2])))
     return hipErrorInvalidValue;
-  const int threads = (runs + 63) / 64 * 64;
-  const size_t lds = 2 * (size_t)(seg ? a.v_seg + 4 : a.n[2]) * a.runs_per_row * SL * sizeof(T);
+  // two buffers of the plane (or of the segment and its halo rows) per row;
+  // two-row blocks add two buffers of the published neighbours per row
+  const size_t plane_lds = 2 * (size_t)(seg ? a.v_seg + 4 : a.n[2]) * a.runs_per_row * SL * sizeof(T);
+  const size_t lds = rows2 ? 2 * plane_lds + 4 * (size_t)rows * a.runs_per_row * SL * sizeof(T) : plane_lds;
   if (lds > (size_t)kPlaneMaxLdsBytes) return hipErrorInvalidValue;
   const unsigned blocks = a.span ? (unsigned)a.span : (unsigned)(a.blocks_per_chunk * a.n_chunks);
+  if constexpr (!RANGE && !BALL) {
+    if (rows2) {
+      if (seg && R != 3)
+        launch_plane_form<T, R, DERIV, SG, BALL, R != 3, false, true>(a, blocks, threads, lds, s);
+      else
+        launch_plane_form<T, R, DERIV, SG, BALL, false, false, true>(a, blocks, threads, lds, s);
+      return hipGetLastError();
+    }
+  }
   if constexpr (R == 3) {
     launch_plane_form<T, R, DERIV, SG, BALL, false, RANGE>(a, blocks, threads, lds, s);
   } else {

@@ -86,6 +86,7 @@ class hj_launch_info(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("x_chunks", ctypes.c_int32), ("target_xy", ctypes.c_int32),
                 ("autotuned", ctypes.c_int32), ("plane_segments", ctypes.c_int32), ("solve_graph", ctypes.c_int32),
                 ("theta_run", ctypes.c_int32), ("span_blocks", ctypes.c_int32),
+                ("plane_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("bytes_per_point_step", ctypes.c_double)]
 
 
@@ -367,7 +368,7 @@ def hj_get_launch_info(h: int) -> dict:
     return {"kernel": KERNEL_NAMES.get(li.kernel, li.kernel), "x_chunks": li.x_chunks, "target_xy": bool(li.target_xy),
             "autotuned": bool(li.autotuned), "plane_segments": li.plane_segments,
             "solve_graph": bool(li.solve_graph), "theta_run": li.theta_run, "span_blocks": li.span_blocks,
-            "bytes_per_point_step": li.bytes_per_point_step}
+            "plane_rows": li.plane_rows, "bytes_per_point_step": li.bytes_per_point_step}
 
 
 def hj_autotune(h: int) -> None:

@@ -48,7 +48,7 @@ def test_struct_sizes_match_the_header_layout():
     assert ctypes.sizeof(hj.hj_scheme_desc) == 32
     assert ctypes.sizeof(hj.hj_solve_info) == 32
     assert ctypes.sizeof(hj.hj_dynamics_desc) == 112
-    assert ctypes.sizeof(hj.hj_launch_info) == 40
+    assert ctypes.sizeof(hj.hj_launch_info) == 48
 
 
 def _create(grid=None, dyn=None, sch=None, precision="f32"):

@@ -55,7 +55,7 @@ def _fake_profile(root, chunks=(2, 2), stage_kib=((100.0, 200.0), (50.0, 50.0)),
                            [(d, "__amd_rocclr_copyBuffer", counter, copy_kib[i]) for d in range(5)])
         with open(os.path.join(root, f"stage_{key}.log"), "w") as f:
             f.write("some profiler output\n")
-            f.write(json.dumps({"metric": "m", "config": {"x_chunks": chunks[i]}}) + "\n")
+            f.write(json.dumps({"metric": "m", "config": {"x_chunks": chunks[i], "plane_rows": 2}}) + "\n")
 
 
 def test_summarize_traffic_calibration(tmp_path, monkeypatch):
@@ -71,15 +71,16 @@ def test_summarize_traffic_calibration(tmp_path, monkeypatch):
     s2 = (200.0 * f_factor + 50.0 * w_factor) * 1024
     assert t["stage1_bytes"] == pytest.approx(s1) and t["stage2_bytes"] == pytest.approx(s2)
     assert t["bytes_per_launch"] == pytest.approx((s1 + s2) / 2)
-    assert t["x_chunks"] == 2 and t["points"] == W.LARGE_120.points
+    assert t["x_chunks"] == 2 and t["plane_rows"] == 2 and t["points"] == W.LARGE_120.points
     assert t["kernel_source_sha256_16"] == bench.kernel_source_hash()
-    # the benchmark uses it only for the same kernels, size and chunking
-    assert bench.measured_traffic(W.LARGE_120.points, 2) == pytest.approx((s1 + s2) / 2)
-    assert bench.measured_traffic(W.LARGE_120.points, 4) is None
-    assert bench.measured_traffic(W.LARGE_120.points + 1, 2) is None
+    # the benchmark uses it only for the same kernels, size, chunking and rows per block
+    assert bench.measured_traffic(W.LARGE_120.points, 2, 2) == pytest.approx((s1 + s2) / 2)
+    assert bench.measured_traffic(W.LARGE_120.points, 2, 1) is None
+    assert bench.measured_traffic(W.LARGE_120.points, 4, 2) is None
+    assert bench.measured_traffic(W.LARGE_120.points + 1, 2, 2) is None
     t["kernel_source_sha256_16"] = "0" * 16
     out.write_text(json.dumps(t))
-    assert bench.measured_traffic(W.LARGE_120.points, 2) is None
+    assert bench.measured_traffic(W.LARGE_120.points, 2, 2) is None
 
 
 def test_summarize_traffic_refuses_mixed_configurations(tmp_path, monkeypatch):

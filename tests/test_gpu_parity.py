@@ -555,6 +555,94 @@ def test_short_runs_kernels_bitwise_and_solve(monkeypatch, precision, nth):
         check_f32_solve(V, ref, grid, "eno2")
 
 
+# (grid n, periodic y, plane run forced): whole planes and v-split planes
+# (each row's runs beyond half a block), ragged theta rows (odd N_theta),
+# runs of 3 (FP32), open and periodic y
+TWO_ROW_SHAPES = [
+    ((22, 20, 8, 36), False, None),
+    ((18, 12, 24, 72), False, None),
+    ((20, 14, 10, 13), False, None),
+    ((16, 10, 12, 48), False, "3"),
+    ((14, 8, 24, 72), True, None),
+]
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("scheme", [("eno2", "rk2"), ("upwind1", "euler")])
+@pytest.mark.parametrize("shape", range(len(TWO_ROW_SHAPES)))
+def test_two_row_blocks_bitwise_equal(monkeypatch, precision, scheme, shape):
+    """Plane-kernel blocks that hold two neighbouring y rows (each thread
+    loads its outer y neighbours, the inner ones come from the other row
+    through LDS) give bitwise the one-row blocks' result: whole planes and
+    v-split planes, ragged theta rows, runs of 3, open and periodic y, ENO2
+    and first order, at several x-chunkings."""
+    from paper_2012_04011_amd import hj
+
+    n, per_y, run = TWO_ROW_SHAPES[shape]
+    if run == "3" and precision == "f64":
+        pytest.skip("runs of 3 are FP32 only")
+    grid = W.car_grid(*n)
+    if per_y:
+        grid["periodic_mask"] |= 2
+    dyn = W.car_dynamics(d_max=0.1)
+    sch = W.scheme(*scheme)
+    cyl = W.cylinders(5, 3)
+    V0 = oracle.target_cylinders(W.car_grid(*n), *cyl) if per_y else None
+    if run:
+        monkeypatch.setenv("HJ_PLANE_RUN", run)
+    outs = {}
+    for rows, chunks in [("1", "1"), ("2", "1"), ("2", "3"), ("1", "4"), ("2", "4")]:
+        monkeypatch.setenv("HJ_X_CHUNKS", chunks)
+        monkeypatch.setenv("HJ_PLANE_ROWS", rows)
+        with hj.Grid(grid, dyn, sch, precision) as g:
+            if per_y:  # cylinder targets need open x and y: the same distances as a 4D target
+                g.set_target(V0.astype(np.float32 if precision == "f32" else np.float64))
+            else:
+                g.set_target_cylinders(*cyl)
+            info = g.launch_info()
+            assert info["kernel"] == "plane"
+            assert info["plane_rows"] == int(rows), (rows, info)
+            if run:
+                assert info["theta_run"] == int(run)
+            for _ in range(5):
+                g.step()
+            outs[(rows, chunks)] = g.value()
+    ref = outs[("1", "1")]
+    assert np.isfinite(ref).all()
+    for k, v in outs.items():
+        assert np.array_equal(v, ref), k
+
+
+def test_two_row_blocks_solve_and_autotune(monkeypatch):
+    """A whole ENO2 + TVD-RK2 solve on two-row blocks (the paper's grid)
+    equals the one-row solve bitwise, and with HJ_PLANE_ROWS=2 the autotuner
+    times only two-row plane blocks (beside the streaming kernel)."""
+    from paper_2012_04011_amd import hj
+
+    wl = W.ENO_60_DIST
+    cyl = W.cylinders(3, wl.obstacles)
+    outs = {}
+    monkeypatch.setenv("HJ_X_CHUNKS", "6")
+    for rows in ("1", "2"):
+        monkeypatch.setenv("HJ_PLANE_ROWS", rows)
+        with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32") as g:
+            g.set_target_cylinders(*cyl)
+            g.solve_brt(0.5)
+            info = g.launch_info()
+            assert info["kernel"] == "plane" and info["plane_rows"] == int(rows)
+            outs[rows] = g.value()
+    assert np.array_equal(outs["1"], outs["2"])
+    monkeypatch.delenv("HJ_X_CHUNKS")
+    monkeypatch.setenv("HJ_PLANE_ROWS", "2")
+    with hj.Grid(wl.grid, wl.dyn, wl.scheme, "f32") as g:
+        g.set_target_cylinders(*cyl)
+        g.solve_brt(0.5)
+        info = g.launch_info()
+        assert info["autotuned"]
+        assert info["plane_rows"] == (2 if info["kernel"] == "plane" else 0)
+        assert np.array_equal(g.value(), outs["1"])
+
+
 def test_autotune_and_launch_info():
     from paper_2012_04011_amd import hj
 
