@@ -905,10 +905,12 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
       const int hv = hk < 2 ? va - 2 + hk : va + nvs + (hk - 2);
       hcopy = h < 4 * rpr && (perv || (hv >= 0 && hv < nv));
       const int hw = hv < 0 ? hv + nv : (hv >= nv ? hv - nv : hv);
-      hoff = (uint32_t)((y * nv + (hcopy ? hw : 0)) * nth + ht * R) * E;
+      // every lane issues the load, so that each plane issues a fixed set of
+      // loads; the lanes that copy nothing load at the end of the buffer
+      // (lane offset total), out of range: 0 without a memory access (their
+      // H is never used)
+      hoff = hcopy ? (uint32_t)((y * nv + hw) * nth + ht * R) * E : total;
       hl = (hv - vbase) * rowl + ht * SL;
-      // every lane loads (the others a run of row v = 0 of their own y, in
-      // bounds), so that each plane issues a fixed set of loads
       bload<T, R>(rs, hoff, (uint32_t)x0 * pb, H);
     }
 
