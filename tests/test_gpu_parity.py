@@ -564,6 +564,8 @@ TWO_ROW_SHAPES = [
     ((20, 14, 10, 13), False, None),
     ((16, 10, 12, 48), False, "3"),
     ((14, 8, 24, 72), True, None),
+    ((5, 6, 8, 36), False, None),  # x chunks of 1 and 2 planes
+    ((9, 4, 8, 36), False, None),  # two row pairs, every row at a y end
 ]
 
 
