@@ -678,7 +678,10 @@ hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mod
                            bool last = false) {
   bool ball = G->ball_mask != 0;
   if (G->kernel > 0) {
-    hj::StreamArgs<T> a = stream_args<T>(G);
+    // the stage that folds eps (convergence mode) takes one-row plane blocks:
+    // the runtime stage form spills registers in blocks of two rows
+    const bool fold = last && G->kernel == 2 && G->eps_acc;
+    hj::StreamArgs<T> a = fold ? stream_args<T>(G, true, 0, 1) : stream_args<T>(G);
     a.vs = vs;
     a.vn = vn;
     a.v0 = buf<const T>(G->v0);
@@ -686,7 +689,7 @@ hj_status launch_one_stage(hj_grid *G, const T *vs, const T *vn, T *out, int mod
     a.mode = mode;
     a.clamp = clamp;
     a.dt = (T)dt;
-    if (last && G->kernel == 2) a.eps = G->eps_acc;
+    if (fold) a.eps = G->eps_acc;
     if (G->kernel == 2)
       HJ_HIP(hj::launch_plane(a, G->sch.deriv, ball, S(G)));
     else
