@@ -718,8 +718,9 @@ __device__ inline unsigned long long order_key(double x) {
 
 // Stage forms the plane kernel compiles in (see FORM below): Euler or TVD-RK2
 // stage 1 without a clamp, the last stage of an Euler step with the clamp
-// value from the Nx x Ny table, TVD-RK2 stage 2 (the average) with it.
-enum PlaneForm { kFormRuntime = 0, kFormPlain = 1, kFormPlainXY = 2, kFormAverageXY = 3 };
+// value from the Nx x Ny table, TVD-RK2 stage 2 (the average) with it, and
+// that stage folding eps = max |V^n+1 - V^n| (convergence mode; a.eps set).
+enum PlaneForm { kFormRuntime = 0, kFormPlain = 1, kFormPlainXY = 2, kFormAverageXY = 3, kFormAverageXYEps = 4 };
 
 // SEG: the block holds one v segment [va, va + v_seg) of the plane plus two
 // halo rows on each side (copied from global memory by the first 4 * rpr
@@ -830,10 +831,10 @@ __device__ __forceinline__ void plane_block(const StreamArgs<T> &a, const int lb
   const bool ball_v = (a.ball_mask & 4u) != 0, ball_t = (a.ball_mask & 8u) != 0;
   // the stage's form: compile-time constants unless FORM is kFormRuntime
   constexpr bool kRT = FORM == kFormRuntime;
-  const bool avg = kRT ? a.mode == kAverage : FORM == kFormAverageXY;
+  const bool avg = kRT ? a.mode == kAverage : (FORM == kFormAverageXY || FORM == kFormAverageXYEps);
   const bool clamp = kRT ? a.clamp != 0 : FORM != kFormPlain;
   const bool xy = kRT ? a.v0xy != nullptr : true;  // clamp value from the Nx x Ny table
-  const bool fold_eps = kRT && a.eps != nullptr;
+  const bool fold_eps = kRT ? a.eps != nullptr : FORM == kFormAverageXYEps;
 
   const uint32_t pb = (uint32_t)a.plane * E;
   const uint32_t total = pb * (uint32_t)nx;
@@ -1404,8 +1405,9 @@ hipError_t launch_stream_d(const StreamArgs<T> &a, bool ball, hipStream_t s) {
 
 template <typename T, int R, int DERIV, bool SG, bool BALL, bool SEG, bool RANGE, bool ROWS2 = false>
 void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, size_t lds, hipStream_t s) {
-  // the compiled-in forms (not for the ball test dynamics); the eps fold and
-  // the 4D clamp target take the runtime form
+  // the compiled-in forms (not for the ball test dynamics); the 4D clamp
+  // target, and the eps fold other than in TVD-RK2 stage 2 of one-row
+  // blocks, take the runtime form
   int form = kFormRuntime;
   if (RANGE)
     form = kFormPlain;
@@ -1416,6 +1418,8 @@ void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, siz
       form = kFormPlainXY;
     else if (a.mode == kAverage && a.clamp && a.v0xy)
       form = kFormAverageXY;
+  } else if (!BALL && !ROWS2 && a.mode == kAverage && a.clamp && a.v0xy) {
+    form = kFormAverageXYEps;  // a.eps set
   }
   if (form == kFormPlain)
     hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, RANGE, kFormPlain, ROWS2>), dim3(blocks),
@@ -1426,6 +1430,9 @@ void launch_plane_form(const StreamArgs<T> &a, unsigned blocks, int threads, siz
                          dim3(threads), lds, s, a);
     else if (form == kFormAverageXY)
       hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormAverageXY, ROWS2>), dim3(blocks),
+                         dim3(threads), lds, s, a);
+    else if (form == kFormAverageXYEps && !ROWS2)
+      hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormAverageXYEps, false>), dim3(blocks),
                          dim3(threads), lds, s, a);
     else
       hipLaunchKernelGGL((stage_plane<T, R, DERIV, SG, BALL, SEG, false, kFormRuntime, ROWS2>), dim3(blocks),
