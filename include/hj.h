@@ -308,7 +308,8 @@ typedef struct {
 hj_status hj_get_launch_info(hj_grid *g, hj_launch_info *out);
 
 /* Time the candidate launch configurations (stage kernel that fits the
- * shape, x-chunk counts 1..8, 10, 12, 16) on the handle's current buffers, time the three
+ * shape, the plane kernel's theta runs and one- or two-row blocks, x-chunk
+ * counts 1..8, 10, 12, 16) on the handle's current buffers, time the three
  * fastest again in three alternating rounds and keep the fastest of those; a
  * few tens of milliseconds, synchronises.  The result of a solve does
  * not depend on the choice (every candidate evaluates each node with the
